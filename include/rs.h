@@ -1,0 +1,138 @@
+/*
+ * rs.h -- C ABI of the MI355X (gfx950) novel-polynomial-basis Reed-Solomon
+ * erasure codec: the transform Psi_h^l and its inverse, the formal
+ * derivative, and the (n, k) encoder and erasure decoder built on them
+ * (Lin, Chung, Han, "Novel Polynomial Basis and Its Application to
+ * Reed-Solomon Erasure Codes", arXiv:1404.3458).
+ *
+ * Library: librs_nb.so (HIP, hand-written gfx950 kernels).  No torch or HIP
+ * type appears in these signatures: device buffers are plain pointers and a
+ * stream is an opaque hipStream_t passed as void* (NULL = the null stream).
+ *
+ * Conventions fixed by this library where the paper leaves a choice:
+ *   - field GF(2^r), r in {8, 16}; field polynomial 0x11D (r = 8) or 0x1100B
+ *     (r = 16); primitive element alpha = 2 (it only enters the locator's
+ *     logarithms and never changes an output);
+ *   - symbols: r = 8 -> one byte; r = 16 -> a little-endian 16-bit word.  Bit
+ *     b of a symbol is the coefficient of x^b.  Row t of a buffer starts at
+ *     byte t * row_bytes; symbol c of a row is at byte c * (r / 8);
+ *   - points: omega_i = sum_j i_j v_j over the basis v (Sec. 2.1);
+ *   - codeword rows: message row i is the point omega_i (eq. F(i)=m_i);
+ *     parity row t is the point omega_{k'+t} where k' = pow2ceil(k);
+ *   - shortening (Sec. 5 allows any k through zero padding): the mother code
+ *     is (n', k') with n' = pow2ceil(k' + n - k) <= 2^r; points
+ *     omega_k..omega_{k'-1} carry virtual zero symbols and points
+ *     omega_{k'+n-k}..omega_{n'-1} are never stored;
+ *   - nb_fft output b is [D](omega_b + omega_l) for any shift l < 2^r (the
+ *     definition of Psi_h^l in Sec. 3); these are consecutive points only
+ *     when h divides l.
+ *
+ * Ownership and ordering: data pointers are device memory owned by the
+ * caller and must stay valid until the stream reaches the call.  Host arrays
+ * (erasure masks, descriptors) are copied before the call returns.  Work is
+ * stream-ordered; calls that share a context but run on different streams
+ * use separate per-stream scratch.  Argument errors are returned before any
+ * work is queued, with no partial writes.  Device faults surface as
+ * RS_EDEVICE from the next call or from rs_sync().
+ */
+#ifndef RS_NB_H
+#define RS_NB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rs_ctx rs_ctx;
+
+enum {
+    RS_OK = 0,
+    RS_EINVAL = -1,    /* null pointer or invalid argument */
+    RS_EFIELD = -2,    /* r not in {8, 16} */
+    RS_EBASIS = -3,    /* basis not F2-independent or out of range */
+    RS_ESHAPE = -4,    /* h or (n, k) not supported: see each call */
+    RS_ETOOMANY = -5,  /* more than n - k erasures */
+    RS_EALIGN = -6,    /* row length not a multiple of the symbol size */
+    RS_ENOMEM = -7,    /* device or pinned host allocation failed */
+    RS_EDEVICE = -8    /* a HIP call or kernel failed */
+};
+
+/* Create a context on the current HIP device (Sec. 2.1, 2.2, 3.5, 4.2 and
+ * the appendix).  basis: r field elements v_0..v_{r-1}, F2-independent, each
+ * < 2^r; NULL selects v_j = 2^j (omega_i = i).  Builds, on the device, the
+ * skew-factor table W_i(omega_{b 2^{i+1}}) / W_i(omega_{2^i}) for every level
+ * i < r (2^r - 1 factors, Sec. 3.5), the derivative table B of eq. B and its
+ * inverses, the log/exp tables and the Walsh-Hadamard transforms of the
+ * logarithm vector L_N for every N = 2^t <= 2^r (appendix).  The context owns
+ * only these tables and per-stream scratch; free it with rs_free. */
+int rs_init(int r, const uint32_t *basis, rs_ctx **out);
+void rs_free(rs_ctx *ctx);
+
+/* Algorithm 1.  msg: k rows, parity: n - k rows, each row_bytes long,
+ * row-major and contiguous, device memory, not overlapping.  Writes the n - k
+ * parity rows of the systematic codeword (message rows are the codeword's
+ * first k rows and are not copied).  1 <= k < n, n' <= 2^r (RS_ESHAPE);
+ * row_bytes a multiple of r/8 (RS_EALIGN); row_bytes == 0 is a no-op. */
+int rs_encode(rs_ctx *ctx, int n, int k, const void *msg, void *parity,
+              size_t row_bytes, void *stream);
+
+/* Algorithm 2.  shards: n rows (device); erasure_mask: n host bytes, nonzero
+ * = erased (the erased rows of shards are never read).  On return every row
+ * of out (n rows, device) holds the codeword: erased rows recovered,
+ * surviving rows copied unless out == shards (in place).  Any number of
+ * erasures e <= n - k is accepted (RS_ETOOMANY otherwise); e == 0 copies. */
+int rs_decode(rs_ctx *ctx, int n, int k, const uint8_t *erasure_mask,
+              const void *shards, void *out, size_t row_bytes, void *stream);
+
+/* Transform Psi_h^l (Sec. 3.2) and its inverse (Sec. 3.3), in place on h
+ * rows of `data` (device); each column of symbols is one coefficient vector
+ * (nb_fft input) or one evaluation vector (nb_ifft input).  h a power of two,
+ * 1 <= h <= 2^r; l < 2^r. */
+int nb_fft(rs_ctx *ctx, int h, uint32_t l, void *data, size_t row_bytes, void *stream);
+int nb_ifft(rs_ctx *ctx, int h, uint32_t l, void *data, size_t row_bytes, void *stream);
+
+/* Formal derivative (Sec. 4.2): replaces each column's coefficients of
+ * [D_h](x) by those of [D_h]'(x), in place; h as for nb_fft. */
+int nb_derivative(rs_ctx *ctx, int h, void *data, size_t row_bytes, void *stream);
+
+/* One stripe of a batch.  Encode: in = k message rows, out = n - k parity
+ * rows.  Decode: in = n shard rows, out = n rows (may equal in). */
+typedef struct rs_stripe_desc {
+    int32_t n, k;
+    uint64_t row_bytes;
+    const void *in;
+    void *out;
+} rs_stripe_desc;
+
+/* Batched Algorithm 1 / Algorithm 2 over `count` independent stripes of
+ * possibly different (n, k) and row lengths, queued as a few launches.
+ * masks: for decode, the stripes' erasure masks concatenated in descriptor
+ * order (sum of n bytes, host).  Every descriptor is validated as for the
+ * single-stripe call before any work is queued. */
+int rs_encode_batch(rs_ctx *ctx, const rs_stripe_desc *descs, int count, void *stream);
+int rs_decode_batch(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks,
+                    int count, void *stream);
+
+/* Wait for all work of this context on `stream`; reports deferred device
+ * errors. */
+int rs_sync(rs_ctx *ctx, void *stream);
+
+/* Copy one of the context's raw tables to host memory (inspection and
+ * tests).  which: RS_TAB_SKEW (2^r - 1 factors, level i at offset
+ * 2^r - 2^{r-i}, entry b = W_i(omega_{b 2^{i+1}}) / W_i(omega_{2^i})),
+ * RS_TAB_B and RS_TAB_BINV (2^r entries: B_j of eq. B and its inverse),
+ * RS_TAB_LOG and RS_TAB_EXP (2^r entries each, Log(0) = 0).  count must be
+ * at least the table length; returns the length or a negative error. */
+enum { RS_TAB_SKEW = 0, RS_TAB_B = 1, RS_TAB_BINV = 2, RS_TAB_LOG = 3, RS_TAB_EXP = 4 };
+int rs_get_table(rs_ctx *ctx, int which, uint32_t *host_out, size_t count);
+
+/* Static description of an error code. */
+const char *rs_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RS_NB_H */

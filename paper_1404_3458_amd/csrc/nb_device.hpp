@@ -1,0 +1,304 @@
+// nb_device.hpp -- device primitives for the gfx950 codec kernels.
+//
+// Data layout in registers ("byte-sliced"): a lane owns 4 adjacent columns of
+// a row.  For r = 16 the 4 symbols are held as two dwords, L = their four low
+// bytes and H = their four high bytes; for r = 8 one dword holds the four
+// byte symbols.  Field addition is XOR on these words.
+//
+// Multiplication by a constant s that every column of a row shares (the skew
+// factors of Sec. 3.2, the B table of Sec. 4.2, the locator values of the
+// appendix) uses v_perm_b32 as an 8-entry byte lookup: each byte of a symbol
+// is split into bit groups of 3, 3 and 2 bits, and s * (group << offset) is
+// looked up per group and per output byte, then XOR-ed (the product is
+// GF(2)-linear in the multiplicand).  A constant's lookup tables ("perm
+// table") take 20 dwords for r = 16 and 5 (stored as 8) for r = 8:
+//
+//   r = 16, input byte b in {L = 0, H = 1}, base = 10 b:
+//     group 0 (bits 0-2): [base+0] L-out entries 0-3, [base+1] L-out 4-7,
+//                         [base+2] H-out entries 0-3, [base+3] H-out 4-7
+//     group 1 (bits 3-5): [base+4 .. base+7] likewise
+//     group 2 (bits 6-7): [base+8] L-out entries 0-3, [base+9] H-out 0-3
+//   r = 8: [0..1] group 0, [2..3] group 1, [4] group 2
+//
+// Entry e of a table occupies byte (e mod 4) of dword (e / 4), which is the
+// byte v_perm_b32 returns for selector value e when the dword pair is passed
+// as (hi = entries 4-7, lo = entries 0-3).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nb {
+
+constexpr int TAB16 = 20;   // dwords per perm table, r = 16
+constexpr int TAB8 = 8;     // dwords per perm table, r = 8 (5 used)
+
+template <int R> struct Traits;
+template <> struct Traits<16> { static constexpr int NW = 2, TS = TAB16, SYM = 2; };
+template <> struct Traits<8> { static constexpr int NW = 1, TS = TAB8, SYM = 1; };
+
+__host__ __device__ inline uint32_t field_poly(int r) { return r == 8 ? 0x11Du : 0x1100Bu; }
+
+// a * x in GF(2^r)
+__host__ __device__ inline uint32_t gf_times_x(uint32_t a, int r)
+{
+    a <<= 1;
+    return ((a >> r) & 1u) ? (a ^ field_poly(r)) : a;
+}
+
+// General product, right-to-left over the bits of b with the multiplicand
+// doubled (and reduced) at each step.  Used only by table builders.
+__host__ __device__ inline uint32_t gf_mul(uint32_t a, uint32_t b, int r)
+{
+    uint32_t acc = 0;
+    while (b) {
+        if (b & 1u)
+            acc ^= a;
+        a = gf_times_x(a, r);
+        b >>= 1;
+    }
+    return acc;
+}
+
+__host__ __device__ inline uint32_t gf_pow(uint32_t a, uint32_t e, int r)
+{
+    uint32_t acc = 1;
+    while (e) {
+        if (e & 1u)
+            acc = gf_mul(acc, a, r);
+        a = gf_mul(a, a, r);
+        e >>= 1;
+    }
+    return acc;
+}
+
+// Inverse through Fermat: a^(2^r - 2).
+__host__ __device__ inline uint32_t gf_inv(uint32_t a, int r)
+{
+    return gf_pow(a, (1u << r) - 2u, r);
+}
+
+// Build the perm table of constant s (layout in the file comment).
+__device__ inline void build_perm_table(uint32_t s, int r, uint32_t *out)
+{
+    uint32_t px[16];                 // s * x^t
+    px[0] = s;
+    for (int t = 1; t < r; t++)
+        px[t] = gf_times_x(px[t - 1], r);
+    const int nbytes = r / 8;
+    for (int b = 0; b < nbytes; b++) {
+        for (int g = 0; g < 3; g++) {
+            const int nbits = g == 2 ? 2 : 3;
+            const int shift = 8 * b + 3 * g;
+            uint32_t lo_out[2] = {0, 0}, hi_out[2] = {0, 0};
+            for (int e = 0; e < (1 << nbits); e++) {
+                uint32_t prod = 0;
+                for (int u = 0; u < nbits; u++)
+                    if ((e >> u) & 1)
+                        prod ^= px[shift + u];
+                lo_out[e >> 2] |= (prod & 0xFFu) << (8 * (e & 3));
+                hi_out[e >> 2] |= ((prod >> 8) & 0xFFu) << (8 * (e & 3));
+            }
+            if (r == 16) {
+                uint32_t *o = out + 10 * b + 4 * g;
+                if (g < 2) {
+                    o[0] = lo_out[0]; o[1] = lo_out[1]; o[2] = hi_out[0]; o[3] = hi_out[1];
+                } else {
+                    o[0] = lo_out[0]; o[1] = hi_out[0];
+                }
+            } else {
+                uint32_t *o = out + 2 * g;
+                o[0] = lo_out[0];
+                if (g < 2)
+                    o[1] = lo_out[1];
+            }
+        }
+    }
+    if (r == 8) {
+        out[5] = out[6] = out[7] = 0;
+    }
+}
+
+// ---------------------------------------------------------------- hot ops
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+__device__ __forceinline__ uint32_t prm(uint32_t hi, uint32_t lo, uint32_t sel)
+{
+    return __builtin_amdgcn_perm(hi, lo, sel);
+}
+
+// a ^= s * b for 4 symbols, r = 16 (t: perm table of s).
+__device__ __forceinline__ void mac16(uint32_t &aL, uint32_t &aH, uint32_t bL, uint32_t bH,
+                                      const uint32_t *__restrict__ t)
+{
+    const uint32_t m3 = 0x07070707u, m2 = 0x03030303u;
+    const uint32_t s0 = bL & m3, s1 = (bL >> 3) & m3, s2 = (bL >> 6) & m2;
+    const uint32_t s3 = bH & m3, s4 = (bH >> 3) & m3, s5 = (bH >> 6) & m2;
+    aL = xor3(aL, prm(t[1], t[0], s0), prm(t[5], t[4], s1));
+    aH = xor3(aH, prm(t[3], t[2], s0), prm(t[7], t[6], s1));
+    aL = xor3(aL, prm(t[8], t[8], s2), prm(t[11], t[10], s3));
+    aH = xor3(aH, prm(t[9], t[9], s2), prm(t[13], t[12], s3));
+    aL = xor3(aL, prm(t[15], t[14], s4), prm(t[18], t[18], s5));
+    aH = xor3(aH, prm(t[17], t[16], s4), prm(t[19], t[19], s5));
+}
+
+// a ^= s * b for 4 symbols, r = 8.
+__device__ __forceinline__ void mac8(uint32_t &a, uint32_t b, const uint32_t *__restrict__ t)
+{
+    const uint32_t m3 = 0x07070707u, m2 = 0x03030303u;
+    const uint32_t s0 = b & m3, s1 = (b >> 3) & m3, s2 = (b >> 6) & m2;
+    a = xor3(a, prm(t[1], t[0], s0), prm(t[3], t[2], s1));
+    a ^= prm(t[4], t[4], s2);
+}
+
+template <int R> struct Ops;
+
+template <> struct Ops<16> {
+    static constexpr int NW = 2;
+    __device__ static __forceinline__ void mac(uint32_t *a, const uint32_t *b, const uint32_t *t)
+    {
+        mac16(a[0], a[1], b[0], b[1], t);
+    }
+    // packed symbols (two little-endian u16 per dword) -> byte-sliced
+    __device__ static __forceinline__ void unpack(uint32_t w0, uint32_t w1, uint32_t *v)
+    {
+        v[0] = prm(w1, w0, 0x06040200u);
+        v[1] = prm(w1, w0, 0x07050301u);
+    }
+    __device__ static __forceinline__ void pack(const uint32_t *v, uint32_t &w0, uint32_t &w1)
+    {
+        w0 = prm(v[1], v[0], 0x05010400u);
+        w1 = prm(v[1], v[0], 0x07030602u);
+    }
+};
+
+template <> struct Ops<8> {
+    static constexpr int NW = 1;
+    __device__ static __forceinline__ void mac(uint32_t *a, const uint32_t *b, const uint32_t *t)
+    {
+        mac8(a[0], b[0], t);
+    }
+};
+
+// Global-address-space views of row pointers: loads and stores then use an
+// SGPR row base plus a 32-bit VGPR lane offset (and immediate offsets)
+// instead of 64-bit flat addresses.
+typedef __attribute__((address_space(1))) uint8_t gu8;
+typedef __attribute__((address_space(1))) uint16_t gu16;
+typedef __attribute__((address_space(1))) uint32_t gu32;
+typedef __attribute__((address_space(1))) uint64_t gu64;
+
+// How a lane reaches its 4 symbols of a row:
+//   LD_VEC  one 8-byte (r = 16) or 4-byte (r = 8) access; rows are aligned
+//           and only full chunks are touched;
+//   LD_SYM  one access per symbol (only symbol alignment is required), with
+//           a bound nsym on the symbols that exist (the last partial chunk).
+enum { LD_VEC = 0, LD_SYM = 1 };
+
+// Uniform value the compiler must treat as freshly computed, so that row
+// pointers derived from it are rebuilt where used instead of being kept
+// live in scalar registers from one phase of a kernel to the next.
+__device__ __forceinline__ uint32_t fresh(uint32_t v)
+{
+    v = __builtin_amdgcn_readfirstlane(v);
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
+// Load this lane's chunk (byte offset `off` in the row) into byte-sliced
+// registers; inactive lanes and symbols >= nsym read zero.
+template <int R, int LD>
+__device__ __forceinline__ void load_chunk(const uint8_t *row_, uint32_t off, bool act, int nsym, uint32_t *v)
+{
+    const gu8 *row = (const gu8 *)row_ + off;
+    if (R == 16) {
+        uint32_t w0 = 0, w1 = 0;
+        if (act) {
+            if (LD == LD_VEC) {
+                const uint64_t t = *(const gu64 *)row;
+                w0 = (uint32_t)t;
+                w1 = (uint32_t)(t >> 32);
+            } else {
+                const gu16 *r16 = (const gu16 *)row;
+                const uint32_t s0 = r16[0];
+                const uint32_t s1 = nsym > 1 ? (uint32_t)r16[1] : 0u;
+                const uint32_t s2 = nsym > 2 ? (uint32_t)r16[2] : 0u;
+                const uint32_t s3 = nsym > 3 ? (uint32_t)r16[3] : 0u;
+                w0 = s0 | (s1 << 16);
+                w1 = s2 | (s3 << 16);
+            }
+        }
+        Ops<16>::unpack(w0, w1, v);
+    } else {
+        uint32_t w = 0;
+        if (act) {
+            if (LD == LD_VEC) {
+                w = *(const gu32 *)row;
+            } else {
+                w = row[0];
+                if (nsym > 1) w |= (uint32_t)row[1] << 8;
+                if (nsym > 2) w |= (uint32_t)row[2] << 16;
+                if (nsym > 3) w |= (uint32_t)row[3] << 24;
+            }
+        }
+        v[0] = w;
+    }
+}
+
+template <int R, int LD>
+__device__ __forceinline__ void store_chunk(uint8_t *row_, uint32_t off, bool act, int nsym, const uint32_t *v)
+{
+    if (!act)
+        return;
+    gu8 *row = (gu8 *)row_ + off;
+    if (R == 16) {
+        uint32_t w0, w1;
+        Ops<16>::pack(v, w0, w1);
+        if (LD == LD_VEC) {
+            *(gu64 *)row = (uint64_t)w0 | ((uint64_t)w1 << 32);
+        } else {
+            gu16 *r16 = (gu16 *)row;
+            r16[0] = (uint16_t)w0;
+            if (nsym > 1) r16[1] = (uint16_t)(w0 >> 16);
+            if (nsym > 2) r16[2] = (uint16_t)w1;
+            if (nsym > 3) r16[3] = (uint16_t)(w1 >> 16);
+        }
+    } else {
+        if (LD == LD_VEC) {
+            *(gu32 *)row = v[0];
+        } else {
+            row[0] = (uint8_t)v[0];
+            if (nsym > 1) row[1] = (uint8_t)(v[0] >> 8);
+            if (nsym > 2) row[2] = (uint8_t)(v[0] >> 16);
+            if (nsym > 3) row[3] = (uint8_t)(v[0] >> 24);
+        }
+    }
+}
+
+// Per-lane view of a tile: byte offset of the lane's chunk, whether the lane
+// holds real columns, and how many of its 4 symbols exist.
+struct Lane {
+    uint32_t off;
+    bool act;
+    int nsym;
+};
+
+// Chunk q of a launch covers columns col0 + 4q .. col0 + 4q + 3.  LD_VEC
+// launches only touch chunks that lie entirely below ncols; LD_SYM launches
+// also serve the last partial chunk.
+template <int R, int LD>
+__device__ __forceinline__ Lane lane_of(int tile_rel, int lane, int col0, int ncols)
+{
+    Lane ln;
+    constexpr uint32_t SB = R / 8;
+    const int c = col0 + 4 * (tile_rel * 64 + lane);
+    ln.off = (uint32_t)c * SB;
+    ln.nsym = ncols - c < 4 ? ncols - c : 4;
+    ln.act = LD == LD_VEC ? ln.nsym == 4 : ln.nsym > 0;
+    return ln;
+}
+
+}  // namespace nb

@@ -1,0 +1,15 @@
+// nb_fused16.hip -- instantiation of the fused kernels for GF(2^16).
+#include "nb_fused_impl.hpp"
+
+namespace nb {
+
+hipError_t fused_prepare_16() { return fused_prepare_r<16>(); }
+
+hipError_t fused_launch_16(int mode, bool gen_l, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
+                          hipStream_t s)
+{
+    return ld == LD_VEC ? launch_ld<16, LD_VEC>(mode, gen_l, L, a, k, ntiles, s)
+                        : launch_ld<16, LD_SYM>(mode, gen_l, L, a, k, ntiles, s);
+}
+
+}  // namespace nb

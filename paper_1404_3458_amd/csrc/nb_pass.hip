@@ -1,0 +1,226 @@
+// nb_pass.hip -- multi-pass kernels for transform sizes h > 256 (up to 2^16).
+//
+// A pass applies up to four consecutive levels lo .. lo+T-1 of the transform
+// (Sec. 3.2 / 3.3) to every group of 2^T rows base + j 2^lo (base has no set
+// bit in lo .. lo+T-1), reading the rows from global memory into registers
+// and writing them back.  The group and the 256-column tile are uniform per
+// workgroup, so the skew factors are wave-uniform as in the fused kernels.
+// Rows may be multiplied by B_p before or after the levels (Sec. 4.2).
+#include "nb_xform.hpp"
+
+namespace nb {
+
+__device__ __forceinline__ uint32_t group_base(uint32_t g, int lo, int T)
+{
+    return (g & ((1u << lo) - 1u)) | ((g >> lo) << (lo + T));
+}
+
+__device__ __forceinline__ const uint8_t *prow(const uint8_t *base, uint32_t t, uint64_t rb)
+{
+    return base + (uint64_t)t * rb;
+}
+__device__ __forceinline__ uint8_t *prow(uint8_t *base, uint32_t t, uint64_t rb)
+{
+    return base + (uint64_t)t * rb;
+}
+
+template <int R, int T, bool INV, bool GEN_L, int LD>
+__global__ __launch_bounds__(64) void k_pass(PassArgs a, const uint32_t *__restrict__ p_tw,
+                                             const uint32_t *__restrict__ p_one, const uint32_t *__restrict__ p_B)
+{
+    constexpr int NW = Traits<R>::NW, TS = Traits<R>::TS, NR = 1 << T;
+    const Tabs tb = {p_tw, p_one, p_B, nullptr};
+    const uint32_t g = blockIdx.x / (uint32_t)a.nct;
+    const int ct = (int)(blockIdx.x % (uint32_t)a.nct);
+    const uint32_t base = group_base(g, a.lo, T);
+    const Lane ln = lane_of<R, LD>(ct, (int)threadIdx.x, a.col0, a.ncols);
+    const uint64_t rb = a.row_bytes;
+    uint32_t x[NR][NW];
+#pragma unroll
+    for (int j = 0; j < NR; j++) {
+        const uint32_t p = base + ((uint32_t)j << a.lo);
+        if ((int)p < a.src_rows)
+            load_chunk<R, LD>(prow(a.src, p, rb), ln.off, ln.act, ln.nsym, x[j]);
+        else
+            zero_vec<R>(x[j]);
+        if (a.pre_B)
+            scale<R>(x[j], p_B + (size_t)TS * p);
+    }
+    reg_levels<R, T, INV, GEN_L>(x, base, a.lo, a.l, tb);
+#pragma unroll
+    for (int j = 0; j < NR; j++) {
+        const uint32_t p = fresh(base + ((uint32_t)j << a.lo));
+        if (a.post_B)
+            scale<R>(x[j], p_B + (size_t)TS * p);
+        if ((int)p >= a.dst_lo && (int)p < a.dst_hi)
+            store_chunk<R, LD>(prow(a.dst, p - (uint32_t)a.dst_lo, rb), ln.off, ln.act, ln.nsym, x[j]);
+    }
+}
+
+template <int R, int T, int LD>
+__global__ __launch_bounds__(64) void k_dpart(DerivPassArgs a, const uint32_t *__restrict__ p_Binv)
+{
+    constexpr int NW = Traits<R>::NW, TS = Traits<R>::TS, NR = 1 << T;
+    const uint32_t g = blockIdx.x / (uint32_t)a.nct;
+    const int ct = (int)(blockIdx.x % (uint32_t)a.nct);
+    const uint32_t base = group_base(g, a.lo, T);
+    const Lane ln = lane_of<R, LD>(ct, (int)threadIdx.x, a.col0, a.ncols);
+    const uint64_t rb = a.row_bytes;
+    uint32_t y[NR][NW];
+#pragma unroll
+    for (int j = 0; j < NR; j++)
+        load_chunk<R, LD>(prow(a.y, base + ((uint32_t)j << a.lo), rb), ln.off, ln.act, ln.nsym, y[j]);
+#pragma unroll
+    for (int j = 0; j < NR; j++) {
+        const uint32_t p = fresh(base + ((uint32_t)j << a.lo));
+        uint32_t z[NW];
+        if (a.first)
+            zero_vec<R>(z);
+        else
+            load_chunk<R, LD>(prow(a.z, p, rb), ln.off, ln.act, ln.nsym, z);
+#pragma unroll
+        for (int lv = 0; lv < T; lv++)
+            if (!((j >> lv) & 1))
+#pragma unroll
+                for (int w = 0; w < NW; w++)
+                    z[w] ^= y[j + (1 << lv)][w];
+        if (a.last) {
+            scale<R>(z, p_Binv + (size_t)TS * p);
+            store_chunk<R, LD>(prow(a.out, p, rb), ln.off, ln.act, ln.nsym, z);
+        } else {
+            store_chunk<R, LD>(prow(a.z, p, rb), ln.off, ln.act, ln.nsym, z);
+        }
+    }
+}
+
+// Decode step 2 for the multi-pass decoder: A[p] = rx * Pi(omega_p) for
+// received points, 0 otherwise; surviving rows copied when out != in.
+template <int R, int LD>
+__global__ __launch_bounds__(64) void k_dec_gather(DecodeIOArgs a, const uint8_t *__restrict__ p_masks,
+                                                   const uint32_t *__restrict__ p_rowtabs)
+{
+    constexpr int NW = Traits<R>::NW, TS = Traits<R>::TS;
+    const int p = (int)(blockIdx.x / (uint32_t)a.nct);
+    const int ct = (int)(blockIdx.x % (uint32_t)a.nct);
+    const DevStripe &st = a.st;
+    const Lane ln = lane_of<R, LD>(ct, (int)threadIdx.x, st.col0, st.ncols);
+    const uint8_t *__restrict__ mask = p_masks + st.mask_off;
+    const uint32_t *__restrict__ rowtab = p_rowtabs + st.rowtab_off;
+    uint32_t v[NW];
+    zero_vec<R>(v);
+    const int t = point_row(p, st);
+    if (t >= 0 && !mask[t]) {
+        uint32_t raw[NW];
+        load_chunk<R, LD>(prow(st.in, t, st.row_bytes), ln.off, ln.act, ln.nsym, raw);
+        if (st.copy_survivors)
+            store_chunk<R, LD>(prow(st.out, t, st.row_bytes), ln.off, ln.act, ln.nsym, raw);
+        Ops<R>::mac(v, raw, rowtab + (size_t)TS * p);
+    }
+    store_chunk<R, LD>(prow(a.A, p, st.row_bytes), ln.off, ln.act, ln.nsym, v);
+}
+
+// Decode step 6 for the multi-pass decoder: erased stored row t of point p
+// gets A[p] / Pi'(omega_p).
+template <int R, int LD>
+__global__ __launch_bounds__(64) void k_dec_scatter(DecodeIOArgs a, const uint8_t *__restrict__ p_masks,
+                                                    const uint32_t *__restrict__ p_rowtabs)
+{
+    constexpr int NW = Traits<R>::NW, TS = Traits<R>::TS;
+    const int t = (int)(blockIdx.x / (uint32_t)a.nct);
+    const int ct = (int)(blockIdx.x % (uint32_t)a.nct);
+    const DevStripe &st = a.st;
+    const uint8_t *__restrict__ mask = p_masks + st.mask_off;
+    const uint32_t *__restrict__ rowtab = p_rowtabs + st.rowtab_off;
+    if (!mask[t])
+        return;
+    const Lane ln = lane_of<R, LD>(ct, (int)threadIdx.x, st.col0, st.ncols);
+    const int p = t < st.k ? t : st.kp + (t - st.k);
+    uint32_t v[NW], o[NW];
+    load_chunk<R, LD>(prow(a.A, p, st.row_bytes), ln.off, ln.act, ln.nsym, v);
+    zero_vec<R>(o);
+    Ops<R>::mac(o, v, rowtab + (size_t)TS * p);
+    store_chunk<R, LD>(prow(st.out, t, st.row_bytes), ln.off, ln.act, ln.nsym, o);
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <int R, bool INV, bool GEN_L, int LD>
+static hipError_t pass_T(int T, const PassArgs &a, const KPtrs &k, uint32_t nblocks, hipStream_t s)
+{
+    switch (T) {
+    case 0: hipLaunchKernelGGL((k_pass<R, 0, INV, GEN_L, LD>), dim3(nblocks), dim3(64), 0, s, a, k.tw, k.one, k.B); break;
+    case 1: hipLaunchKernelGGL((k_pass<R, 1, INV, GEN_L, LD>), dim3(nblocks), dim3(64), 0, s, a, k.tw, k.one, k.B); break;
+    case 2: hipLaunchKernelGGL((k_pass<R, 2, INV, GEN_L, LD>), dim3(nblocks), dim3(64), 0, s, a, k.tw, k.one, k.B); break;
+    case 3: hipLaunchKernelGGL((k_pass<R, 3, INV, GEN_L, LD>), dim3(nblocks), dim3(64), 0, s, a, k.tw, k.one, k.B); break;
+    case 4: hipLaunchKernelGGL((k_pass<R, 4, INV, GEN_L, LD>), dim3(nblocks), dim3(64), 0, s, a, k.tw, k.one, k.B); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int R, int LD>
+static hipError_t pass_r(int T, bool inv, bool gen_l, const PassArgs &a, const KPtrs &k, uint32_t nblocks,
+                         hipStream_t s)
+{
+    if (inv)
+        return gen_l ? pass_T<R, true, true, LD>(T, a, k, nblocks, s) : pass_T<R, true, false, LD>(T, a, k, nblocks, s);
+    return gen_l ? pass_T<R, false, true, LD>(T, a, k, nblocks, s) : pass_T<R, false, false, LD>(T, a, k, nblocks, s);
+}
+
+hipError_t pass_launch(int r, int ld, int T, bool inv, bool gen_l, const PassArgs &a, const KPtrs &k,
+                       uint32_t nblocks, hipStream_t s)
+{
+    if (nblocks == 0)
+        return hipSuccess;
+    if (r == 16)
+        return ld == LD_VEC ? pass_r<16, LD_VEC>(T, inv, gen_l, a, k, nblocks, s)
+                            : pass_r<16, LD_SYM>(T, inv, gen_l, a, k, nblocks, s);
+    return ld == LD_VEC ? pass_r<8, LD_VEC>(T, inv, gen_l, a, k, nblocks, s)
+                        : pass_r<8, LD_SYM>(T, inv, gen_l, a, k, nblocks, s);
+}
+
+template <int R, int LD>
+static hipError_t dpart_T(int T, const DerivPassArgs &a, const KPtrs &k, uint32_t nblocks, hipStream_t s)
+{
+    switch (T) {
+    case 1: hipLaunchKernelGGL((k_dpart<R, 1, LD>), dim3(nblocks), dim3(64), 0, s, a, k.Binv); break;
+    case 2: hipLaunchKernelGGL((k_dpart<R, 2, LD>), dim3(nblocks), dim3(64), 0, s, a, k.Binv); break;
+    case 3: hipLaunchKernelGGL((k_dpart<R, 3, LD>), dim3(nblocks), dim3(64), 0, s, a, k.Binv); break;
+    case 4: hipLaunchKernelGGL((k_dpart<R, 4, LD>), dim3(nblocks), dim3(64), 0, s, a, k.Binv); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t dpart_launch(int r, int ld, int T, const DerivPassArgs &a, const KPtrs &k, uint32_t nblocks,
+                        hipStream_t s)
+{
+    if (nblocks == 0)
+        return hipSuccess;
+    if (r == 16)
+        return ld == LD_VEC ? dpart_T<16, LD_VEC>(T, a, k, nblocks, s) : dpart_T<16, LD_SYM>(T, a, k, nblocks, s);
+    return ld == LD_VEC ? dpart_T<8, LD_VEC>(T, a, k, nblocks, s) : dpart_T<8, LD_SYM>(T, a, k, nblocks, s);
+}
+
+template <int R, int LD>
+static void dec_io_r(bool scatter, const DecodeIOArgs &a, const KPtrs &k, uint32_t nblocks, hipStream_t s)
+{
+    if (scatter)
+        hipLaunchKernelGGL((k_dec_scatter<R, LD>), dim3(nblocks), dim3(64), 0, s, a, k.masks, k.rowtabs);
+    else
+        hipLaunchKernelGGL((k_dec_gather<R, LD>), dim3(nblocks), dim3(64), 0, s, a, k.masks, k.rowtabs);
+}
+
+hipError_t dec_io_launch(int r, int ld, bool scatter, const DecodeIOArgs &a, const KPtrs &k, uint32_t nblocks,
+                         hipStream_t s)
+{
+    if (nblocks == 0)
+        return hipSuccess;
+    if (r == 16)
+        ld == LD_VEC ? dec_io_r<16, LD_VEC>(scatter, a, k, nblocks, s) : dec_io_r<16, LD_SYM>(scatter, a, k, nblocks, s);
+    else
+        ld == LD_VEC ? dec_io_r<8, LD_VEC>(scatter, a, k, nblocks, s) : dec_io_r<8, LD_SYM>(scatter, a, k, nblocks, s);
+    return hipGetLastError();
+}
+
+}  // namespace nb

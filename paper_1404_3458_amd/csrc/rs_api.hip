@@ -1,0 +1,985 @@
+// rs_api.hip -- host side of librs_nb.so: context and tables, argument
+// validation, per-stream scratch, launch planning (fused kernels for
+// transform sizes <= 256, multi-pass kernels above), and the C ABI of
+// include/rs.h.
+#include "rs.h"
+#include "nb_device.hpp"
+#include "nb_internal.hpp"
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+namespace nb {
+hipError_t init_tables(int r, const uint32_t *d_basis, uint32_t *d_Wv, uint32_t *d_S, uint32_t *d_wp,
+                       uint32_t *d_skew, uint32_t *d_B, uint32_t *d_Binv, uint32_t *d_exp, uint32_t *d_log,
+                       uint32_t *d_FL, uint32_t *d_tw_tab, uint32_t *d_B_tab, uint32_t *d_Binv_tab,
+                       uint32_t *d_one_val, uint32_t *d_one_tab, hipStream_t s);
+hipError_t init_prepare(int r);
+hipError_t locator_launch(const LocatorArgs &a, const KPtrs &k, const uint32_t *fwht_L, const uint32_t *expt,
+                          int nstripes, int max_np, hipStream_t s);
+hipError_t fused_prepare_16();
+hipError_t fused_prepare_8();
+hipError_t fused_launch_16(int mode, bool gen_l, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
+                           hipStream_t s);
+hipError_t fused_launch_8(int mode, bool gen_l, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
+                          hipStream_t s);
+hipError_t pass_launch(int r, int ld, int T, bool inv, bool gen_l, const PassArgs &a, const KPtrs &k,
+                       uint32_t nblocks, hipStream_t s);
+hipError_t dpart_launch(int r, int ld, int T, const DerivPassArgs &a, const KPtrs &k, uint32_t nblocks,
+                        hipStream_t s);
+hipError_t dec_io_launch(int r, int ld, bool scatter, const DecodeIOArgs &a, const KPtrs &k, uint32_t nblocks,
+                         hipStream_t s);
+}  // namespace nb
+
+using namespace nb;
+
+namespace {
+
+enum { MODE_FFT = 0, MODE_IFFT = 1, MODE_DERIV = 2, MODE_ENC = 3, MODE_DEC = 4 };
+constexpr int FUSED_MAX_L = 8;      // fused single-launch kernels cover h <= 256
+constexpr int NSLOTS = 4;           // pinned staging slots per stream
+
+struct Slot {
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool recorded = false;
+};
+
+struct Scratch {
+    hipStream_t stream = nullptr;
+    void *dev = nullptr;             // descriptors, masks, locator tables
+    size_t dev_cap = 0;
+    void *big = nullptr;             // rows of the multi-pass pipelines
+    size_t big_cap = 0;
+    Slot slots[NSLOTS];
+    int next = 0;
+};
+
+int ilog2(long v)
+{
+    int t = 0;
+    while ((1L << t) < v)
+        t++;
+    return t;
+}
+
+bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
+long pow2ceil(long v)
+{
+    long p = 1;
+    while (p < v)
+        p <<= 1;
+    return p;
+}
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct rs_ctx {
+    int r = 0;
+    int device = 0;
+    uint32_t basis[16] = {};
+    void *d_mem = nullptr;
+    uint32_t *d_basis, *d_Wv, *d_S, *d_wp, *d_skew, *d_B, *d_Binv, *d_exp, *d_log, *d_FL;
+    uint32_t *d_tw_tab, *d_B_tab, *d_Binv_tab, *d_one_val, *d_one_tab;
+    KPtrs kp;           // method tables (masks / rowtabs filled per call)
+    std::mutex mu;
+    std::vector<Scratch *> scratch;
+    int sticky = RS_OK;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) {
+            ok = false;
+            return;
+        }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess)
+            ok = false;
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev)
+            (void)hipSetDevice(prev);
+    }
+};
+
+int dev_err(rs_ctx *ctx, hipError_t e)
+{
+    if (e == hipSuccess)
+        return RS_OK;
+    ctx->sticky = RS_EDEVICE;
+    return RS_EDEVICE;
+}
+
+Scratch *get_scratch(rs_ctx *ctx, hipStream_t s)
+{
+    for (Scratch *sc : ctx->scratch)
+        if (sc->stream == s)
+            return sc;
+    Scratch *sc = new (std::nothrow) Scratch();
+    if (!sc)
+        return nullptr;
+    sc->stream = s;
+    for (int i = 0; i < NSLOTS; i++) {
+        if (hipEventCreateWithFlags(&sc->slots[i].ev, hipEventDisableTiming) != hipSuccess) {
+            delete sc;
+            return nullptr;
+        }
+    }
+    ctx->scratch.push_back(sc);
+    return sc;
+}
+
+// Grow a device buffer; the stream's earlier work may still read the old one.
+int ensure_dev(Scratch *sc, void **buf, size_t *cap, size_t need)
+{
+    if (need <= *cap)
+        return RS_OK;
+    if (*buf) {
+        if (hipStreamSynchronize(sc->stream) != hipSuccess)
+            return RS_EDEVICE;
+        (void)hipFree(*buf);
+        *buf = nullptr;
+        *cap = 0;
+    }
+    size_t want = std::max(need, (size_t)1 << 20);
+    if (hipMalloc(buf, want) != hipSuccess) {
+        *buf = nullptr;
+        return RS_ENOMEM;
+    }
+    *cap = want;
+    return RS_OK;
+}
+
+// Copy `bytes` of host data to the device arena through a pinned slot whose
+// previous copy is known to have completed.
+int stage_upload(Scratch *sc, const void *src, size_t bytes, void *dst)
+{
+    if (!bytes)
+        return RS_OK;
+    Slot &sl = sc->slots[sc->next];
+    sc->next = (sc->next + 1) % NSLOTS;
+    if (sl.recorded && hipEventSynchronize(sl.ev) != hipSuccess)
+        return RS_EDEVICE;
+    if (sl.cap < bytes) {
+        if (sl.host)
+            (void)hipHostFree(sl.host);
+        sl.host = nullptr;
+        sl.cap = 0;
+        size_t want = std::max(bytes, (size_t)1 << 16);
+        if (hipHostMalloc(&sl.host, want, hipHostMallocDefault) != hipSuccess) {
+            sl.host = nullptr;
+            return RS_ENOMEM;
+        }
+        sl.cap = want;
+    }
+    std::memcpy(sl.host, src, bytes);
+    if (hipMemcpyAsync(dst, sl.host, bytes, hipMemcpyHostToDevice, sc->stream) != hipSuccess)
+        return RS_EDEVICE;
+    if (hipEventRecord(sl.ev, sc->stream) != hipSuccess)
+        return RS_EDEVICE;
+    sl.recorded = true;
+    return RS_OK;
+}
+
+int sym_bytes(const rs_ctx *ctx) { return ctx->r / 8; }
+
+bool vec_aligned(const rs_ctx *ctx, const void *a, const void *b, size_t rb)
+{
+    const size_t al = ctx->r == 16 ? 8 : 4;
+    return ((uintptr_t)a % al == 0) && ((uintptr_t)b % al == 0) && (rb % al == 0);
+}
+
+int mother_shape(const rs_ctx *ctx, int n, int k, int *kp, int *np)
+{
+    if (k < 1 || n <= k)
+        return RS_ESHAPE;
+    long k2 = pow2ceil(k), n2 = pow2ceil(k2 + (long)n - k);
+    if (n2 > (1L << ctx->r))
+        return RS_ESHAPE;
+    *kp = (int)k2;
+    *np = (int)n2;
+    return RS_OK;
+}
+
+// One stripe of a codec call after validation.
+struct Plan {
+    DevStripe ds;       // col0 / tile0 / offsets filled when launches are planned
+    int L;              // lg of the transform size (k' for encode, n' for decode)
+    int erasures;
+    bool aligned;       // rows and bases allow LD_VEC accesses
+    size_t mask_src;    // offset of the stripe's mask in the caller's mask array
+};
+
+// Column ranges of a stripe and the access variant each is launched with:
+// aligned rows use LD_VEC on the full 4-column chunks and LD_SYM on the last
+// partial chunk; unaligned rows use LD_SYM throughout.
+struct ColPart {
+    int ld;
+    int col0;
+    int ntiles;
+};
+
+int ntiles_of_chunks(long chunks) { return (int)((chunks + 63) / 64); }
+
+std::vector<ColPart> col_parts(bool aligned, int ncols)
+{
+    std::vector<ColPart> v;
+    if (ncols <= 0)
+        return v;
+    if (!aligned) {
+        v.push_back({LD_SYM, 0, ntiles_of_chunks((ncols + 3) / 4)});
+        return v;
+    }
+    const int full = ncols / 4;
+    if (full)
+        v.push_back({LD_VEC, 0, ntiles_of_chunks(full)});
+    if (ncols % 4)
+        v.push_back({LD_SYM, 4 * full, 1});
+    return v;
+}
+
+int validate_stripe(rs_ctx *ctx, const rs_stripe_desc &d, bool decode, const uint8_t *mask, Plan &pl)
+{
+    const int sym = sym_bytes(ctx);
+    int kp, np;
+    int rc = mother_shape(ctx, d.n, d.k, &kp, &np);
+    if (rc)
+        return rc;
+    if (d.row_bytes % (uint64_t)sym)
+        return RS_EALIGN;
+    if (d.row_bytes && (!d.in || !d.out))
+        return RS_EINVAL;
+    if (d.row_bytes / sym > (uint64_t)INT32_MAX / 2)
+        return RS_ESHAPE;
+    std::memset(&pl.ds, 0, sizeof(pl.ds));
+    pl.ds.in = (const uint8_t *)d.in;
+    pl.ds.out = (uint8_t *)d.out;
+    pl.ds.row_bytes = d.row_bytes;
+    pl.ds.n = d.n;
+    pl.ds.k = d.k;
+    pl.ds.kp = kp;
+    pl.ds.np = np;
+    pl.ds.ncols = (int32_t)(d.row_bytes / sym);
+    pl.ds.copy_survivors = decode && d.in != d.out ? 1 : 0;
+    pl.aligned = vec_aligned(ctx, d.in, d.out, d.row_bytes);
+    pl.L = ilog2(decode ? np : kp);
+    pl.erasures = 0;
+    if (decode) {
+        if (!mask)
+            return RS_EINVAL;
+        int e = 0;
+        for (int t = 0; t < d.n; t++)
+            e += mask[t] ? 1 : 0;
+        if (e > d.n - d.k)
+            return RS_ETOOMANY;
+        pl.erasures = e;
+    }
+    return RS_OK;
+}
+
+// ------------------------------------------------------------------ multi-pass pipelines
+
+// Apply levels [0, L) (inverse) or [L-1 .. 0] (forward) to h = 2^L rows with
+// passes of up to 4 levels.  The first pass reads `src` (src_rows rows, the
+// rest zero), every pass writes `work`, except that the last pass writes
+// rows [dst_lo, dst_hi) to `final_dst` when it is given.
+int run_passes(rs_ctx *ctx, hipStream_t s, bool inv, bool gen_l, int L, uint32_t l, const uint8_t *src,
+               int src_rows, uint8_t *work, uint8_t *final_dst, int dst_lo, int dst_hi, uint64_t rb,
+               int ncols, bool aligned, bool pre_B_first, bool post_B_last)
+{
+    std::vector<std::pair<int, int>> chunks;   // (lo, T)
+    if (inv) {
+        for (int lo = 0; lo < L; lo += 4)
+            chunks.push_back({lo, std::min(4, L - lo)});
+    } else {
+        int top = L;
+        while (top > 0) {
+            const int T = std::min(4, top);
+            chunks.push_back({top - T, T});
+            top -= T;
+        }
+    }
+    if (chunks.empty())
+        chunks.push_back({0, 0});
+    const int h = 1 << L;
+    const std::vector<ColPart> parts = col_parts(aligned, ncols);
+    for (size_t c = 0; c < chunks.size(); c++) {
+        const bool first = c == 0, last = c + 1 == chunks.size();
+        for (const ColPart &cp : parts) {
+            PassArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.src = first ? src : work;
+            a.src_rows = first ? src_rows : h;
+            if (last && final_dst) {
+                a.dst = final_dst;
+                a.dst_lo = dst_lo;
+                a.dst_hi = dst_hi;
+            } else {
+                a.dst = work;
+                a.dst_lo = 0;
+                a.dst_hi = h;
+            }
+            a.row_bytes = rb;
+            a.ncols = ncols;
+            a.lo = chunks[c].first;
+            a.col0 = cp.col0;
+            a.l = l;
+            a.pre_B = first && pre_B_first;
+            a.post_B = last && post_B_last;
+            a.nct = cp.ntiles;
+            const int T = chunks[c].second;
+            const uint32_t nblocks = (uint32_t)((h >> T) * cp.ntiles);
+            if (dev_err(ctx, pass_launch(ctx->r, cp.ld, T, inv, gen_l, a, ctx->kp, nblocks, s)))
+                return RS_EDEVICE;
+        }
+    }
+    return RS_OK;
+}
+
+// Multiply every one of h rows by B_p in place (a pass with no levels).
+int scale_rows_B(rs_ctx *ctx, hipStream_t s, uint8_t *d, int h, uint64_t rb, int ncols, bool aligned)
+{
+    for (const ColPart &cp : col_parts(aligned, ncols)) {
+        PassArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.src = d;
+        a.src_rows = h;
+        a.dst = d;
+        a.dst_hi = h;
+        a.row_bytes = rb;
+        a.ncols = ncols;
+        a.col0 = cp.col0;
+        a.post_B = 1;
+        a.nct = cp.ntiles;
+        if (dev_err(ctx, pass_launch(ctx->r, cp.ld, 0, false, false, a, ctx->kp, (uint32_t)(h * cp.ntiles), s)))
+            return RS_EDEVICE;
+    }
+    return RS_OK;
+}
+
+// Derivative of h = 2^L rows held in y (already multiplied by B): z gets the
+// partial sums level range by level range; the last range writes
+// (sum) / B_p into out.
+int run_deriv_passes(rs_ctx *ctx, hipStream_t s, int L, const uint8_t *y, uint8_t *z, uint8_t *out,
+                     uint64_t rb, int ncols, bool aligned)
+{
+    const int h = 1 << L;
+    for (int lo = 0; lo < L; lo += 4) {
+        const int T = std::min(4, L - lo);
+        for (const ColPart &cp : col_parts(aligned, ncols)) {
+            DerivPassArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.y = y;
+            a.z = z;
+            a.out = out;
+            a.row_bytes = rb;
+            a.ncols = ncols;
+            a.lo = lo;
+            a.nct = cp.ntiles;
+            a.col0 = cp.col0;
+            a.first = lo == 0;
+            a.last = lo + T >= L;
+            if (dev_err(ctx, dpart_launch(ctx->r, cp.ld, T, a, ctx->kp, (uint32_t)((h >> T) * cp.ntiles), s)))
+                return RS_EDEVICE;
+        }
+    }
+    return RS_OK;
+}
+
+// Zero one row (the derivative of a constant) with a no-level pass that
+// reads nothing, so that the call records no memset node.
+int fill_zero(rs_ctx *ctx, hipStream_t s, uint8_t *data, uint64_t rb)
+{
+    const int ncols = (int)(rb / sym_bytes(ctx));
+    for (const ColPart &cp : col_parts(vec_aligned(ctx, data, data, rb), ncols)) {
+        PassArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.src = data;
+        a.src_rows = 0;
+        a.dst = data;
+        a.dst_hi = 1;
+        a.row_bytes = rb;
+        a.ncols = ncols;
+        a.col0 = cp.col0;
+        a.nct = cp.ntiles;
+        if (dev_err(ctx, pass_launch(ctx->r, cp.ld, 0, false, false, a, ctx->kp, (uint32_t)cp.ntiles, s)))
+            return RS_EDEVICE;
+    }
+    return RS_OK;
+}
+
+int big_scratch(Scratch *sc, size_t need, uint8_t **p)
+{
+    int rc = ensure_dev(sc, &sc->big, &sc->big_cap, need);
+    *p = (uint8_t *)sc->big;
+    return rc;
+}
+
+int encode_large(rs_ctx *ctx, Scratch *sc, const Plan &pl)
+{
+    const DevStripe &ds = pl.ds;
+    const uint64_t rb = ds.row_bytes;
+    const int nblocks = ds.np / ds.kp;
+    uint8_t *A;
+    int rc = big_scratch(sc, (size_t)ds.kp * rb * (nblocks > 2 ? 2 : 1), &A);
+    if (rc)
+        return rc;
+    uint8_t *Bb = nblocks > 2 ? A + (size_t)ds.kp * rb : A;
+    // the scratch rows share the stripe's row length; they are aligned when the stripe is
+    rc = run_passes(ctx, sc->stream, true, false, pl.L, 0, ds.in, ds.k, A, nullptr, 0, 0, rb, ds.ncols,
+                    pl.aligned, false, false);
+    const int npar = ds.n - ds.k;
+    for (int blk = 1; !rc && blk < nblocks; blk++) {
+        const int first_par = (blk - 1) * ds.kp;
+        if (first_par >= npar)
+            break;
+        rc = run_passes(ctx, sc->stream, false, false, pl.L, (uint32_t)(blk * ds.kp), A, ds.kp, Bb,
+                        ds.out + (size_t)first_par * rb, 0, std::min(ds.kp, npar - first_par), rb, ds.ncols,
+                        pl.aligned, false, false);
+    }
+    return rc;
+}
+
+int decode_large(rs_ctx *ctx, Scratch *sc, const Plan &pl, const DevStripe &dsl, const KPtrs &kp)
+{
+    const DevStripe &ds = pl.ds;
+    const uint64_t rb = ds.row_bytes;
+    uint8_t *A;
+    int rc = big_scratch(sc, (size_t)ds.np * rb * 2, &A);
+    if (rc)
+        return rc;
+    uint8_t *Z = A + (size_t)ds.np * rb;
+    // step 2 (the locator has already run), step 3, step 4, step 5, step 6
+    for (const ColPart &cp : col_parts(pl.aligned, ds.ncols)) {
+        DecodeIOArgs io;
+        std::memset(&io, 0, sizeof(io));
+        io.st = dsl;
+        io.st.col0 = cp.col0;
+        io.A = A;
+        io.nct = cp.ntiles;
+        if (dev_err(ctx, dec_io_launch(ctx->r, cp.ld, false, io, kp, (uint32_t)(ds.np * cp.ntiles), sc->stream)))
+            return RS_EDEVICE;
+    }
+    rc = run_passes(ctx, sc->stream, true, false, pl.L, 0, A, ds.np, A, nullptr, 0, 0, rb, ds.ncols, pl.aligned,
+                    false, true);
+    if (!rc)
+        rc = run_deriv_passes(ctx, sc->stream, pl.L, A, Z, A, rb, ds.ncols, pl.aligned);
+    if (!rc)
+        rc = run_passes(ctx, sc->stream, false, false, pl.L, 0, A, ds.np, A, nullptr, 0, 0, rb, ds.ncols,
+                        pl.aligned, false, false);
+    for (const ColPart &cp : col_parts(pl.aligned, ds.ncols)) {
+        if (rc)
+            break;
+        DecodeIOArgs io;
+        std::memset(&io, 0, sizeof(io));
+        io.st = dsl;
+        io.st.col0 = cp.col0;
+        io.A = A;
+        io.nct = cp.ntiles;
+        if (dev_err(ctx, dec_io_launch(ctx->r, cp.ld, true, io, kp, (uint32_t)(ds.n * cp.ntiles), sc->stream)))
+            rc = RS_EDEVICE;
+    }
+    return rc;
+}
+
+hipError_t fused_launch(int r, int mode, bool gen_l, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
+                        hipStream_t s)
+{
+    return r == 16 ? fused_launch_16(mode, gen_l, ld, L, a, k, ntiles, s)
+                   : fused_launch_8(mode, gen_l, ld, L, a, k, ntiles, s);
+}
+
+// ------------------------------------------------------------------ codec driver
+
+// One launch unit: a column part of one stripe.
+struct Entry {
+    int plan;
+    ColPart cp;
+};
+
+int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, int count, bool decode,
+              hipStream_t stream)
+{
+    if (!ctx || (count > 0 && !descs) || count < 0)
+        return RS_EINVAL;
+    if (decode && count > 0 && !masks)
+        return RS_EINVAL;
+    std::vector<Plan> plans((size_t)count);
+    size_t mask_total = 0;
+    for (int i = 0; i < count; i++) {
+        const uint8_t *m = decode ? masks + mask_total : nullptr;
+        int rc = validate_stripe(ctx, descs[i], decode, m, plans[i]);
+        if (rc)
+            return rc;
+        plans[i].mask_src = mask_total;
+        if (decode)
+            mask_total += (size_t)descs[i].n;
+    }
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return RS_EDEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->sticky)
+        return ctx->sticky;
+    Scratch *sc = get_scratch(ctx, stream);
+    if (!sc)
+        return RS_ENOMEM;
+
+    // Active stripes: with columns and, for decode, at least one erasure.
+    std::vector<int> act;
+    for (int i = 0; i < count; i++) {
+        const Plan &p = plans[i];
+        if (p.ds.ncols == 0)
+            continue;
+        if (decode && p.erasures == 0) {
+            if (p.ds.copy_survivors &&
+                dev_err(ctx, hipMemcpyAsync(p.ds.out, p.ds.in, (size_t)p.ds.n * p.ds.row_bytes,
+                                            hipMemcpyDeviceToDevice, stream)))
+                return RS_EDEVICE;
+            continue;
+        }
+        act.push_back(i);
+    }
+    if (act.empty())
+        return RS_OK;
+    const int m = (int)act.size();
+    const int ts = ctx->r == 16 ? TAB16 : TAB8;
+
+    // Per-stripe device data: masks and locator tables (decode).
+    size_t mask_bytes = 0, rt_dwords = 0;
+    int max_np = 1;
+    for (int q = 0; q < m; q++) {
+        Plan &p = plans[act[q]];
+        if (decode) {
+            p.ds.mask_off = mask_bytes;
+            mask_bytes += (size_t)p.ds.n;
+            p.ds.rowtab_off = rt_dwords;
+            rt_dwords += (size_t)p.ds.np * ts;
+            max_np = std::max(max_np, p.ds.np);
+        }
+    }
+    // Launch entries for the fused path, grouped by (L, access variant).
+    std::vector<Entry> ents;
+    for (int q = 0; q < m; q++) {
+        const Plan &p = plans[act[q]];
+        if (p.L > FUSED_MAX_L)
+            continue;
+        for (const ColPart &cp : col_parts(p.aligned, p.ds.ncols))
+            ents.push_back({act[q], cp});
+    }
+    std::stable_sort(ents.begin(), ents.end(), [&](const Entry &a, const Entry &b) {
+        const int ka = plans[a.plan].L * 2 + a.cp.ld, kb = plans[b.plan].L * 2 + b.cp.ld;
+        return ka < kb;
+    });
+    const int ne = (int)ents.size();
+    std::vector<DevStripe> eds((size_t)ne);
+    for (int j = 0; j < ne;) {
+        const int key = plans[ents[j].plan].L * 2 + ents[j].cp.ld;
+        int e = j, tiles = 0;
+        while (e < ne && plans[ents[e].plan].L * 2 + ents[e].cp.ld == key) {
+            eds[e] = plans[ents[e].plan].ds;
+            eds[e].col0 = ents[e].cp.col0;
+            eds[e].tile0 = tiles;
+            tiles += ents[e].cp.ntiles;
+            e++;
+        }
+        j = e;
+    }
+    // Locator descriptors: one per active decode stripe.
+    std::vector<DevStripe> lds_((size_t)(decode ? m : 0));
+    for (int q = 0; decode && q < m; q++)
+        lds_[q] = plans[act[q]].ds;
+
+    // Device arena: [entries | locator stripes | masks | locator tables]
+    const size_t off_loc = align_up(sizeof(DevStripe) * ne, 256);
+    const size_t off_masks = align_up(off_loc + sizeof(DevStripe) * lds_.size(), 256);
+    const size_t off_rt = align_up(off_masks + mask_bytes, 256);
+    const size_t host_bytes = off_rt;
+    const size_t dev_bytes = off_rt + rt_dwords * 4;
+    int rc = ensure_dev(sc, &sc->dev, &sc->dev_cap, dev_bytes);
+    if (rc)
+        return rc;
+    uint8_t *dev = (uint8_t *)sc->dev;
+    std::vector<uint8_t> host(host_bytes, 0);
+    if (ne)
+        std::memcpy(host.data(), eds.data(), sizeof(DevStripe) * ne);
+    if (decode) {
+        std::memcpy(host.data() + off_loc, lds_.data(), sizeof(DevStripe) * m);
+        for (int q = 0; q < m; q++) {
+            const Plan &p = plans[act[q]];
+            std::memcpy(host.data() + off_masks + p.ds.mask_off, masks + p.mask_src, (size_t)p.ds.n);
+        }
+    }
+    rc = stage_upload(sc, host.data(), host_bytes, dev);
+    if (rc)
+        return rc;
+    KPtrs kp = ctx->kp;
+    kp.masks = dev + off_masks;
+    kp.rowtabs = (const uint32_t *)(dev + off_rt);
+
+    if (decode) {
+        LocatorArgs la;
+        la.stripes = (const DevStripe *)(dev + off_loc);
+        la.r = ctx->r;
+        if (dev_err(ctx, locator_launch(la, kp, ctx->d_FL, ctx->d_exp, m, max_np, stream)))
+            return RS_EDEVICE;
+    }
+    const DevStripe *d_ents = (const DevStripe *)dev;
+    for (int j = 0; j < ne;) {
+        const int key = plans[ents[j].plan].L * 2 + ents[j].cp.ld;
+        int e = j, tiles = 0;
+        while (e < ne && plans[ents[e].plan].L * 2 + ents[e].cp.ld == key) {
+            tiles += ents[e].cp.ntiles;
+            e++;
+        }
+        FusedArgs fa;
+        fa.stripes = d_ents + j;
+        fa.nstripes = e - j;
+        fa.l = 0;
+        if (dev_err(ctx, fused_launch(ctx->r, decode ? MODE_DEC : MODE_ENC, false, ents[j].cp.ld,
+                                      plans[ents[j].plan].L, fa, kp, tiles, stream)))
+            return RS_EDEVICE;
+        j = e;
+    }
+    for (int q = 0; q < m; q++) {
+        const Plan &p = plans[act[q]];
+        if (p.L <= FUSED_MAX_L)
+            continue;
+        rc = decode ? decode_large(ctx, sc, p, lds_[q], kp) : encode_large(ctx, sc, p);
+        if (rc)
+            return rc;
+    }
+    return RS_OK;
+}
+
+int run_xform(rs_ctx *ctx, int mode, int h, uint32_t l, void *data, size_t rb, hipStream_t stream)
+{
+    if (!ctx)
+        return RS_EINVAL;
+    if (!is_pow2(h) || h > (1 << ctx->r))
+        return RS_ESHAPE;
+    if (l >= (1u << ctx->r))
+        return RS_EINVAL;
+    if (rb % (size_t)sym_bytes(ctx))
+        return RS_EALIGN;
+    if (rb == 0)
+        return RS_OK;
+    if (!data)
+        return RS_EINVAL;
+    if (rb / sym_bytes(ctx) > (size_t)INT32_MAX / 2)
+        return RS_ESHAPE;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return RS_EDEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->sticky)
+        return ctx->sticky;
+    Scratch *sc = get_scratch(ctx, stream);
+    if (!sc)
+        return RS_ENOMEM;
+    const int L = ilog2(h);
+    const int ncols = (int)(rb / sym_bytes(ctx));
+    const bool aligned = vec_aligned(ctx, data, data, rb);
+    // with h | l every factor is a plain table entry; otherwise bit i of l adds 1
+    const bool gen_l = mode != MODE_DERIV && (l & (uint32_t)(h - 1)) != 0;
+    uint8_t *d = (uint8_t *)data;
+    if (mode == MODE_DERIV && L == 0)
+        return fill_zero(ctx, stream, d, rb);
+    if (L <= FUSED_MAX_L) {
+        const std::vector<ColPart> parts = col_parts(aligned, ncols);
+        std::vector<DevStripe> st(parts.size());
+        for (size_t i = 0; i < parts.size(); i++) {
+            std::memset(&st[i], 0, sizeof(DevStripe));
+            st[i].in = d;
+            st[i].out = d;
+            st[i].row_bytes = rb;
+            st[i].n = h;
+            st[i].kp = st[i].np = h;
+            st[i].ncols = ncols;
+            st[i].col0 = parts[i].col0;
+        }
+        int rc = ensure_dev(sc, &sc->dev, &sc->dev_cap, sizeof(DevStripe) * parts.size());
+        if (rc)
+            return rc;
+        rc = stage_upload(sc, st.data(), sizeof(DevStripe) * parts.size(), sc->dev);
+        if (rc)
+            return rc;
+        for (size_t i = 0; i < parts.size(); i++) {
+            FusedArgs fa;
+            fa.stripes = (const DevStripe *)sc->dev + i;
+            fa.nstripes = 1;
+            fa.l = l;
+            if (dev_err(ctx, fused_launch(ctx->r, mode, gen_l, parts[i].ld, L, fa, ctx->kp, parts[i].ntiles, stream)))
+                return RS_EDEVICE;
+        }
+        return RS_OK;
+    }
+    if (mode == MODE_FFT || mode == MODE_IFFT)
+        return run_passes(ctx, stream, mode == MODE_IFFT, gen_l, L, l, d, h, d, nullptr, 0, 0, rb, ncols, aligned,
+                          false, false);
+    // derivative: y = B d in place, partial sums into scratch, result / B back in place
+    uint8_t *Z;
+    int rc = big_scratch(sc, (size_t)h * rb, &Z);
+    if (!rc)
+        rc = scale_rows_B(ctx, stream, d, h, rb, ncols, aligned);
+    if (!rc)
+        rc = run_deriv_passes(ctx, stream, L, d, Z, d, rb, ncols, aligned);
+    return rc;
+}
+
+bool basis_independent(int r, const uint32_t *b)
+{
+    uint32_t rows[16];
+    for (int j = 0; j < r; j++) {
+        if (b[j] >> r)
+            return false;
+        rows[j] = b[j];
+    }
+    int rank = 0;
+    for (int bit = r - 1; bit >= 0; bit--) {
+        int piv = -1;
+        for (int j = rank; j < r; j++)
+            if ((rows[j] >> bit) & 1u) {
+                piv = j;
+                break;
+            }
+        if (piv < 0)
+            continue;
+        std::swap(rows[rank], rows[piv]);
+        for (int j = 0; j < r; j++)
+            if (j != rank && ((rows[j] >> bit) & 1u))
+                rows[j] ^= rows[rank];
+        rank++;
+    }
+    return rank == r;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+__attribute__((visibility("default"))) int rs_init(int r, const uint32_t *basis, rs_ctx **out)
+{
+    if (!out)
+        return RS_EINVAL;
+    *out = nullptr;
+    if (r != 8 && r != 16)
+        return RS_EFIELD;
+    uint32_t b[16];
+    for (int j = 0; j < r; j++)
+        b[j] = basis ? basis[j] : (1u << j);
+    if (!basis_independent(r, b))
+        return RS_EBASIS;
+    rs_ctx *ctx = new (std::nothrow) rs_ctx();
+    if (!ctx)
+        return RS_ENOMEM;
+    ctx->r = r;
+    std::memcpy(ctx->basis, b, sizeof(uint32_t) * r);
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        delete ctx;
+        return RS_EDEVICE;
+    }
+    static std::once_flag prep_once;
+    static hipError_t prep_err = hipSuccess;
+    std::call_once(prep_once, [] {
+        hipError_t e1 = fused_prepare_16();
+        hipError_t e2 = fused_prepare_8();
+        hipError_t e3 = init_prepare(16);
+        prep_err = e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3);
+    });
+    if (prep_err != hipSuccess) {
+        delete ctx;
+        return RS_EDEVICE;
+    }
+    const size_t q = (size_t)1 << r;
+    const int ts = r == 16 ? TAB16 : TAB8;
+    // dword counts of every table, one allocation
+    const size_t n_basis = 16, n_Wv = 256, n_S = 256, n_wp = 16, n_skew = q, n_B = q, n_Binv = q, n_exp = q,
+                 n_log = q, n_FL = 2 * q, n_tw = ts * q, n_Bt = ts * q, n_Binvt = ts * q, n_one = 4, n_onet = 32;
+    const size_t sizes[] = {n_basis, n_Wv, n_S, n_wp, n_skew, n_B, n_Binv, n_exp, n_log, n_FL, n_tw, n_Bt, n_Binvt,
+                            n_one, n_onet};
+    size_t total = 0;
+    for (size_t s : sizes)
+        total += align_up(s * 4, 256);
+    if (hipMalloc(&ctx->d_mem, total) != hipSuccess) {
+        delete ctx;
+        return RS_ENOMEM;
+    }
+    uint32_t **dst[] = {&ctx->d_basis, &ctx->d_Wv, &ctx->d_S, &ctx->d_wp, &ctx->d_skew, &ctx->d_B, &ctx->d_Binv,
+                        &ctx->d_exp, &ctx->d_log, &ctx->d_FL, &ctx->d_tw_tab, &ctx->d_B_tab, &ctx->d_Binv_tab,
+                        &ctx->d_one_val, &ctx->d_one_tab};
+    size_t off = 0;
+    for (size_t i = 0; i < sizeof(sizes) / sizeof(sizes[0]); i++) {
+        *dst[i] = (uint32_t *)((uint8_t *)ctx->d_mem + off);
+        off += align_up(sizes[i] * 4, 256);
+    }
+    uint32_t hb[16] = {0}, one[4] = {1, 0, 0, 0};
+    std::memcpy(hb, b, sizeof(uint32_t) * r);
+    hipError_t e = hipMemcpy(ctx->d_basis, hb, sizeof(hb), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(ctx->d_one_val, one, sizeof(one), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = init_tables(r, ctx->d_basis, ctx->d_Wv, ctx->d_S, ctx->d_wp, ctx->d_skew, ctx->d_B, ctx->d_Binv,
+                        ctx->d_exp, ctx->d_log, ctx->d_FL, ctx->d_tw_tab, ctx->d_B_tab, ctx->d_Binv_tab,
+                        ctx->d_one_val, ctx->d_one_tab, nullptr);
+    if (e == hipSuccess)
+        e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        (void)hipFree(ctx->d_mem);
+        delete ctx;
+        return RS_EDEVICE;
+    }
+    ctx->kp.tw = ctx->d_tw_tab;
+    ctx->kp.one = ctx->d_one_tab;
+    ctx->kp.B = ctx->d_B_tab;
+    ctx->kp.Binv = ctx->d_Binv_tab;
+    ctx->kp.masks = nullptr;
+    ctx->kp.rowtabs = nullptr;
+    *out = ctx;
+    return RS_OK;
+}
+
+__attribute__((visibility("default"))) void rs_free(rs_ctx *ctx)
+{
+    if (!ctx)
+        return;
+    DeviceGuard guard(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (Scratch *sc : ctx->scratch) {
+        if (sc->dev)
+            (void)hipFree(sc->dev);
+        if (sc->big)
+            (void)hipFree(sc->big);
+        for (int i = 0; i < NSLOTS; i++) {
+            if (sc->slots[i].host)
+                (void)hipHostFree(sc->slots[i].host);
+            if (sc->slots[i].ev)
+                (void)hipEventDestroy(sc->slots[i].ev);
+        }
+        delete sc;
+    }
+    if (ctx->d_mem)
+        (void)hipFree(ctx->d_mem);
+    delete ctx;
+}
+
+__attribute__((visibility("default"))) int rs_encode(rs_ctx *ctx, int n, int k, const void *msg, void *parity,
+                                                     size_t row_bytes, void *stream)
+{
+    rs_stripe_desc d;
+    d.n = n;
+    d.k = k;
+    d.row_bytes = row_bytes;
+    d.in = msg;
+    d.out = parity;
+    return run_codec(ctx, &d, nullptr, 1, false, (hipStream_t)stream);
+}
+
+__attribute__((visibility("default"))) int rs_decode(rs_ctx *ctx, int n, int k, const uint8_t *erasure_mask,
+                                                     const void *shards, void *out, size_t row_bytes,
+                                                     void *stream)
+{
+    rs_stripe_desc d;
+    d.n = n;
+    d.k = k;
+    d.row_bytes = row_bytes;
+    d.in = shards;
+    d.out = out;
+    return run_codec(ctx, &d, erasure_mask, 1, true, (hipStream_t)stream);
+}
+
+__attribute__((visibility("default"))) int rs_encode_batch(rs_ctx *ctx, const rs_stripe_desc *descs, int count,
+                                                           void *stream)
+{
+    return run_codec(ctx, descs, nullptr, count, false, (hipStream_t)stream);
+}
+
+__attribute__((visibility("default"))) int rs_decode_batch(rs_ctx *ctx, const rs_stripe_desc *descs,
+                                                           const uint8_t *masks, int count, void *stream)
+{
+    return run_codec(ctx, descs, masks, count, true, (hipStream_t)stream);
+}
+
+__attribute__((visibility("default"))) int nb_fft(rs_ctx *ctx, int h, uint32_t l, void *data, size_t row_bytes,
+                                                  void *stream)
+{
+    return run_xform(ctx, MODE_FFT, h, l, data, row_bytes, (hipStream_t)stream);
+}
+
+__attribute__((visibility("default"))) int nb_ifft(rs_ctx *ctx, int h, uint32_t l, void *data, size_t row_bytes,
+                                                   void *stream)
+{
+    return run_xform(ctx, MODE_IFFT, h, l, data, row_bytes, (hipStream_t)stream);
+}
+
+__attribute__((visibility("default"))) int nb_derivative(rs_ctx *ctx, int h, void *data, size_t row_bytes,
+                                                         void *stream)
+{
+    return run_xform(ctx, MODE_DERIV, h, 0, data, row_bytes, (hipStream_t)stream);
+}
+
+__attribute__((visibility("default"))) int rs_sync(rs_ctx *ctx, void *stream)
+{
+    if (!ctx)
+        return RS_EINVAL;
+    DeviceGuard guard(ctx->device);
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+        ctx->sticky = RS_EDEVICE;
+    return ctx->sticky;
+}
+
+__attribute__((visibility("default"))) int rs_get_table(rs_ctx *ctx, int which, uint32_t *host_out, size_t count)
+{
+    if (!ctx || !host_out)
+        return RS_EINVAL;
+    const size_t q = (size_t)1 << ctx->r;
+    const uint32_t *src = nullptr;
+    size_t len = 0;
+    switch (which) {
+    case RS_TAB_SKEW: src = ctx->d_skew; len = q - 1; break;
+    case RS_TAB_B: src = ctx->d_B; len = q; break;
+    case RS_TAB_BINV: src = ctx->d_Binv; len = q; break;
+    case RS_TAB_LOG: src = ctx->d_log; len = q; break;
+    case RS_TAB_EXP: src = ctx->d_exp; len = q; break;
+    default: return RS_EINVAL;
+    }
+    if (count < len)
+        return RS_EINVAL;
+    DeviceGuard guard(ctx->device);
+    if (hipMemcpy(host_out, src, len * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return RS_EDEVICE;
+    return (int)len;
+}
+
+__attribute__((visibility("default"))) const char *rs_strerror(int code)
+{
+    switch (code) {
+    case RS_OK: return "success";
+    case RS_EINVAL: return "invalid argument";
+    case RS_EFIELD: return "unsupported field (r must be 8 or 16)";
+    case RS_EBASIS: return "basis is not F2-independent";
+    case RS_ESHAPE: return "unsupported transform size or code shape";
+    case RS_ETOOMANY: return "more erasures than parity symbols";
+    case RS_EALIGN: return "row length is not a multiple of the symbol size";
+    case RS_ENOMEM: return "out of memory";
+    case RS_EDEVICE: return "device error";
+    default: return "unknown error";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,213 @@
+"""ctypes binding of librs_nb.so (the C ABI of include/rs.h).
+
+Argument marshalling only: every step of the codec runs in the HIP library.
+Device buffers are torch tensors (uint8, CUDA/HIP device, C-contiguous) or
+raw integer device addresses; streams default to torch's current stream.
+The library is loaded from the package directory; if it has not been built
+the first call raises, and nothing falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librs_nb.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "rs.h")
+
+RS_OK, RS_EINVAL, RS_EFIELD, RS_EBASIS, RS_ESHAPE, RS_ETOOMANY, RS_EALIGN, RS_ENOMEM, RS_EDEVICE = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+RS_TAB_SKEW, RS_TAB_B, RS_TAB_BINV, RS_TAB_LOG, RS_TAB_EXP = range(5)
+
+_lib = None
+
+
+class RSError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (what, strerror(code) if _lib else "error", code))
+
+
+class StripeDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("k", ctypes.c_int32), ("row_bytes", ctypes.c_uint64),
+                ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+def load():
+    """Load librs_nb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("librs_nb.so is not built (run python -m paper_1404_3458_amd.build)")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i32, u32, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_size_t
+        sig = {
+            "rs_init": (i32, [i32, vp, ctypes.POINTER(vp)]),
+            "rs_free": (None, [vp]),
+            "rs_encode": (i32, [vp, i32, i32, vp, vp, sz, vp]),
+            "rs_decode": (i32, [vp, i32, i32, vp, vp, vp, sz, vp]),
+            "nb_fft": (i32, [vp, i32, u32, vp, sz, vp]),
+            "nb_ifft": (i32, [vp, i32, u32, vp, sz, vp]),
+            "nb_derivative": (i32, [vp, i32, vp, sz, vp]),
+            "rs_encode_batch": (i32, [vp, vp, i32, vp]),
+            "rs_decode_batch": (i32, [vp, vp, vp, i32, vp]),
+            "rs_sync": (i32, [vp, vp]),
+            "rs_get_table": (i32, [vp, i32, vp, sz]),
+            "rs_strerror": (ctypes.c_char_p, [i32]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def header_functions():
+    """Names of the functions include/rs.h declares."""
+    txt = open(HEADER_PATH).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:rs|nb)_[a-z_]+)\s*\(", txt)))
+
+
+def strerror(code):
+    return load().rs_strerror(code).decode()
+
+
+def _check(rc, what):
+    if rc != RS_OK:
+        raise RSError(rc, what)
+    return rc
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _rows(t, nrows=None):
+    """(rows, row_bytes) of a contiguous uint8 tensor; raw ints pass through."""
+    import torch
+
+    assert t.dtype == torch.uint8 and t.is_contiguous(), "expected a contiguous uint8 tensor"
+    if nrows is not None:
+        assert t.dim() == 2 and t.shape[0] == nrows, (t.shape, nrows)
+    return t.shape[0], (t.shape[1] if t.dim() == 2 else 0)
+
+
+class Codec:
+    """One rs_ctx: field GF(2^r) with a basis, tables resident on the current device."""
+
+    def __init__(self, r=16, basis=None):
+        lib = load()
+        self.r = r
+        self._ctx = ctypes.c_void_p()
+        b = None
+        if basis is not None:
+            self._basis = np.ascontiguousarray(np.asarray(basis, dtype=np.uint32))
+            b = self._basis.ctypes.data_as(ctypes.c_void_p)
+        _check(lib.rs_init(r, b, ctypes.byref(self._ctx)), "rs_init")
+
+    def close(self):
+        if self._ctx:
+            load().rs_free(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ codec
+    def encode(self, n, k, msg, parity, row_bytes=None, stream=None):
+        if row_bytes is None:
+            _, row_bytes = _rows(msg, k)
+            _rows(parity, n - k)
+        return _check(load().rs_encode(self._ctx, n, k, _ptr(msg), _ptr(parity), row_bytes, _stream(stream)),
+                      "rs_encode")
+
+    def decode(self, n, k, mask, shards, out=None, row_bytes=None, stream=None):
+        mk = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        assert mk.shape == (n,)
+        if out is None:
+            out = shards
+        if row_bytes is None:
+            _, row_bytes = _rows(shards, n)
+            _rows(out, n)
+        return _check(load().rs_decode(self._ctx, n, k, mk.ctypes.data_as(ctypes.c_void_p), _ptr(shards),
+                                       _ptr(out), row_bytes, _stream(stream)), "rs_decode")
+
+    def encode_batch(self, stripes, stream=None):
+        """stripes: list of (n, k, msg, parity[, row_bytes])."""
+        arr = (StripeDesc * len(stripes))()
+        for i, s in enumerate(stripes):
+            n, k, msg, par = s[:4]
+            rb = s[4] if len(s) > 4 else _rows(msg, k)[1]
+            arr[i] = StripeDesc(n, k, rb, _ptr(msg), _ptr(par))
+        return _check(load().rs_encode_batch(self._ctx, ctypes.cast(arr, ctypes.c_void_p), len(stripes),
+                                             _stream(stream)), "rs_encode_batch")
+
+    def decode_batch(self, stripes, stream=None):
+        """stripes: list of (n, k, mask, shards, out[, row_bytes])."""
+        arr = (StripeDesc * len(stripes))()
+        masks = []
+        for i, s in enumerate(stripes):
+            n, k, mask, sh, out = s[:5]
+            rb = s[5] if len(s) > 5 else _rows(sh, n)[1]
+            arr[i] = StripeDesc(n, k, rb, _ptr(sh), _ptr(out if out is not None else sh))
+            masks.append(np.asarray(mask, dtype=np.uint8).reshape(-1))
+        allm = np.ascontiguousarray(np.concatenate(masks) if masks else np.zeros(0, np.uint8))
+        return _check(load().rs_decode_batch(self._ctx, ctypes.cast(arr, ctypes.c_void_p),
+                                             allm.ctypes.data_as(ctypes.c_void_p), len(stripes),
+                                             _stream(stream)), "rs_decode_batch")
+
+    # ------------------------------------------------------------ transforms
+    def fft(self, h, l, data, row_bytes=None, stream=None):
+        if row_bytes is None:
+            _, row_bytes = _rows(data, h)
+        return _check(load().nb_fft(self._ctx, h, l, _ptr(data), row_bytes, _stream(stream)), "nb_fft")
+
+    def ifft(self, h, l, data, row_bytes=None, stream=None):
+        if row_bytes is None:
+            _, row_bytes = _rows(data, h)
+        return _check(load().nb_ifft(self._ctx, h, l, _ptr(data), row_bytes, _stream(stream)), "nb_ifft")
+
+    def derivative(self, h, data, row_bytes=None, stream=None):
+        if row_bytes is None:
+            _, row_bytes = _rows(data, h)
+        return _check(load().nb_derivative(self._ctx, h, _ptr(data), row_bytes, _stream(stream)),
+                      "nb_derivative")
+
+    # ------------------------------------------------------------ misc
+    def sync(self, stream=None):
+        return _check(load().rs_sync(self._ctx, _stream(stream)), "rs_sync")
+
+    def table(self, which):
+        q = 1 << self.r
+        out = np.zeros(q, dtype=np.uint32)
+        n = load().rs_get_table(self._ctx, which, out.ctypes.data_as(ctypes.c_void_p), q)
+        if n < 0:
+            raise RSError(n, "rs_get_table")
+        return out[:n]
+
+    def raw_call(self, name, *args):
+        """Call a C-ABI function with this context first and return its code
+        (error-path tests)."""
+        return getattr(load(), name)(self._ctx, *args)

@@ -19,3 +19,21 @@ def orc():
 
     oracle.build()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def codec16():
+    from paper_1404_3458_amd import rs
+
+    c = rs.Codec(16)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="session")
+def codec8():
+    from paper_1404_3458_amd import rs
+
+    c = rs.Codec(8)
+    yield c
+    c.close()

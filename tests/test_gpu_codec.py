@@ -1,0 +1,182 @@
+"""GPU parity of Algorithm 1 (encode) and Algorithm 2 (erasure decode),
+single-stripe and batched, against the oracle, bit for bit, through the C ABI;
+plus the error paths of the boundary."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1404_3458_amd import rs, synth
+from gpu_util import first_diff, rand_rows, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+SHAPES16 = [(4, 2), (16, 8), (64, 48), (256, 128), (256, 224), (40, 7), (1024, 512), (4096, 2048)]
+SHAPES8 = [(2, 1), (16, 8), (12, 8), (10, 3), (64, 48), (256, 128), (200, 100)]
+
+
+def _cols(n):
+    return [1, 5, 259] if n <= 256 else [3, 260]
+
+
+def _encode_check(c, r, n, k, ncols, key):
+    sym = r // 8
+    msg = rand_rows(k, ncols * sym, 50, r, n, k, ncols, key)
+    dm = to_dev(msg)
+    dp = torch.zeros((n - k, ncols * sym), dtype=torch.uint8, device="cuda")
+    c.encode(n, k, dm, dp)
+    got = to_host(dp)
+    exp = oracle.encode(r, n, k, msg)
+    assert (got == exp).all(), (r, n, k, ncols, first_diff(got, exp))
+    return msg, exp
+
+
+@pytest.mark.parametrize("n,k", SHAPES16)
+def test_encode_r16(codec16, n, k):
+    for ncols in _cols(n):
+        _encode_check(codec16, 16, n, k, ncols, 1)
+
+
+@pytest.mark.parametrize("n,k", SHAPES8)
+def test_encode_r8(codec8, n, k):
+    for ncols in _cols(n):
+        _encode_check(codec8, 8, n, k, ncols, 2)
+
+
+def _decode_check(c, r, n, k, ncols, e, key, inplace):
+    sym = r // 8
+    msg = rand_rows(k, ncols * sym, 51, r, n, k, ncols, key)
+    cw = np.concatenate([msg, oracle.encode(r, n, k, msg)])
+    mask = synth.erasure_mask(synth.key(52, r, n, k, key), n, e)
+    rx = cw.copy()
+    rx[mask == 1] = 0xA5                       # garbage in erased rows
+    ds = to_dev(rx)
+    if inplace:
+        c.decode(n, k, mask, ds)
+        got = to_host(ds)
+    else:
+        do = torch.zeros_like(ds)
+        c.decode(n, k, mask, ds, do)
+        got = to_host(do)
+        assert (to_host(ds) == rx).all()      # input untouched
+    assert (got == cw).all(), (r, n, k, ncols, e, first_diff(got, cw))
+
+
+@pytest.mark.parametrize("n,k", SHAPES16)
+def test_decode_r16(codec16, n, k):
+    for ncols in _cols(n):
+        for e, inplace in ((n - k, True), ((n - k) // 2, False), (1, True)):
+            _decode_check(codec16, 16, n, k, ncols, e, ncols + e, inplace)
+
+
+@pytest.mark.parametrize("n,k", SHAPES8)
+def test_decode_r8(codec8, n, k):
+    for ncols in _cols(n):
+        for e, inplace in ((n - k, True), ((n - k) // 2, False), (0, False)):
+            _decode_check(codec8, 8, n, k, ncols, e, ncols + e, inplace)
+
+
+def test_decode_every_k_subset_n16_gpu(codec8):
+    # all 12870 8-subsets of a (16, 8) code, one column each, as one batch
+    import itertools
+
+    n, k = 16, 8
+    msg = rand_rows(k, 1, 53)
+    cw = np.concatenate([msg, oracle.encode(8, n, k, msg)])
+    pats = list(itertools.combinations(range(n), k))
+    rx = np.tile(cw, (len(pats), 1, 1))
+    masks = np.ones((len(pats), n), dtype=np.uint8)
+    for i, keep in enumerate(pats):
+        masks[i, list(keep)] = 0
+    rx[masks == 1] = 0
+    d = to_dev(rx)
+    codec8.decode_batch([(n, k, masks[i], d[i], d[i]) for i in range(len(pats))])
+    got = to_host(d)
+    assert (got == cw[None]).all()
+
+
+def test_c3_shape_encode_decode(codec16):
+    # one (65536, 32768) codeword with 128 symbols per row (256-byte rows)
+    n, k, ncols = 65536, 32768, 128
+    msg, par = _encode_check(codec16, 16, n, k, ncols, 3)
+    cw = np.concatenate([msg, par])
+    mask = synth.erasure_mask(synth.key(54), n, n - k)
+    rx = cw.copy()
+    rx[mask == 1] = 0
+    d = to_dev(rx)
+    codec16.decode(n, k, mask, d)
+    got = to_host(d)
+    assert (got == cw).all(), first_diff(got, cw)
+
+
+def test_batch_mixed_shapes(codec16):
+    specs = [(16, 8, 1000), (64, 48, 514), (256, 224, 2050), (1024, 512, 300), (256, 128, 4096), (16, 8, 2)]
+    msgs, pars, exps = [], [], []
+    for i, (n, k, rb) in enumerate(specs):
+        m = rand_rows(k, rb, 55, i)
+        msgs.append(to_dev(m))
+        pars.append(torch.zeros((n - k, rb), dtype=torch.uint8, device="cuda"))
+        exps.append(oracle.encode(16, n, k, m))
+    codec16.encode_batch([(n, k, msgs[i], pars[i]) for i, (n, k, _) in enumerate(specs)])
+    for i in range(len(specs)):
+        got = to_host(pars[i])
+        assert (got == exps[i]).all(), (specs[i], first_diff(got, exps[i]))
+    # decode all in one batch, half in place
+    items, cws = [], []
+    for i, (n, k, rb) in enumerate(specs):
+        cw = np.concatenate([to_host(msgs[i]), exps[i]])
+        e = int(synth.uniform_int(synth.key(56, i), 1, 0, n - k)[0])
+        mask = synth.erasure_mask(synth.key(57, i), n, e)
+        rx = cw.copy()
+        rx[mask == 1] = 0
+        ds = to_dev(rx)
+        do = ds if i % 2 == 0 else torch.zeros_like(ds)
+        items.append((n, k, mask, ds, do))
+        cws.append(cw)
+    codec16.decode_batch(items)
+    for i, it in enumerate(items):
+        got = to_host(it[4])
+        assert (got == cws[i]).all(), (specs[i], first_diff(got, cws[i]))
+
+
+def test_error_paths(codec16):
+    d = torch.zeros((16, 8), dtype=torch.uint8, device="cuda")
+    p = torch.zeros((8, 8), dtype=torch.uint8, device="cuda")
+    with pytest.raises(rs.RSError) as e:
+        codec16.encode(16, 16, d, d, row_bytes=8)
+    assert e.value.code == rs.RS_ESHAPE
+    with pytest.raises(rs.RSError) as e:
+        codec16.encode(16, 8, d[:8], p, row_bytes=7)
+    assert e.value.code == rs.RS_EALIGN
+    with pytest.raises(rs.RSError) as e:
+        codec16.encode(131072, 8, d[:8], p, row_bytes=8)
+    assert e.value.code == rs.RS_ESHAPE
+    mask = np.zeros(16, np.uint8)
+    mask[:9] = 1
+    with pytest.raises(rs.RSError) as e:
+        codec16.decode(16, 8, mask, d)
+    assert e.value.code == rs.RS_ETOOMANY
+    with pytest.raises(rs.RSError) as e:
+        codec16.fft(12, 0, d, row_bytes=8)
+    assert e.value.code == rs.RS_ESHAPE
+    assert codec16.raw_call("rs_encode", 16, 8, None, None, 8, None) == rs.RS_EINVAL
+    # nothing was written by the rejected calls
+    assert int(p.sum()) == 0 and int(d.sum()) == 0
+    assert codec16.raw_call("rs_encode", 16, 8, None, None, 0, None) == rs.RS_OK   # empty rows: no-op
+
+
+def test_corrupted_survivor_is_not_detected(codec16):
+    # the decoder is erasure-only: a wrong surviving symbol silently yields a
+    # wrong (but well-formed) result, as the paper's decoder has no check
+    n, k = 16, 8
+    msg = rand_rows(k, 8, 58)
+    cw = np.concatenate([msg, oracle.encode(16, n, k, msg)])
+    mask = np.zeros(n, np.uint8)
+    mask[[1, 3, 9]] = 1
+    rx = cw.copy()
+    rx[0, 0] ^= 1
+    d = to_dev(rx)
+    codec16.decode(n, k, mask, d)
+    got = to_host(d)
+    assert not (got == cw).all()
+    assert (got == oracle.decode(16, n, k, mask, rx)).all()
