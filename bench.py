@@ -1,0 +1,266 @@
+#!/usr/bin/env python3
+"""Benchmark of the novel-basis Reed-Solomon erasure codec on one MI355X.
+
+A step is one pass of the whole hot path over one batch of synthetic stripes:
+Algorithm 1 (encode every stripe), then Algorithm 2 (recover the erased rows
+of every stripe, in place).  Default workload: GF(2^16) mod 0x1100B, the
+(n, k) = (256, 128) code, 64 stripes of 64 KiB shards (512 MiB of message),
+n - k = 128 uniformly drawn erasures per stripe.
+
+Prints one JSON line.  `value` is message bytes per second of the whole step
+(each message byte is encoded and then decoded once per step).  `roofline`
+describes the dominant kernel (the decode launch): algorithmic bytes (n * S
+per stripe: survivors read and erased rows written) over its average duration
+measured with HIP events on the launch stream.  `cpu_baseline` times the CPU
+oracle on a bounded sample of the same workload on this host's cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+CONFIGS = {
+    "c2": dict(r=16, n=256, k=128, stripes=64, shard_bytes=65536, erasures=128,
+               workload="GF(2^16) mod 0x1100B, (n,k)=(256,128), 64 stripes x 64 KiB shards, "
+                        "encode + 128 erasures per stripe + decode"),
+    "c1": dict(r=8, n=16, k=8, stripes=4096, shard_bytes=1, erasures=8,
+               workload="GF(2^8) mod 0x11D, (n,k)=(16,8), 4096 stripes x 1 B shards, "
+                        "encode + 8 erasures per stripe + decode"),
+    "c3": dict(r=16, n=65536, k=32768, stripes=1, shard_bytes=256, erasures=32768,
+               workload="GF(2^16) mod 0x1100B, (n,k)=(65536,32768), 1 stripe x 256 B shards, "
+                        "encode + 32768 erasures + decode"),
+}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1404_3458_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(cfg_name, launches_per_step):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when it was taken from different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % cfg_name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(cfg, sample_stripes, sample_cols, threads):
+    """Oracle encode + decode of `sample_stripes` stripes restricted to
+    `sample_cols` columns each, on `threads` host threads (column blocks)."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    import oracle
+    from paper_1404_3458_amd import synth
+
+    r, n, k, S = cfg["r"], cfg["n"], cfg["k"], cfg["shard_bytes"]
+    sym = r // 8
+    cols = min(sample_cols, S // sym)
+    jobs = []
+    for s in range(sample_stripes):
+        msg = synth.random_bytes(synth.key(cfg["id"], s, synth.DATA), k * S).reshape(k, S)[:, :cols * sym]
+        mask = synth.erasure_mask(synth.key(cfg["id"], s, synth.ERASURE), n, cfg["erasures"])
+        jobs.append((np.ascontiguousarray(msg), mask))
+    blocks = []
+    for msg, mask in jobs:
+        per = max(1, cols // threads)
+        for c0 in range(0, cols, per):
+            blocks.append((msg[:, c0 * sym:min(cols, c0 + per) * sym].copy(), mask))
+    oracle.build()
+
+    def work(item):
+        msg, mask = item
+        par = oracle.encode(r, n, k, msg)
+        cw = np.concatenate([msg, par])
+        rx = cw.copy()
+        rx[mask == 1] = 0
+        out = oracle.decode(r, n, k, mask, rx)
+        assert (out == cw).all()
+        return msg.nbytes
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        nbytes = sum(ex.map(work, blocks))
+    dt = time.perf_counter() - t0
+    return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": "%d stripe(s) x %d columns of the same workload (%d B of message), encode + decode, "
+                      "%.2f s wall" % (sample_stripes, cols, nbytes, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--cpu-stripes", type=int, default=2)
+    ap.add_argument("--cpu-cols", type=int, default=32768)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-per-stripe", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no collectives or sharding); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1404_3458_amd import rs, synth
+
+    cfg = dict(CONFIGS[args.config])
+    cfg["id"] = {"c1": 1, "c2": 2, "c3": 3}[args.config]
+    r, n, k, S, ns, e = cfg["r"], cfg["n"], cfg["k"], cfg["shard_bytes"], cfg["stripes"], cfg["erasures"]
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    codec = rs.Codec(r)
+    stream = torch.cuda.current_stream()
+
+    # Codeword buffer: stripe s rows 0..k-1 are its message, k..n-1 its parity.
+    cw = torch.empty((ns, n, S), dtype=torch.uint8, device=dev)
+    for s in range(ns):
+        synth.fill_random_torch(synth.key(cfg["id"], s, synth.DATA), cw[s, :k])
+    masks = [synth.erasure_mask(synth.key(cfg["id"], s, synth.ERASURE), n, e) for s in range(ns)]
+    enc_items = [(n, k, cw[s, :k], cw[s, k:]) for s in range(ns)]
+    dec_items = [(n, k, masks[s], cw[s], cw[s]) for s in range(ns)]
+
+    def step():
+        codec.encode_batch(enc_items)
+        codec.decode_batch(dec_items)
+
+    # Parity check on a column sample before timing (the oracle, one column
+    # block of two stripes), and recovery of explicitly zeroed erasures.
+    if not args.no_check:
+        import oracle
+
+        codec.encode_batch(enc_items)
+        torch.cuda.synchronize()
+        ref = cw.clone()
+        for s in range(ns):
+            cw[s][torch.from_numpy(masks[s]).bool().to(dev)] = 0
+        codec.decode_batch(dec_items)
+        torch.cuda.synchronize()
+        assert torch.equal(cw, ref), "decode did not restore the codeword"
+        sym = r // 8
+        for s in sorted({0, ns - 1}):
+            cols = sorted({0, 1, 2, 3, S // sym - 1, S // sym - 4} | set(
+                int(c) for c in synth.uniform_int(synth.key(cfg["id"], s, 77), 24, 0, S // sym - 1)))
+            cols = [c for c in cols if 0 <= c < S // sym]
+            host = cw[s].cpu().numpy().reshape(n, S // sym, sym)[:, cols, :].reshape(n, len(cols) * sym)
+            par = oracle.encode(r, n, k, np.ascontiguousarray(host[:k]))
+            assert (par == host[k:]).all(), "parity differs from the oracle on sampled columns"
+        del ref
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        codec.encode_batch(enc_items)
+        ev[i][1].record(stream)
+        codec.decode_batch(dec_items)
+        ev[i][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    enc_ms = np.array([ev[i][0].elapsed_time(ev[i][1]) for i in range(args.steps)])
+    dec_ms = np.array([ev[i][1].elapsed_time(ev[i][2]) for i in range(args.steps)])
+    step_ms = enc_ms + dec_ms
+    ms_per_step = wall * 1e3 / args.steps
+
+    msg_bytes = ns * k * S
+    algo_bytes = ns * n * S               # per encode launch and per decode launch
+    value = msg_bytes / (ms_per_step * 1e-3) / 1e9
+    enc_gbs = msg_bytes / (enc_ms.mean() * 1e-3) / 1e9
+    dec_gbs = msg_bytes / (dec_ms.mean() * 1e-3) / 1e9
+    dom = "decode" if dec_ms.mean() >= enc_ms.mean() else "encode"
+    dom_ms = max(dec_ms.mean(), enc_ms.mean())
+    achieved = algo_bytes / (dom_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_from_profiles(args.config, 1),
+            "kernel": "fused %s launch (k_%s, L=%d)" % (dom, "tiled" if (n if dom == "decode" else k) > 16 else "small",
+                                                        int(np.log2(n if dom == "decode" else k))),
+            "algorithmic_bytes_per_launch": algo_bytes}
+
+    extra = {
+        "encode_ms": round(float(enc_ms.mean()), 4), "decode_ms": round(float(dec_ms.mean()), 4),
+        "encode_msg_GBps": round(enc_gbs, 1), "decode_msg_GBps": round(dec_gbs, 1),
+        "encode_hbm_frac": round(algo_bytes / (enc_ms.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "decode_hbm_frac": round(algo_bytes / (dec_ms.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "step_ms_p50": round(float(np.percentile(step_ms, 50)), 4),
+        "step_ms_p99": round(float(np.percentile(step_ms, 99)), 4),
+        "msg_over_hbm_peak": round(value / HBM_PEAK_GBS, 4),
+    }
+
+    if not args.no_per_stripe and ns > 1:
+        # the same work as per-stripe launches (one call per stripe and direction)
+        reps = max(2, args.steps // 4)
+        for s in range(ns):
+            codec.encode(n, k, cw[s, :k], cw[s, k:])
+            codec.decode(n, k, masks[s], cw[s])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            for s in range(ns):
+                codec.encode(n, k, cw[s, :k], cw[s, k:])
+            for s in range(ns):
+                codec.decode(n, k, masks[s], cw[s])
+        torch.cuda.synchronize()
+        ps_ms = (time.perf_counter() - t1) * 1e3 / reps
+        extra["per_stripe_ms_per_step"] = round(ps_ms, 3)
+        extra["batched_over_per_stripe"] = round(ps_ms / ms_per_step, 3)
+
+    cpu = None
+    if not args.no_cpu:
+        threads = min(16, len(os.sched_getaffinity(0)))
+        cpu = cpu_baseline(cfg, min(args.cpu_stripes, ns), args.cpu_cols, threads)
+        cpu["ratio_gpu_over_cpu"] = round(value / cpu["value"], 1)
+
+    out = {
+        "metric": "RS encode/decode GB/s of message data (% HBM peak); batched vs per-stripe; p99",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16" if r == 16 else "u8",
+        "data": "synthetic (seeded splitmix64 bytes, uniform erasure subsets)",
+        "config": {"workload": cfg["workload"], "field_bits": r, "n": n, "k": k, "stripes": ns,
+                   "shard_bytes": S, "erasures_per_stripe": e, "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "detail": extra,
+    }
+    print(json.dumps(out))
+    codec.close()
+
+
+if __name__ == "__main__":
+    main()

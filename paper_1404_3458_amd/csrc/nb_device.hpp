@@ -11,18 +11,19 @@
 // is split into bit groups of 3, 3 and 2 bits, and s * (group << offset) is
 // looked up per group and per output byte, then XOR-ed (the product is
 // GF(2)-linear in the multiplicand).  A constant's lookup tables ("perm
-// table") take 20 dwords for r = 16 and 5 (stored as 8) for r = 8:
+// table") take 20 dwords for r = 16 and 5 (stored as 8) for r = 8.
 //
-//   r = 16, input byte b in {L = 0, H = 1}, base = 10 b:
-//     group 0 (bits 0-2): [base+0] L-out entries 0-3, [base+1] L-out 4-7,
-//                         [base+2] H-out entries 0-3, [base+3] H-out 4-7
-//     group 1 (bits 3-5): [base+4 .. base+7] likewise
-//     group 2 (bits 6-7): [base+8] L-out entries 0-3, [base+9] H-out 0-3
-//   r = 8: [0..1] group 0, [2..3] group 1, [4] group 2
-//
-// Entry e of a table occupies byte (e mod 4) of dword (e / 4), which is the
-// byte v_perm_b32 returns for selector value e when the dword pair is passed
-// as (hi = entries 4-7, lo = entries 0-3).
+// v_perm_b32 reads 8 table bytes from a (hi, lo) dword pair and can take only
+// one scalar operand, so every 3-bit group table has one word that must sit
+// in a vector register (its entries 0-3, "V words") and one that can stay
+// scalar (entries 4-7, "S words"); the 2-bit group tables have 4 entries and
+// are one S word, with the selector itself as the ignored high operand.
+// Layout, r = 16 (tables numbered by input byte L/H, group, output byte):
+//   [0..7]   V words: gL0->L, gL0->H, gL1->L, gL1->H, gH0->L, gH0->H, gH1->L, gH1->H
+//   [8..15]  S words of the same eight tables, same order
+//   [16..19] 2-bit tables: gL2->L, gL2->H, gH2->L, gH2->H
+// r = 8: [0..1] V words of g0, g1; [2..3] their S words; [4] the 2-bit table.
+// Entry e of a table occupies byte (e mod 4) of the word holding it.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -99,17 +100,23 @@ __device__ inline void build_perm_table(uint32_t s, int r, uint32_t *out)
                 hi_out[e >> 2] |= ((prod >> 8) & 0xFFu) << (8 * (e & 3));
             }
             if (r == 16) {
-                uint32_t *o = out + 10 * b + 4 * g;
                 if (g < 2) {
-                    o[0] = lo_out[0]; o[1] = lo_out[1]; o[2] = hi_out[0]; o[3] = hi_out[1];
+                    const int v = 4 * b + 2 * g;          // table index among the eight
+                    out[v] = lo_out[0];
+                    out[8 + v] = lo_out[1];
+                    out[v + 1] = hi_out[0];
+                    out[8 + v + 1] = hi_out[1];
                 } else {
-                    o[0] = lo_out[0]; o[1] = hi_out[0];
+                    out[16 + 2 * b] = lo_out[0];
+                    out[16 + 2 * b + 1] = hi_out[0];
                 }
             } else {
-                uint32_t *o = out + 2 * g;
-                o[0] = lo_out[0];
-                if (g < 2)
-                    o[1] = lo_out[1];
+                if (g < 2) {
+                    out[g] = lo_out[0];
+                    out[2 + g] = lo_out[1];
+                } else {
+                    out[4] = lo_out[0];
+                }
             }
         }
     }
@@ -130,37 +137,87 @@ __device__ __forceinline__ uint32_t prm(uint32_t hi, uint32_t lo, uint32_t sel)
     return __builtin_amdgcn_perm(hi, lo, sel);
 }
 
-// a ^= s * b for 4 symbols, r = 16 (t: perm table of s).
-__device__ __forceinline__ void mac16(uint32_t &aL, uint32_t &aH, uint32_t bL, uint32_t bH,
-                                      const uint32_t *__restrict__ t)
+constexpr int VW16 = 8;     // V words per table, r = 16
+constexpr int VW8 = 2;      // V words per table, r = 8
+
+// A constant's perm table as the multiply reads it: the V words in vector
+// registers (read from LDS, or copied from scalar registers by the compiler)
+// and the S words through a scalar-load pointer to the full table.
+template <int NV>
+struct TabT {
+    uint32_t v[NV];
+    const uint32_t *__restrict__ t;
+};
+typedef TabT<VW16> Tab16;
+typedef TabT<VW8> Tab8;
+
+// a ^= s * b for 4 symbols, r = 16.
+__device__ __forceinline__ void mac16(uint32_t &aL, uint32_t &aH, uint32_t bL, uint32_t bH, const Tab16 &T)
 {
     const uint32_t m3 = 0x07070707u, m2 = 0x03030303u;
     const uint32_t s0 = bL & m3, s1 = (bL >> 3) & m3, s2 = (bL >> 6) & m2;
     const uint32_t s3 = bH & m3, s4 = (bH >> 3) & m3, s5 = (bH >> 6) & m2;
-    aL = xor3(aL, prm(t[1], t[0], s0), prm(t[5], t[4], s1));
-    aH = xor3(aH, prm(t[3], t[2], s0), prm(t[7], t[6], s1));
-    aL = xor3(aL, prm(t[8], t[8], s2), prm(t[11], t[10], s3));
-    aH = xor3(aH, prm(t[9], t[9], s2), prm(t[13], t[12], s3));
-    aL = xor3(aL, prm(t[15], t[14], s4), prm(t[18], t[18], s5));
-    aH = xor3(aH, prm(t[17], t[16], s4), prm(t[19], t[19], s5));
+    const uint32_t *__restrict__ t = T.t;
+    const uint32_t *v = T.v;
+    aL = xor3(aL, prm(t[8], v[0], s0), prm(t[10], v[2], s1));
+    aH = xor3(aH, prm(t[9], v[1], s0), prm(t[11], v[3], s1));
+    aL = xor3(aL, prm(s2, t[16], s2), prm(t[12], v[4], s3));
+    aH = xor3(aH, prm(s2, t[17], s2), prm(t[13], v[5], s3));
+    aL = xor3(aL, prm(t[14], v[6], s4), prm(s5, t[18], s5));
+    aH = xor3(aH, prm(t[15], v[7], s4), prm(s5, t[19], s5));
 }
 
 // a ^= s * b for 4 symbols, r = 8.
-__device__ __forceinline__ void mac8(uint32_t &a, uint32_t b, const uint32_t *__restrict__ t)
+__device__ __forceinline__ void mac8(uint32_t &a, uint32_t b, const Tab8 &T)
 {
     const uint32_t m3 = 0x07070707u, m2 = 0x03030303u;
     const uint32_t s0 = b & m3, s1 = (b >> 3) & m3, s2 = (b >> 6) & m2;
-    a = xor3(a, prm(t[1], t[0], s0), prm(t[3], t[2], s1));
-    a ^= prm(t[4], t[4], s2);
+    const uint32_t *__restrict__ t = T.t;
+    a = xor3(a, prm(t[2], T.v[0], s0), prm(t[3], T.v[1], s1));
+    a ^= prm(s2, t[4], s2);
+}
+
+// Table from global memory only (V words taken from the scalar loads).
+template <int NV>
+__device__ __forceinline__ TabT<NV> tab_global(const uint32_t *__restrict__ t)
+{
+    TabT<NV> r;
+#pragma unroll
+    for (int u = 0; u < NV; u++)
+        r.v[u] = t[u];
+    r.t = t;
+    return r;
+}
+
+// Table with the V words read from LDS (all lanes read the same address).
+template <int NV>
+__device__ __forceinline__ TabT<NV> tab_lds(const uint32_t *lds_v, const uint32_t *__restrict__ t)
+{
+    TabT<NV> r;
+    if (NV == 8) {
+        const uint4 a = *reinterpret_cast<const uint4 *>(lds_v);
+        const uint4 b = *reinterpret_cast<const uint4 *>(lds_v + 4);
+        r.v[0] = a.x; r.v[1] = a.y; r.v[2] = a.z; r.v[3] = a.w;
+        r.v[NV > 4 ? 4 : 0] = b.x; r.v[NV > 5 ? 5 : 0] = b.y; r.v[NV > 6 ? 6 : 0] = b.z; r.v[NV > 7 ? 7 : 0] = b.w;
+    } else {
+        const uint2 a = *reinterpret_cast<const uint2 *>(lds_v);
+        r.v[0] = a.x;
+        r.v[NV > 1 ? 1 : 0] = a.y;
+    }
+    r.t = t;
+    return r;
 }
 
 template <int R> struct Ops;
 
 template <> struct Ops<16> {
-    static constexpr int NW = 2;
-    __device__ static __forceinline__ void mac(uint32_t *a, const uint32_t *b, const uint32_t *t)
+    static constexpr int NW = 2, NV = VW16;
+    typedef Tab16 Tab;
+    __device__ static __forceinline__ Tab prep(const uint32_t *t) { return tab_global<NV>(t); }
+    __device__ static __forceinline__ Tab prep_lds(const uint32_t *v, const uint32_t *t) { return tab_lds<NV>(v, t); }
+    __device__ static __forceinline__ void mac(uint32_t *a, const uint32_t *b, const Tab &T)
     {
-        mac16(a[0], a[1], b[0], b[1], t);
+        mac16(a[0], a[1], b[0], b[1], T);
     }
     // packed symbols (two little-endian u16 per dword) -> byte-sliced
     __device__ static __forceinline__ void unpack(uint32_t w0, uint32_t w1, uint32_t *v)
@@ -176,10 +233,13 @@ template <> struct Ops<16> {
 };
 
 template <> struct Ops<8> {
-    static constexpr int NW = 1;
-    __device__ static __forceinline__ void mac(uint32_t *a, const uint32_t *b, const uint32_t *t)
+    static constexpr int NW = 1, NV = VW8;
+    typedef Tab8 Tab;
+    __device__ static __forceinline__ Tab prep(const uint32_t *t) { return tab_global<NV>(t); }
+    __device__ static __forceinline__ Tab prep_lds(const uint32_t *v, const uint32_t *t) { return tab_lds<NV>(v, t); }
+    __device__ static __forceinline__ void mac(uint32_t *a, const uint32_t *b, const Tab &T)
     {
-        mac8(a[0], b[0], t);
+        mac8(a[0], b[0], T);
     }
 };
 

@@ -33,19 +33,18 @@ __device__ __forceinline__ uint8_t *row_ptr(uint8_t *base, uint32_t t, uint64_t 
 // copied to the output when decoding out of place.
 template <int R, int LD>
 __device__ __forceinline__ void dec_load(uint32_t *v, int p, const DevStripe &st, const Lane &ln,
-                                         const uint8_t *__restrict__ mask, const uint32_t *__restrict__ rowtab)
+                                         const uint32_t *__restrict__ bits, const uint32_t *__restrict__ rowtab)
 {
     constexpr int TS = Traits<R>::TS;
-    const int t = point_row(p, st);
-    const bool rcv = t >= 0 && !mask[t >= 0 ? t : 0];
-    const uint32_t tr = rcv ? (uint32_t)t : 0u;
+    const bool rcv = point_bit(bits, p);
+    const uint32_t tr = rcv ? (uint32_t)point_row(p, st) : 0u;
     uint32_t raw[Traits<R>::NW];
     load_chunk<R, LD>(row_ptr(st.in, tr, st.row_bytes), ln.off, ln.act && rcv, ln.nsym, raw);
     if (st.copy_survivors)
         store_chunk<R, LD>(row_ptr(st.out, tr, st.row_bytes), ln.off, ln.act && rcv, ln.nsym, raw);
     zero_vec<R>(v);
     if (rcv)
-        Ops<R>::mac(v, raw, rowtab + (size_t)TS * p);
+        Ops<R>::mac(v, raw, Ops<R>::prep(rowtab + (size_t)TS * p));
     __builtin_amdgcn_sched_barrier(0);
 }
 
@@ -53,15 +52,15 @@ __device__ __forceinline__ void dec_load(uint32_t *v, int p, const DevStripe &st
 // Phi^d[p] / Pi'(omega_p).
 template <int R, int LD>
 __device__ __forceinline__ void dec_store(const uint32_t *v, int p_, const DevStripe &st, const Lane &ln,
-                                          const uint8_t *__restrict__ mask, const uint32_t *__restrict__ rowtab)
+                                          const uint32_t *__restrict__ bits, const uint32_t *__restrict__ rowtab)
 {
     constexpr int TS = Traits<R>::TS;
     const int p = (int)fresh((uint32_t)p_);
-    const int t = point_row(p, st);
-    if (t >= 0 && mask[t]) {
+    if (point_bit(bits + bitmap_words(st.np), p)) {
+        const int t = point_row(p, st);
         uint32_t o[Traits<R>::NW];
         zero_vec<R>(o);
-        Ops<R>::mac(o, v, rowtab + (size_t)TS * p);
+        Ops<R>::mac(o, v, Ops<R>::prep(rowtab + (size_t)TS * p));
         store_chunk<R, LD>(row_ptr(st.out, (uint32_t)t, st.row_bytes), ln.off, ln.act, ln.nsym, o);
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -99,11 +98,11 @@ __device__ __forceinline__ void deriv_regs(uint32_t (*x)[Traits<R>::NW], const T
 #define NB_FUSED_PARAMS                                                                                       \
     FusedArgs a, const uint32_t *__restrict__ p_tw, const uint32_t *__restrict__ p_one,                       \
         const uint32_t *__restrict__ p_B, const uint32_t *__restrict__ p_Binv,                                \
-        const uint8_t *__restrict__ p_masks, const uint32_t *__restrict__ p_rowtabs
+        const uint32_t *__restrict__ p_bits, const uint32_t *__restrict__ p_rowtabs
 
 // ------------------------------------------------------------------ L <= 4
 
-template <int R, int L, int MODE, bool GEN_L, int LD>
+template <int R, int L, int MODE, int SH, int LD>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_small(NB_FUSED_PARAMS)
 {
     constexpr int NW = Traits<R>::NW, NR = 1 << L;
@@ -113,7 +112,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const Lane ln = lane_of<R, LD>(tile - st.tile0, (int)threadIdx.x, st.col0, st.ncols);
     const uint64_t rb = st.row_bytes;
     const Tabs tb = {p_tw, p_one, p_B, p_Binv};
-    const uint8_t *__restrict__ mask = p_masks + st.mask_off;
+    const uint32_t *__restrict__ bits = p_bits + st.bits_off;
     const uint32_t *__restrict__ rowtab = p_rowtabs + st.rowtab_off;
     uint32_t x[NR][NW];
 
@@ -122,9 +121,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         for (int j = 0; j < NR; j++)
             load_chunk<R, LD>(row_ptr(st.in, j, rb), ln.off, ln.act, ln.nsym, x[j]);
         if (MODE == M_FFT)
-            reg_levels<R, L, false, GEN_L>(x, 0, 0, a.l, tb);
+            reg_levels<R, L, false, SH, true>(x, 0, 0, a.l, tb);
         else if (MODE == M_IFFT)
-            reg_levels<R, L, true, GEN_L>(x, 0, 0, a.l, tb);
+            reg_levels<R, L, true, SH, true>(x, 0, 0, a.l, tb);
         else
             deriv_regs<R, L>(x, tb);
 #pragma unroll
@@ -136,7 +135,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #pragma unroll
         for (int j = 0; j < NR; j++)
             load_chunk<R, LD>(row_ptr(st.in, j, rb), ln.off, ln.act && j < st.k, ln.nsym, x[j]);
-        reg_levels<R, L, true, false>(x, 0, 0, 0u, tb);
+        reg_levels<R, L, true, SH_ZERO, true>(x, 0, 0, 0u, tb);
         const int nblocks = st.np / st.kp;
         const int npar = st.n - st.k;
         for (int blk = 1; blk < nblocks; blk++) {
@@ -146,7 +145,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #pragma unroll
                 for (int w = 0; w < NW; w++)
                     y[j][w] = x[j][w];
-            reg_levels<R, L, false, false>(y, 0, 0, (uint32_t)(blk * NR), tb);
+            reg_levels<R, L, false, SH_ALIGNED, true>(y, 0, 0, (uint32_t)(blk * NR), tb);
 #pragma unroll
             for (int j = 0; j < NR; j++) {
                 const int t = (blk - 1) * NR + j;
@@ -157,19 +156,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     } else {  // M_DEC with n' = NR
 #pragma unroll
         for (int p = 0; p < NR; p++)
-            dec_load<R, LD>(x[p], p, st, ln, mask, rowtab);
-        reg_levels<R, L, true, false>(x, 0, 0, 0u, tb);     // step 3
+            dec_load<R, LD>(x[p], p, st, ln, bits, rowtab);
+        reg_levels<R, L, true, SH_ZERO, true>(x, 0, 0, 0u, tb);     // step 3
         deriv_regs<R, L>(x, tb);                             // step 4
-        reg_levels<R, L, false, false>(x, 0, 0, 0u, tb);    // step 5
+        reg_levels<R, L, false, SH_ZERO, true>(x, 0, 0, 0u, tb);    // step 5
 #pragma unroll
         for (int p = 0; p < NR; p++)                         // step 6
-            dec_store<R, LD>(x[p], p, st, ln, mask, rowtab);
+            dec_store<R, LD>(x[p], p, st, ln, bits, rowtab);
     }
 }
 
 // ------------------------------------------------------------------ 5 <= L <= 8
 
-template <int R, int L, int MODE, bool GEN_L, int LD>
+template <int R, int L, int MODE, int SH, int LD>
 __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4))) void k_tiled(NB_FUSED_PARAMS)
 {
     constexpr int NW = Traits<R>::NW, TS = Traits<R>::TS;
@@ -186,7 +185,7 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
     const Lane ln = lane_of<R, LD>(tile - st.tile0, lane, st.col0, st.ncols);
     const uint64_t rb = st.row_bytes;
     const Tabs tb = {p_tw, p_one, p_B, p_Binv};
-    const uint8_t *__restrict__ mask = p_masks + st.mask_off;
+    const uint32_t *__restrict__ bits = p_bits + st.bits_off;
     const uint32_t *__restrict__ rowtab = p_rowtabs + st.rowtab_off;
 
     auto lds_put = [&](int row, const uint32_t *v) {
@@ -218,7 +217,7 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
             for (int j = 0; j < NR2; j++)
                 load_chunk<R, LD>(row_ptr(st.in, r0 + 16 * j, rb), ln.off, ln.act, ln.nsym, y[u][j]);
-            reg_levels<R, L2, false, GEN_L>(y[u], (uint32_t)r0, 4, a.l, tb);
+            reg_levels<R, L2, false, SH, true>(y[u], (uint32_t)r0, 4, a.l, tb);
 #pragma unroll
             for (int j = 0; j < NR2; j++)
                 lds_put(r0 + 16 * j, y[u][j]);
@@ -227,7 +226,7 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
         for (int j = 0; j < 16; j++)
             lds_get(16 * g + j, x[j]);
-        reg_levels<R, 4, false, GEN_L>(x, (uint32_t)(16 * g), 0, a.l, tb);
+        reg_levels<R, 4, false, SH, false>(x, (uint32_t)(16 * g), 0, a.l, tb);
 #pragma unroll
         for (int j = 0; j < 16; j++)
             store_chunk<R, LD>(row_ptr(st.out, fresh(16 * g + j), rb), ln.off, ln.act, ln.nsym, x[j]);
@@ -291,10 +290,11 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
             // rows k .. k'-1 are the zero padding of a shortened message
             load_chunk<R, LD>(row_ptr(st.in, p, rb), ln.off, ln.act && p < st.k, ln.nsym, x[j]);
         } else {
-            dec_load<R, LD>(x[j], p, st, ln, mask, rowtab);
+            dec_load<R, LD>(x[j], p, st, ln, bits, rowtab);
         }
     }
-    reg_levels<R, 4, true, GEN_L>(x, (uint32_t)(16 * g), 0, MODE == M_IFFT ? a.l : 0u, tb);
+    reg_levels<R, 4, true, (MODE == M_IFFT ? SH : SH_ZERO), false>(x, (uint32_t)(16 * g), 0,
+                                                                   MODE == M_IFFT ? a.l : 0u, tb);
 #pragma unroll
     for (int j = 0; j < 16; j++)
         lds_put(16 * g + j, x[j]);
@@ -307,7 +307,8 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
         for (int j = 0; j < NR2; j++)
             lds_get(r0 + 16 * j, y[u][j]);
-        reg_levels<R, L2, true, GEN_L>(y[u], (uint32_t)r0, 4, MODE == M_IFFT ? a.l : 0u, tb);
+        reg_levels<R, L2, true, (MODE == M_IFFT ? SH : SH_ZERO), true>(y[u], (uint32_t)r0, 4,
+                                                                      MODE == M_IFFT ? a.l : 0u, tb);
     }
 
     if (MODE == M_IFFT) {
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
                     for (int w = 0; w < NW; w++)
                         z[j][w] = y[u][j][w];
-                reg_levels<R, L2, false, false>(z, (uint32_t)r0, 4, lsh, tb);
+                reg_levels<R, L2, false, SH_ALIGNED, true>(z, (uint32_t)r0, 4, lsh, tb);
 #pragma unroll
                 for (int j = 0; j < NR2; j++)
                     lds_put(r0 + 16 * j, z[j]);
@@ -346,7 +347,7 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
             for (int j = 0; j < 16; j++)
                 lds_get(16 * g + j, x[j]);
-            reg_levels<R, 4, false, false>(x, (uint32_t)(16 * g), 0, lsh, tb);
+            reg_levels<R, 4, false, SH_ALIGNED, false>(x, (uint32_t)(16 * g), 0, lsh, tb);
 #pragma unroll
             for (int j = 0; j < 16; j++) {
                 const int t = (blk - 1) * (1 << L) + 16 * g + j;
@@ -409,7 +410,7 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
             if (p)
                 scale<R>(z[u][j], tb.Binv + (size_t)TS * p);
         }
-        reg_levels<R, L2, false, false>(z[u], (uint32_t)r0, 4, 0u, tb);
+        reg_levels<R, L2, false, SH_ZERO, true>(z[u], (uint32_t)r0, 4, 0u, tb);
 #pragma unroll
         for (int j = 0; j < NR2; j++)
             lds_put(r0 + 16 * j, z[u][j]);
@@ -418,81 +419,86 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
     for (int j = 0; j < 16; j++)
         lds_get(16 * g + j, x[j]);
-    reg_levels<R, 4, false, false>(x, (uint32_t)(16 * g), 0, 0u, tb);
+    reg_levels<R, 4, false, SH_ZERO, false>(x, (uint32_t)(16 * g), 0, 0u, tb);
 #pragma unroll
     for (int j = 0; j < 16; j++)
-        dec_store<R, LD>(x[j], 16 * g + j, st, ln, mask, rowtab);
+        dec_store<R, LD>(x[j], 16 * g + j, st, ln, bits, rowtab);
 }
 
 // ------------------------------------------------------------------ launchers
 
-template <int R, int L, int MODE, bool GEN_L, int LD>
+template <int R, int L, int MODE, int SH, int LD>
 static hipError_t launch_one(const FusedArgs &a, const KPtrs &k, int ntiles, hipStream_t stream)
 {
     if (ntiles <= 0)
         return hipSuccess;
     if (L <= 4) {
-        hipLaunchKernelGGL((k_small<R, (L <= 4 ? L : 4), MODE, GEN_L, LD>), dim3(ntiles), dim3(64), 0, stream, a,
-                           k.tw, k.one, k.B, k.Binv, k.masks, k.rowtabs);
+        hipLaunchKernelGGL((k_small<R, (L <= 4 ? L : 4), MODE, SH, LD>), dim3(ntiles), dim3(64), 0, stream, a,
+                           k.tw, k.one, k.B, k.Binv, k.bits, k.rowtabs);
     } else {
         constexpr int LL = L > 4 ? L : 5;
         const size_t lds = (size_t)(1u << LL) * 64 * Traits<R>::NW * 4;
-        hipLaunchKernelGGL((k_tiled<R, LL, MODE, GEN_L, LD>), dim3(ntiles), dim3(64 << (LL - 4)), lds, stream, a,
-                           k.tw, k.one, k.B, k.Binv, k.masks, k.rowtabs);
+        hipLaunchKernelGGL((k_tiled<R, LL, MODE, SH, LD>), dim3(ntiles), dim3(64 << (LL - 4)), lds, stream, a,
+                           k.tw, k.one, k.B, k.Binv, k.bits, k.rowtabs);
     }
     return hipGetLastError();
 }
 
-template <int R, int L, int MODE, bool GEN_L, int LD>
+template <int R, int L, int MODE, int SH, int LD>
 static hipError_t prep_one()
 {
     if (L > 4) {
         constexpr int LL = L > 4 ? L : 5;
         const int lds = (int)((1u << LL) * 64 * Traits<R>::NW * 4);
-        return hipFuncSetAttribute((const void *)k_tiled<R, LL, MODE, GEN_L, LD>,
+        return hipFuncSetAttribute((const void *)k_tiled<R, LL, MODE, SH, LD>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     }
     return hipSuccess;
 }
 
-template <int R, int MODE, bool GEN_L, int LD>
+template <int R, int MODE, int SH, int LD>
 static hipError_t launch_L(int L, const FusedArgs &a, const KPtrs &k, int ntiles, hipStream_t s)
 {
     switch (L) {
-    case 0: return launch_one<R, 0, MODE, GEN_L, LD>(a, k, ntiles, s);
-    case 1: return launch_one<R, 1, MODE, GEN_L, LD>(a, k, ntiles, s);
-    case 2: return launch_one<R, 2, MODE, GEN_L, LD>(a, k, ntiles, s);
-    case 3: return launch_one<R, 3, MODE, GEN_L, LD>(a, k, ntiles, s);
-    case 4: return launch_one<R, 4, MODE, GEN_L, LD>(a, k, ntiles, s);
-    case 5: return launch_one<R, 5, MODE, GEN_L, LD>(a, k, ntiles, s);
-    case 6: return launch_one<R, 6, MODE, GEN_L, LD>(a, k, ntiles, s);
-    case 7: return launch_one<R, 7, MODE, GEN_L, LD>(a, k, ntiles, s);
-    case 8: return launch_one<R, 8, MODE, GEN_L, LD>(a, k, ntiles, s);
+    case 0: return launch_one<R, 0, MODE, SH, LD>(a, k, ntiles, s);
+    case 1: return launch_one<R, 1, MODE, SH, LD>(a, k, ntiles, s);
+    case 2: return launch_one<R, 2, MODE, SH, LD>(a, k, ntiles, s);
+    case 3: return launch_one<R, 3, MODE, SH, LD>(a, k, ntiles, s);
+    case 4: return launch_one<R, 4, MODE, SH, LD>(a, k, ntiles, s);
+    case 5: return launch_one<R, 5, MODE, SH, LD>(a, k, ntiles, s);
+    case 6: return launch_one<R, 6, MODE, SH, LD>(a, k, ntiles, s);
+    case 7: return launch_one<R, 7, MODE, SH, LD>(a, k, ntiles, s);
+    case 8: return launch_one<R, 8, MODE, SH, LD>(a, k, ntiles, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <int R, int MODE, bool GEN_L, int LD>
+template <int R, int MODE, int SH, int LD>
 static hipError_t prep_L()
 {
     hipError_t e = hipSuccess, f;
-    if ((f = prep_one<R, 5, MODE, GEN_L, LD>()) != hipSuccess) e = f;
-    if ((f = prep_one<R, 6, MODE, GEN_L, LD>()) != hipSuccess) e = f;
-    if ((f = prep_one<R, 7, MODE, GEN_L, LD>()) != hipSuccess) e = f;
-    if ((f = prep_one<R, 8, MODE, GEN_L, LD>()) != hipSuccess) e = f;
+    if ((f = prep_one<R, 5, MODE, SH, LD>()) != hipSuccess) e = f;
+    if ((f = prep_one<R, 6, MODE, SH, LD>()) != hipSuccess) e = f;
+    if ((f = prep_one<R, 7, MODE, SH, LD>()) != hipSuccess) e = f;
+    if ((f = prep_one<R, 8, MODE, SH, LD>()) != hipSuccess) e = f;
     return e;
 }
 
 template <int R, int LD>
-static hipError_t launch_ld(int mode, bool gen_l, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
-                            hipStream_t s)
+static hipError_t launch_ld(int mode, int sh, int L, const FusedArgs &a, const KPtrs &k, int ntiles, hipStream_t s)
 {
     switch (mode) {
-    case M_FFT: return gen_l ? launch_L<R, M_FFT, true, LD>(L, a, k, ntiles, s) : launch_L<R, M_FFT, false, LD>(L, a, k, ntiles, s);
-    case M_IFFT: return gen_l ? launch_L<R, M_IFFT, true, LD>(L, a, k, ntiles, s) : launch_L<R, M_IFFT, false, LD>(L, a, k, ntiles, s);
-    case M_DERIV: return launch_L<R, M_DERIV, false, LD>(L, a, k, ntiles, s);
-    case M_ENC: return launch_L<R, M_ENC, false, LD>(L, a, k, ntiles, s);
-    case M_DEC: return launch_L<R, M_DEC, false, LD>(L, a, k, ntiles, s);
+    case M_FFT:
+        return sh == SH_ZERO ? launch_L<R, M_FFT, SH_ZERO, LD>(L, a, k, ntiles, s)
+             : sh == SH_ALIGNED ? launch_L<R, M_FFT, SH_ALIGNED, LD>(L, a, k, ntiles, s)
+                                : launch_L<R, M_FFT, SH_GENERAL, LD>(L, a, k, ntiles, s);
+    case M_IFFT:
+        return sh == SH_ZERO ? launch_L<R, M_IFFT, SH_ZERO, LD>(L, a, k, ntiles, s)
+             : sh == SH_ALIGNED ? launch_L<R, M_IFFT, SH_ALIGNED, LD>(L, a, k, ntiles, s)
+                                : launch_L<R, M_IFFT, SH_GENERAL, LD>(L, a, k, ntiles, s);
+    case M_DERIV: return launch_L<R, M_DERIV, SH_ZERO, LD>(L, a, k, ntiles, s);
+    case M_ENC: return launch_L<R, M_ENC, SH_ZERO, LD>(L, a, k, ntiles, s);
+    case M_DEC: return launch_L<R, M_DEC, SH_ZERO, LD>(L, a, k, ntiles, s);
     }
     return hipErrorInvalidValue;
 }
@@ -501,13 +507,13 @@ template <int R>
 static hipError_t fused_prepare_r()
 {
     hipError_t e = hipSuccess, f;
-#define NB_PREP(M, G, LD) if ((f = prep_L<R, M, G, LD>()) != hipSuccess) e = f;
-    NB_PREP(M_FFT, false, LD_VEC) NB_PREP(M_FFT, true, LD_VEC) NB_PREP(M_IFFT, false, LD_VEC)
-    NB_PREP(M_IFFT, true, LD_VEC) NB_PREP(M_DERIV, false, LD_VEC) NB_PREP(M_ENC, false, LD_VEC)
-    NB_PREP(M_DEC, false, LD_VEC)
-    NB_PREP(M_FFT, false, LD_SYM) NB_PREP(M_FFT, true, LD_SYM) NB_PREP(M_IFFT, false, LD_SYM)
-    NB_PREP(M_IFFT, true, LD_SYM) NB_PREP(M_DERIV, false, LD_SYM) NB_PREP(M_ENC, false, LD_SYM)
-    NB_PREP(M_DEC, false, LD_SYM)
+#define NB_PREP(M, SHM, LD) if ((f = prep_L<R, M, SHM, LD>()) != hipSuccess) e = f;
+    NB_PREP(M_FFT, SH_ZERO, LD_VEC) NB_PREP(M_FFT, SH_ALIGNED, LD_VEC) NB_PREP(M_FFT, SH_GENERAL, LD_VEC)
+    NB_PREP(M_IFFT, SH_ZERO, LD_VEC) NB_PREP(M_IFFT, SH_ALIGNED, LD_VEC) NB_PREP(M_IFFT, SH_GENERAL, LD_VEC)
+    NB_PREP(M_DERIV, SH_ZERO, LD_VEC) NB_PREP(M_ENC, SH_ZERO, LD_VEC) NB_PREP(M_DEC, SH_ZERO, LD_VEC)
+    NB_PREP(M_FFT, SH_ZERO, LD_SYM) NB_PREP(M_FFT, SH_ALIGNED, LD_SYM) NB_PREP(M_FFT, SH_GENERAL, LD_SYM)
+    NB_PREP(M_IFFT, SH_ZERO, LD_SYM) NB_PREP(M_IFFT, SH_ALIGNED, LD_SYM) NB_PREP(M_IFFT, SH_GENERAL, LD_SYM)
+    NB_PREP(M_DERIV, SH_ZERO, LD_SYM) NB_PREP(M_ENC, SH_ZERO, LD_SYM) NB_PREP(M_DEC, SH_ZERO, LD_SYM)
 #undef NB_PREP
     return e;
 }

@@ -157,15 +157,6 @@ __global__ void k_init_fwhtL(int r, const uint32_t *__restrict__ basis, const ui
 
 // ---------------------------------------------------------------- locator (decode step 1)
 
-__device__ __forceinline__ int loc_point_row(int p, const DevStripe &st)
-{
-    if (p < st.k)
-        return p;
-    if (p < st.kp)
-        return -1;
-    const int t = st.k + (p - st.kp);
-    return t < st.n ? t : -2;
-}
 
 // One block per stripe.  Log Pi(omega_p) (p not erased) and Log Pi'(omega_p)
 // (p erased) for every point p < N of the mother code are the XOR convolution
@@ -174,7 +165,7 @@ __device__ __forceinline__ int loc_point_row(int p, const DevStripe &st)
 // division by N is the inverse transform's normalisation, 2^{r - lg N} mod
 // 2^r - 1).  The stripe's per-point scale factors, Pi(omega_p) for survivors
 // and 1 / Pi'(omega_p) for erasures, are written as perm tables.
-__global__ void k_locator(LocatorArgs a, const uint8_t *__restrict__ p_masks, uint32_t *__restrict__ p_rowtabs,
+__global__ void k_locator(LocatorArgs a, const uint32_t *__restrict__ p_bits, uint32_t *__restrict__ p_rowtabs,
                           const uint32_t *__restrict__ fwht_L, const uint32_t *__restrict__ expt)
 {
     extern __shared__ uint16_t v16[];
@@ -182,13 +173,13 @@ __global__ void k_locator(LocatorArgs a, const uint8_t *__restrict__ p_masks, ui
     const int r = a.r;
     const int N = st.np;
     const uint32_t M = (1u << r) - 1u;
-    const uint8_t *__restrict__ mask = p_masks + st.mask_off;
+    const uint32_t *__restrict__ rxb = p_bits + st.bits_off;   // received points
     int lgN = 0;
     while ((1 << lgN) < N)
         lgN++;
     for (int p = threadIdx.x; p < N; p += blockDim.x) {
-        const int t = loc_point_row(p, st);
-        const bool er = t >= 0 ? mask[t] != 0 : t == -2;
+        // erased in the mother code: neither received nor a virtual zero
+        const bool er = !((rxb[p >> 5] >> (p & 31)) & 1u) && !(p >= st.k && p < st.kp);
         v16[p] = er ? 1 : 0;
     }
     __syncthreads();
@@ -205,8 +196,7 @@ __global__ void k_locator(LocatorArgs a, const uint8_t *__restrict__ p_masks, ui
         uint32_t lg = v16[p];
         if (sh)
             lg = ((lg << sh) | (lg >> (r - sh))) & M;
-        const int t = loc_point_row(p, st);
-        const bool er = t >= 0 ? mask[t] != 0 : t == -2;
+        const bool er = !((rxb[p >> 5] >> (p & 31)) & 1u) && !(p >= st.k && p < st.kp);
         const uint32_t e = er ? (M - lg) % M : lg;
         uint32_t tab[TAB16];
         build_perm_table(expt[e], r, tab);
@@ -249,7 +239,7 @@ hipError_t locator_launch(const LocatorArgs &a, const KPtrs &k, const uint32_t *
 {
     if (nstripes <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_locator, dim3(nstripes), dim3(1024), (size_t)max_np * 2, s, a, k.masks,
+    hipLaunchKernelGGL(k_locator, dim3(nstripes), dim3(1024), (size_t)max_np * 2, s, a, k.bits,
                        (uint32_t *)k.rowtabs, fwht_L, expt);
     return hipGetLastError();
 }

@@ -25,7 +25,7 @@ struct Tabs {
 // separate parameter.
 struct KPtrs {
     const uint32_t *tw, *one, *B, *Binv;
-    const uint8_t *masks;      // decode: erasure masks, stripe s at DevStripe::mask_off
+    const uint32_t *bits;      // decode: point bitmaps, stripe s at DevStripe::bits_off
     const uint32_t *rowtabs;   // decode: locator perm tables, stripe s at DevStripe::rowtab_off
 };
 
@@ -34,7 +34,9 @@ struct KPtrs {
 struct DevStripe {
     const uint8_t *in;        // encode: k message rows; decode: n shard rows; xform: data
     uint8_t *out;             // encode: n - k parity rows; decode: n rows; xform: data
-    uint64_t mask_off;        // decode: byte offset of the n-byte mask (nonzero = erased)
+    uint64_t bits_off;        // decode: dword offset of the point bitmaps: W = ceil(n'/32)
+                              // words "received" (point has a surviving stored row),
+                              // then W words "erased" (point has an erased stored row)
     uint64_t rowtab_off;      // decode: dword offset of the n' per-point perm tables
     uint64_t row_bytes;
     int32_t n, k, kp, np;     // stored shape and mother shape

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(64) void k_pass(PassArgs a, const uint32_t *__restr
         if (a.pre_B)
             scale<R>(x[j], p_B + (size_t)TS * p);
     }
-    reg_levels<R, T, INV, GEN_L>(x, base, a.lo, a.l, tb);
+    reg_levels<R, T, INV, (GEN_L ? SH_GENERAL : SH_ALIGNED), false>(x, base, a.lo, a.l, tb);
 #pragma unroll
     for (int j = 0; j < NR; j++) {
         const uint32_t p = fresh(base + ((uint32_t)j << a.lo));
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(64) void k_dpart(DerivPassArgs a, const uint32_t *_
 // Decode step 2 for the multi-pass decoder: A[p] = rx * Pi(omega_p) for
 // received points, 0 otherwise; surviving rows copied when out != in.
 template <int R, int LD>
-__global__ __launch_bounds__(64) void k_dec_gather(DecodeIOArgs a, const uint8_t *__restrict__ p_masks,
+__global__ __launch_bounds__(64) void k_dec_gather(DecodeIOArgs a, const uint32_t *__restrict__ p_bits,
                                                    const uint32_t *__restrict__ p_rowtabs)
 {
     constexpr int NW = Traits<R>::NW, TS = Traits<R>::TS;
@@ -104,17 +104,17 @@ __global__ __launch_bounds__(64) void k_dec_gather(DecodeIOArgs a, const uint8_t
     const int ct = (int)(blockIdx.x % (uint32_t)a.nct);
     const DevStripe &st = a.st;
     const Lane ln = lane_of<R, LD>(ct, (int)threadIdx.x, st.col0, st.ncols);
-    const uint8_t *__restrict__ mask = p_masks + st.mask_off;
+    const uint32_t *__restrict__ bits = p_bits + st.bits_off;
     const uint32_t *__restrict__ rowtab = p_rowtabs + st.rowtab_off;
     uint32_t v[NW];
     zero_vec<R>(v);
-    const int t = point_row(p, st);
-    if (t >= 0 && !mask[t]) {
+    if (point_bit(bits, p)) {
+        const int t = point_row(p, st);
         uint32_t raw[NW];
         load_chunk<R, LD>(prow(st.in, t, st.row_bytes), ln.off, ln.act, ln.nsym, raw);
         if (st.copy_survivors)
             store_chunk<R, LD>(prow(st.out, t, st.row_bytes), ln.off, ln.act, ln.nsym, raw);
-        Ops<R>::mac(v, raw, rowtab + (size_t)TS * p);
+        Ops<R>::mac(v, raw, Ops<R>::prep(rowtab + (size_t)TS * p));
     }
     store_chunk<R, LD>(prow(a.A, p, st.row_bytes), ln.off, ln.act, ln.nsym, v);
 }
@@ -122,23 +122,23 @@ __global__ __launch_bounds__(64) void k_dec_gather(DecodeIOArgs a, const uint8_t
 // Decode step 6 for the multi-pass decoder: erased stored row t of point p
 // gets A[p] / Pi'(omega_p).
 template <int R, int LD>
-__global__ __launch_bounds__(64) void k_dec_scatter(DecodeIOArgs a, const uint8_t *__restrict__ p_masks,
+__global__ __launch_bounds__(64) void k_dec_scatter(DecodeIOArgs a, const uint32_t *__restrict__ p_bits,
                                                     const uint32_t *__restrict__ p_rowtabs)
 {
     constexpr int NW = Traits<R>::NW, TS = Traits<R>::TS;
     const int t = (int)(blockIdx.x / (uint32_t)a.nct);
     const int ct = (int)(blockIdx.x % (uint32_t)a.nct);
     const DevStripe &st = a.st;
-    const uint8_t *__restrict__ mask = p_masks + st.mask_off;
+    const uint32_t *__restrict__ bits = p_bits + st.bits_off;
     const uint32_t *__restrict__ rowtab = p_rowtabs + st.rowtab_off;
-    if (!mask[t])
+    const int p = t < st.k ? t : st.kp + (t - st.k);
+    if (!point_bit(bits + bitmap_words(st.np), p))
         return;
     const Lane ln = lane_of<R, LD>(ct, (int)threadIdx.x, st.col0, st.ncols);
-    const int p = t < st.k ? t : st.kp + (t - st.k);
     uint32_t v[NW], o[NW];
     load_chunk<R, LD>(prow(a.A, p, st.row_bytes), ln.off, ln.act, ln.nsym, v);
     zero_vec<R>(o);
-    Ops<R>::mac(o, v, rowtab + (size_t)TS * p);
+    Ops<R>::mac(o, v, Ops<R>::prep(rowtab + (size_t)TS * p));
     store_chunk<R, LD>(prow(st.out, t, st.row_bytes), ln.off, ln.act, ln.nsym, o);
 }
 
@@ -206,9 +206,9 @@ template <int R, int LD>
 static void dec_io_r(bool scatter, const DecodeIOArgs &a, const KPtrs &k, uint32_t nblocks, hipStream_t s)
 {
     if (scatter)
-        hipLaunchKernelGGL((k_dec_scatter<R, LD>), dim3(nblocks), dim3(64), 0, s, a, k.masks, k.rowtabs);
+        hipLaunchKernelGGL((k_dec_scatter<R, LD>), dim3(nblocks), dim3(64), 0, s, a, k.bits, k.rowtabs);
     else
-        hipLaunchKernelGGL((k_dec_gather<R, LD>), dim3(nblocks), dim3(64), 0, s, a, k.masks, k.rowtabs);
+        hipLaunchKernelGGL((k_dec_gather<R, LD>), dim3(nblocks), dim3(64), 0, s, a, k.bits, k.rowtabs);
 }
 
 hipError_t dec_io_launch(int r, int ld, bool scatter, const DecodeIOArgs &a, const KPtrs &k, uint32_t nblocks,

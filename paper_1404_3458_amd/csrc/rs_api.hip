@@ -23,9 +23,9 @@ hipError_t locator_launch(const LocatorArgs &a, const KPtrs &k, const uint32_t *
                           int nstripes, int max_np, hipStream_t s);
 hipError_t fused_prepare_16();
 hipError_t fused_prepare_8();
-hipError_t fused_launch_16(int mode, bool gen_l, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
+hipError_t fused_launch_16(int mode, int sh, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
                            hipStream_t s);
-hipError_t fused_launch_8(int mode, bool gen_l, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
+hipError_t fused_launch_8(int mode, int sh, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
                           hipStream_t s);
 hipError_t pass_launch(int r, int ld, int T, bool inv, bool gen_l, const PassArgs &a, const KPtrs &k,
                        uint32_t nblocks, hipStream_t s);
@@ -495,11 +495,12 @@ int decode_large(rs_ctx *ctx, Scratch *sc, const Plan &pl, const DevStripe &dsl,
     return rc;
 }
 
-hipError_t fused_launch(int r, int mode, bool gen_l, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
+// sh: 0 = shift zero, 1 = shift a nonzero multiple of h, 2 = any other shift
+hipError_t fused_launch(int r, int mode, int sh, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
                         hipStream_t s)
 {
-    return r == 16 ? fused_launch_16(mode, gen_l, ld, L, a, k, ntiles, s)
-                   : fused_launch_8(mode, gen_l, ld, L, a, k, ntiles, s);
+    return r == 16 ? fused_launch_16(mode, sh, ld, L, a, k, ntiles, s)
+                   : fused_launch_8(mode, sh, ld, L, a, k, ntiles, s);
 }
 
 // ------------------------------------------------------------------ codec driver
@@ -558,14 +559,14 @@ int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, in
     const int m = (int)act.size();
     const int ts = ctx->r == 16 ? TAB16 : TAB8;
 
-    // Per-stripe device data: masks and locator tables (decode).
-    size_t mask_bytes = 0, rt_dwords = 0;
+    // Per-stripe device data (decode): point bitmaps and locator tables.
+    size_t bit_words = 0, rt_dwords = 0;
     int max_np = 1;
     for (int q = 0; q < m; q++) {
         Plan &p = plans[act[q]];
         if (decode) {
-            p.ds.mask_off = mask_bytes;
-            mask_bytes += (size_t)p.ds.n;
+            p.ds.bits_off = bit_words;
+            bit_words += 2 * (size_t)((p.ds.np + 31) / 32);
             p.ds.rowtab_off = rt_dwords;
             rt_dwords += (size_t)p.ds.np * ts;
             max_np = std::max(max_np, p.ds.np);
@@ -603,10 +604,10 @@ int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, in
     for (int q = 0; decode && q < m; q++)
         lds_[q] = plans[act[q]].ds;
 
-    // Device arena: [entries | locator stripes | masks | locator tables]
+    // Device arena: [entries | locator stripes | point bitmaps | locator tables]
     const size_t off_loc = align_up(sizeof(DevStripe) * ne, 256);
-    const size_t off_masks = align_up(off_loc + sizeof(DevStripe) * lds_.size(), 256);
-    const size_t off_rt = align_up(off_masks + mask_bytes, 256);
+    const size_t off_bits = align_up(off_loc + sizeof(DevStripe) * lds_.size(), 256);
+    const size_t off_rt = align_up(off_bits + bit_words * 4, 256);
     const size_t host_bytes = off_rt;
     const size_t dev_bytes = off_rt + rt_dwords * 4;
     int rc = ensure_dev(sc, &sc->dev, &sc->dev_cap, dev_bytes);
@@ -618,16 +619,32 @@ int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, in
         std::memcpy(host.data(), eds.data(), sizeof(DevStripe) * ne);
     if (decode) {
         std::memcpy(host.data() + off_loc, lds_.data(), sizeof(DevStripe) * m);
+        uint32_t *bits = (uint32_t *)(host.data() + off_bits);
         for (int q = 0; q < m; q++) {
             const Plan &p = plans[act[q]];
-            std::memcpy(host.data() + off_masks + p.ds.mask_off, masks + p.mask_src, (size_t)p.ds.n);
+            const uint8_t *mk = masks + p.mask_src;
+            const int W = (p.ds.np + 31) / 32;
+            uint32_t *rx = bits + p.ds.bits_off, *er = rx + W;
+            for (int pt = 0; pt < p.ds.np; pt++) {
+                int t = -1;
+                if (pt < p.ds.k)
+                    t = pt;
+                else if (pt >= p.ds.kp && pt - p.ds.kp < p.ds.n - p.ds.k)
+                    t = p.ds.k + (pt - p.ds.kp);
+                if (t < 0)
+                    continue;
+                if (mk[t])
+                    er[pt >> 5] |= 1u << (pt & 31);
+                else
+                    rx[pt >> 5] |= 1u << (pt & 31);
+            }
         }
     }
     rc = stage_upload(sc, host.data(), host_bytes, dev);
     if (rc)
         return rc;
     KPtrs kp = ctx->kp;
-    kp.masks = dev + off_masks;
+    kp.bits = (const uint32_t *)(dev + off_bits);
     kp.rowtabs = (const uint32_t *)(dev + off_rt);
 
     if (decode) {
@@ -649,7 +666,7 @@ int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, in
         fa.stripes = d_ents + j;
         fa.nstripes = e - j;
         fa.l = 0;
-        if (dev_err(ctx, fused_launch(ctx->r, decode ? MODE_DEC : MODE_ENC, false, ents[j].cp.ld,
+        if (dev_err(ctx, fused_launch(ctx->r, decode ? MODE_DEC : MODE_ENC, 0, ents[j].cp.ld,
                                       plans[ents[j].plan].L, fa, kp, tiles, stream)))
             return RS_EDEVICE;
         j = e;
@@ -722,7 +739,8 @@ int run_xform(rs_ctx *ctx, int mode, int h, uint32_t l, void *data, size_t rb, h
             fa.stripes = (const DevStripe *)sc->dev + i;
             fa.nstripes = 1;
             fa.l = l;
-            if (dev_err(ctx, fused_launch(ctx->r, mode, gen_l, parts[i].ld, L, fa, ctx->kp, parts[i].ntiles, stream)))
+            const int sh = gen_l ? 2 : (l == 0 ? 0 : 1);
+            if (dev_err(ctx, fused_launch(ctx->r, mode, sh, parts[i].ld, L, fa, ctx->kp, parts[i].ntiles, stream)))
                 return RS_EDEVICE;
         }
         return RS_OK;
@@ -848,7 +866,7 @@ __attribute__((visibility("default"))) int rs_init(int r, const uint32_t *basis,
     ctx->kp.one = ctx->d_one_tab;
     ctx->kp.B = ctx->d_B_tab;
     ctx->kp.Binv = ctx->d_Binv_tab;
-    ctx->kp.masks = nullptr;
+    ctx->kp.bits = nullptr;
     ctx->kp.rowtabs = nullptr;
     *out = ctx;
     return RS_OK;
