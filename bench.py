@@ -116,6 +116,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-per-stripe", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy --steps times (the reference "
+                         "kernel that scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no collectives or sharding); "
@@ -126,6 +129,16 @@ def main():
     import torch
 
     from paper_1404_3458_amd import rs, synth
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": 1 << 30, "launches": args.steps}))
+        return
 
     cfg = dict(CONFIGS[args.config])
     cfg["id"] = {"c1": 1, "c2": 2, "c3": 3}[args.config]
@@ -176,13 +189,18 @@ def main():
 
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
+    host_ms = np.zeros((args.steps, 2))
     t0 = time.perf_counter()
     for i in range(args.steps):
         ev[i][0].record(stream)
+        h0 = time.perf_counter()
         codec.encode_batch(enc_items)
+        h1 = time.perf_counter()
         ev[i][1].record(stream)
         codec.decode_batch(dec_items)
+        h2 = time.perf_counter()
         ev[i][2].record(stream)
+        host_ms[i] = ((h1 - h0) * 1e3, (h2 - h1) * 1e3)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     enc_ms = np.array([ev[i][0].elapsed_time(ev[i][1]) for i in range(args.steps)])
@@ -212,6 +230,10 @@ def main():
         "decode_hbm_frac": round(algo_bytes / (dec_ms.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "step_ms_p50": round(float(np.percentile(step_ms, 50)), 4),
         "step_ms_p99": round(float(np.percentile(step_ms, 99)), 4),
+        "step_ms_max": round(float(step_ms.max()), 4),
+        "slowest_step": int(step_ms.argmax()),
+        "host_call_ms_max": [round(float(host_ms[:, 0].max()), 3), round(float(host_ms[:, 1].max()), 3)],
+        "host_call_ms_p50": [round(float(np.median(host_ms[:, 0])), 3), round(float(np.median(host_ms[:, 1])), 3)],
         "msg_over_hbm_peak": round(value / HBM_PEAK_GBS, 4),
     }
 

@@ -268,6 +268,36 @@ __device__ __forceinline__ uint32_t fresh(uint32_t v)
     return v;
 }
 
+// Marks the values of v as computed at this point of the program: a later
+// fresh() (from which table addresses are derived) is ordered after it, so
+// a table fetch placed after the marker cannot be issued before the work
+// that produced v, which bounds how many tables are in flight.
+template <int NW>
+__device__ __forceinline__ void pin(const uint32_t *v)
+{
+    if (NW == 2)
+        asm volatile("" ::"v"(v[0]), "v"(v[NW - 1]));
+    else
+        asm volatile("" ::"v"(v[0]));
+}
+
+// Runs work(k, table_k) for k < N with table k + 1 fetched before work k, so
+// that one table fetch is in flight while a block is computed; work ends
+// with pin() on what it produced.
+template <class Tab, int N, class F, class W>
+__device__ __forceinline__ void pipelined(const F &fetch, const W &work)
+{
+    Tab cur = fetch(0);
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        Tab nxt = cur;
+        if (k + 1 < N)
+            nxt = fetch(k + 1);
+        work(k, cur);
+        cur = nxt;
+    }
+}
+
 // Load this lane's chunk (byte offset `off` in the row) into byte-sliced
 // registers; inactive lanes and symbols >= nsym read zero.
 template <int R, int LD>

@@ -9,15 +9,18 @@
 //   - "stride" groups: rows r0 + 16 j (r0 < 16), levels 4..L-1;
 // and the tile is exchanged through LDS between the two groupings.  Lanes of
 // a wave always share their rows, so every skew factor (which depends only
-// on the level, the block and the shift, Sec. 3.2) is wave-uniform and its
-// perm table is fetched with scalar loads.  For L <= 4 a single wave holds
-// the whole transform in registers and no LDS is used.
+// on the level, the block and the shift, Sec. 3.2) is wave-uniform.  Each
+// workgroup first copies the vector-operand words of every perm table it
+// will use into LDS (read back as broadcasts); the scalar-operand words are
+// read with scalar loads.  For L <= 4 a single wave holds the whole
+// transform in registers and no LDS is used.
 #pragma once
 #include "nb_xform.hpp"
 
 namespace nb {
 
-enum Mode { M_FFT = 0, M_IFFT = 1, M_DERIV = 2, M_ENC = 3, M_DEC = 4 };
+// M_ENC2: encode of a code with exactly one parity block (n' = 2 k').
+enum Mode { M_FFT = 0, M_IFFT = 1, M_DERIV = 2, M_ENC = 3, M_DEC = 4, M_ENC2 = 5 };
 
 __device__ __forceinline__ const uint8_t *row_ptr(const uint8_t *base, uint32_t t, uint64_t rb)
 {
@@ -28,42 +31,43 @@ __device__ __forceinline__ uint8_t *row_ptr(uint8_t *base, uint32_t t, uint64_t 
     return base + (uint64_t)t * rb;
 }
 
-// Decode step 2 (eq. hatF(l)) for one point: received symbols times Pi(omega_p);
-// erased, virtual and never-stored points are zero.  Surviving rows are
-// copied to the output when decoding out of place.
+// Decode step 2 (eq. hatF(l)), first half: fetch the received row of point
+// p (zeros when the point has none) and copy it to the output when decoding
+// out of place.  Returns whether the point was received.
 template <int R, int LD>
-__device__ __forceinline__ void dec_load(uint32_t *v, int p, const DevStripe &st, const Lane &ln,
-                                         const uint32_t *__restrict__ bits, const uint32_t *__restrict__ rowtab)
+__device__ __forceinline__ bool dec_fetch(uint32_t *raw, int p, const DevStripe &st, const Lane &ln,
+                                          const uint32_t *__restrict__ bits)
 {
-    constexpr int TS = Traits<R>::TS;
     const bool rcv = point_bit(bits, p);
     const uint32_t tr = rcv ? (uint32_t)point_row(p, st) : 0u;
-    uint32_t raw[Traits<R>::NW];
     load_chunk<R, LD>(row_ptr(st.in, tr, st.row_bytes), ln.off, ln.act && rcv, ln.nsym, raw);
     if (st.copy_survivors)
         store_chunk<R, LD>(row_ptr(st.out, tr, st.row_bytes), ln.off, ln.act && rcv, ln.nsym, raw);
-    zero_vec<R>(v);
+    return rcv;
+}
+
+// Second half: x <- Pi(omega_p) x for a received point (x is zero otherwise).
+template <int R>
+__device__ __forceinline__ void dec_weigh(uint32_t *x, bool rcv, const typename Ops<R>::Tab &T)
+{
     if (rcv)
-        Ops<R>::mac(v, raw, Ops<R>::prep(rowtab + (size_t)TS * p));
-    __builtin_amdgcn_sched_barrier(0);
+        scale<R>(x, T);
 }
 
 // Decode step 6 (eq. F(j)) for one point: erased stored rows get
-// Phi^d[p] / Pi'(omega_p).
-template <int R, int LD>
+// Phi^d[p] / Pi'(omega_p); tabf(p) yields the point's perm table.
+template <int R, int LD, class TABF>
 __device__ __forceinline__ void dec_store(const uint32_t *v, int p_, const DevStripe &st, const Lane &ln,
-                                          const uint32_t *__restrict__ bits, const uint32_t *__restrict__ rowtab)
+                                          const uint32_t *__restrict__ bits, const TABF &tabf)
 {
-    constexpr int TS = Traits<R>::TS;
     const int p = (int)fresh((uint32_t)p_);
     if (point_bit(bits + bitmap_words(st.np), p)) {
         const int t = point_row(p, st);
         uint32_t o[Traits<R>::NW];
         zero_vec<R>(o);
-        Ops<R>::mac(o, v, Ops<R>::prep(rowtab + (size_t)TS * p));
+        Ops<R>::mac(o, v, tabf(p));
         store_chunk<R, LD>(row_ptr(st.out, (uint32_t)t, st.row_bytes), ln.off, ln.act, ln.nsym, o);
     }
-    __builtin_amdgcn_sched_barrier(0);
 }
 
 // Sec. 4.2 on rows all held in registers: d^d = B d, coefficient of X_j is
@@ -71,7 +75,7 @@ __device__ __forceinline__ void dec_store(const uint32_t *v, int p_, const DevSt
 template <int R, int L>
 __device__ __forceinline__ void deriv_regs(uint32_t (*x)[Traits<R>::NW], const Tabs &tb)
 {
-    constexpr int NW = Traits<R>::NW, TS = Traits<R>::TS, NR = 1 << L;
+    constexpr int NW = Traits<R>::NW, NR = 1 << L;
     uint32_t y[NR][NW];
 #pragma unroll
     for (int j = 0; j < NR; j++) {
@@ -79,7 +83,7 @@ __device__ __forceinline__ void deriv_regs(uint32_t (*x)[Traits<R>::NW], const T
         for (int w = 0; w < NW; w++)
             y[j][w] = x[j][w];
         if (j)
-            scale<R>(y[j], tb.B + (size_t)TS * fresh(j));     // B_0 = 1
+            scale<R>(y[j], row_tab<R>(tb.B, j));     // B_0 = 1
     }
 #pragma unroll
     for (int j = 0; j < NR; j++) {
@@ -91,14 +95,14 @@ __device__ __forceinline__ void deriv_regs(uint32_t (*x)[Traits<R>::NW], const T
                 for (int w = 0; w < NW; w++)
                     x[j][w] ^= y[j + (1 << lv)][w];
         if (j && j + 1 < NR)
-            scale<R>(x[j], tb.Binv + (size_t)TS * fresh(j));  // 1/B_0 = 1; row NR-1 is 0
+            scale<R>(x[j], row_tab<R>(tb.Binv, j));  // 1/B_0 = 1; row NR-1 is 0
     }
 }
 
 #define NB_FUSED_PARAMS                                                                                       \
-    FusedArgs a, const uint32_t *__restrict__ p_tw, const uint32_t *__restrict__ p_one,                       \
-        const uint32_t *__restrict__ p_B, const uint32_t *__restrict__ p_Binv,                                \
-        const uint32_t *__restrict__ p_bits, const uint32_t *__restrict__ p_rowtabs
+    FusedArgs a, const uint32_t *__restrict__ p_tw, const uint32_t *__restrict__ p_B,                         \
+        const uint32_t *__restrict__ p_Binv, const uint32_t *__restrict__ p_bits,                             \
+        const uint32_t *__restrict__ p_rowtabs
 
 // ------------------------------------------------------------------ L <= 4
 
@@ -111,9 +115,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const DevStripe st = a.stripes[s];
     const Lane ln = lane_of<R, LD>(tile - st.tile0, (int)threadIdx.x, st.col0, st.ncols);
     const uint64_t rb = st.row_bytes;
-    const Tabs tb = {p_tw, p_one, p_B, p_Binv};
+    const Tabs tb = {p_tw, p_B, p_Binv};
     const uint32_t *__restrict__ bits = p_bits + st.bits_off;
     const uint32_t *__restrict__ rowtab = p_rowtabs + st.rowtab_off;
+    const TwGlobal<R> tw = {p_tw, a.l};
+    const TwGlobal<R> tw0 = {p_tw, 0u};
     uint32_t x[NR][NW];
 
     if (MODE == M_FFT || MODE == M_IFFT || MODE == M_DERIV) {
@@ -121,21 +127,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         for (int j = 0; j < NR; j++)
             load_chunk<R, LD>(row_ptr(st.in, j, rb), ln.off, ln.act, ln.nsym, x[j]);
         if (MODE == M_FFT)
-            reg_levels<R, L, false, SH, true>(x, 0, 0, a.l, tb);
+            reg_levels<R, L, false, SH, true>(x, 0, 0, tw);
         else if (MODE == M_IFFT)
-            reg_levels<R, L, true, SH, true>(x, 0, 0, a.l, tb);
+            reg_levels<R, L, true, SH, true>(x, 0, 0, tw);
         else
             deriv_regs<R, L>(x, tb);
 #pragma unroll
         for (int j = 0; j < NR; j++)
             store_chunk<R, LD>(row_ptr(st.out, fresh(j), rb), ln.off, ln.act, ln.nsym, x[j]);
-    } else if (MODE == M_ENC) {
+    } else if (MODE == M_ENC || MODE == M_ENC2) {
         // Algorithm 1: M_bar = inverse transform of the (zero-padded) message,
         // then one forward transform per parity block at shift blk * k'.
 #pragma unroll
         for (int j = 0; j < NR; j++)
             load_chunk<R, LD>(row_ptr(st.in, j, rb), ln.off, ln.act && j < st.k, ln.nsym, x[j]);
-        reg_levels<R, L, true, SH_ZERO, true>(x, 0, 0, 0u, tb);
+        reg_levels<R, L, true, SH_ZERO, true>(x, 0, 0, tw0);
         const int nblocks = st.np / st.kp;
         const int npar = st.n - st.k;
         for (int blk = 1; blk < nblocks; blk++) {
@@ -145,7 +151,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #pragma unroll
                 for (int w = 0; w < NW; w++)
                     y[j][w] = x[j][w];
-            reg_levels<R, L, false, SH_ALIGNED, true>(y, 0, 0, (uint32_t)(blk * NR), tb);
+            const TwGlobal<R> twb = {p_tw, (uint32_t)(blk * NR)};
+            reg_levels<R, L, false, SH_ALIGNED, true>(y, 0, 0, twb);
 #pragma unroll
             for (int j = 0; j < NR; j++) {
                 const int t = (blk - 1) * NR + j;
@@ -154,49 +161,81 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
             }
         }
     } else {  // M_DEC with n' = NR
+        auto tabf = [&](int p) { return row_tab<R>(rowtab, p); };
 #pragma unroll
-        for (int p = 0; p < NR; p++)
-            dec_load<R, LD>(x[p], p, st, ln, bits, rowtab);
-        reg_levels<R, L, true, SH_ZERO, true>(x, 0, 0, 0u, tb);     // step 3
-        deriv_regs<R, L>(x, tb);                             // step 4
-        reg_levels<R, L, false, SH_ZERO, true>(x, 0, 0, 0u, tb);    // step 5
+        for (int p = 0; p < NR; p++) {
+            const bool rcv = dec_fetch<R, LD>(x[p], p, st, ln, bits);
+            dec_weigh<R>(x[p], rcv, tabf(p));
+        }
+        reg_levels<R, L, true, SH_ZERO, true>(x, 0, 0, tw0);      // step 3
+        deriv_regs<R, L>(x, tb);                                  // step 4
+        reg_levels<R, L, false, SH_ZERO, true>(x, 0, 0, tw0);     // step 5
 #pragma unroll
-        for (int p = 0; p < NR; p++)                         // step 6
-            dec_store<R, LD>(x[p], p, st, ln, bits, rowtab);
+        for (int p = 0; p < NR; p++)                              // step 6
+            dec_store<R, LD>(x[p], p, st, ln, bits, tabf);
     }
 }
 
 // ------------------------------------------------------------------ 5 <= L <= 8
 
+// LDS of k_tiled: the tile (2^L rows x 64 lanes x NW dwords), then the V words
+// of every perm table the kernel multiplies by, staged once per workgroup.
+template <int R, int L, int MODE>
+struct TiledLds {
+    static constexpr int H = 1 << L, NV = Ops<R>::NV, NW = Traits<R>::NW;
+    static constexpr int TILE = H * 64 * NW;                             // dwords
+    static constexpr int EX = MODE == M_DERIV ? 0 : H - 1;               // factors of the main transform
+    static constexpr int EY = MODE == M_ENC ? 2 * (H - 1) : MODE == M_ENC2 ? H - 1 : 0;  // parity blocks
+    static constexpr int EB = (MODE == M_DERIV || MODE == M_DEC) ? H : 0;  // B_j, and as many 1/B_j
+    static constexpr int ERT = MODE == M_DEC ? H : 0;                    // per-point locator tables
+    static constexpr size_t BYTES = 4 * ((size_t)TILE + (size_t)NV * (EX + EY + 2 * EB + ERT));
+    static_assert(BYTES <= 160 * 1024, "tile and tables exceed the LDS of a workgroup");
+};
+
 template <int R, int L, int MODE, int SH, int LD>
 __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4))) void k_tiled(NB_FUSED_PARAMS)
 {
-    constexpr int NW = Traits<R>::NW, TS = Traits<R>::TS;
+    typedef TiledLds<R, L, MODE> LY;
+    typedef typename Ops<R>::Tab Tab;
+    constexpr int NW = Traits<R>::NW, NV = Ops<R>::NV, H = 1 << L;
     constexpr int L2 = L - 4;            // levels of the stride phase
     constexpr int NR2 = 1 << L2;         // rows per stride group
     constexpr int GPW = 16 >> L2;        // stride groups per wave (waves = 2^L2)
-    extern __shared__ uint32_t lds[];    // [2^L rows][64 lanes][NW]
+    constexpr int NT = 64 << L2;         // threads
+    extern __shared__ uint32_t lds[];    // [2^L rows][64 lanes][NW], then the staged tables
+    uint32_t *const vX = lds + LY::TILE;
+    uint32_t *const vY = vX + NV * LY::EX;
+    uint32_t *const vB = vY + NV * LY::EY;
+    uint32_t *const vBi = vB + NV * LY::EB;
+    uint32_t *const vRT = vBi + NV * LY::EB;
 
-    const int lane = (int)threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int tid = (int)threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int tile = blockIdx.x;
     const int s = find_stripe(a.stripes, a.nstripes, tile);
     const DevStripe st = a.stripes[s];
     const Lane ln = lane_of<R, LD>(tile - st.tile0, lane, st.col0, st.ncols);
     const uint64_t rb = st.row_bytes;
-    const Tabs tb = {p_tw, p_one, p_B, p_Binv};
     const uint32_t *__restrict__ bits = p_bits + st.bits_off;
     const uint32_t *__restrict__ rowtab = p_rowtabs + st.rowtab_off;
+    const uint32_t lx = (MODE == M_FFT || MODE == M_IFFT) ? a.l : 0u;
+    const TwLds<R, L> twX = {p_tw, lx, vX};
 
-    auto lds_put = [&](int row, const uint32_t *v) {
-        uint32_t *p = lds + ((size_t)row * 64 + lane) * NW;
+    // LDS row slots of this lane: rows are RS dwords apart; callers pass a
+    // group base (a lane slot of the group's first row) and a compile-time
+    // row offset, so accesses are one base register plus an immediate.
+    constexpr int RS = 64 * NW;
+    uint32_t *const my = lds + lane * NW;
+    auto lds_put = [&](uint32_t *base, int rows, const uint32_t *v) {
+        uint32_t *p = base + RS * rows;
         if (NW == 2)
             *reinterpret_cast<uint2 *>(p) = make_uint2(v[0], v[NW - 1]);
         else
             p[0] = v[0];
     };
-    auto lds_get = [&](int row, uint32_t *v) {
-        const uint32_t *p = lds + ((size_t)row * 64 + lane) * NW;
+    auto lds_get = [&](const uint32_t *base, int rows, uint32_t *v) {
+        const uint32_t *p = base + RS * rows;
         if (NW == 2) {
             const uint2 t = *reinterpret_cast<const uint2 *>(p);
             v[0] = t.x;
@@ -205,28 +244,49 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
             v[0] = p[0];
         }
     };
+    // Called by every thread after the first row loads are issued: copies
+    // the tables and makes them visible to the whole workgroup.
+    auto stage_tables = [&]() {
+        if (MODE != M_DERIV)
+            stage_levels<R, L>(vX, p_tw, lx, tid, NT);
+        if (MODE == M_ENC && st.np > H)                 // parity block 1 (shift 2^L) into buffer 1
+            stage_levels<R, L>(vY + NV * (H - 1), p_tw, 1u << L, tid, NT);
+        if (MODE == M_ENC2)                             // the parity block (shift 2^L)
+            stage_levels<R, L>(vY, p_tw, 1u << L, tid, NT);
+        if (LY::EB) {
+            stage_rows<R>(vB, p_B, H, tid, NT);
+            stage_rows<R>(vBi, p_Binv, H, tid, NT);
+        }
+        if (MODE == M_DEC)
+            stage_rows<R>(vRT, rowtab, H, tid, NT);
+        __syncthreads();
+    };
 
     const int g = wave;                       // consecutive group of this wave
+    uint32_t *const cb = my + RS * 16 * g;    // its first row
     uint32_t x[16][NW];                       // consecutive-phase registers
     uint32_t y[GPW][NR2][NW];                 // stride-phase registers
 
     if (MODE == M_FFT) {
 #pragma unroll
+        for (int u = 0; u < GPW; u++)
+#pragma unroll
+            for (int j = 0; j < NR2; j++)
+                load_chunk<R, LD>(row_ptr(st.in, wave * GPW + u + 16 * j, rb), ln.off, ln.act, ln.nsym, y[u][j]);
+        stage_tables();
+#pragma unroll
         for (int u = 0; u < GPW; u++) {
             const int r0 = wave * GPW + u;
+            reg_levels<R, L2, false, SH, true>(y[u], (uint32_t)r0, 4, twX);
 #pragma unroll
             for (int j = 0; j < NR2; j++)
-                load_chunk<R, LD>(row_ptr(st.in, r0 + 16 * j, rb), ln.off, ln.act, ln.nsym, y[u][j]);
-            reg_levels<R, L2, false, SH, true>(y[u], (uint32_t)r0, 4, a.l, tb);
-#pragma unroll
-            for (int j = 0; j < NR2; j++)
-                lds_put(r0 + 16 * j, y[u][j]);
+                lds_put(my + RS * r0, 16 * j, y[u][j]);
         }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < 16; j++)
-            lds_get(16 * g + j, x[j]);
-        reg_levels<R, 4, false, SH, false>(x, (uint32_t)(16 * g), 0, a.l, tb);
+            lds_get(cb, j, x[j]);
+        reg_levels<R, 4, false, SH, false>(x, (uint32_t)(16 * g), 0, twX);
 #pragma unroll
         for (int j = 0; j < 16; j++)
             store_chunk<R, LD>(row_ptr(st.out, fresh(16 * g + j), rb), ln.off, ln.act, ln.nsym, x[j]);
@@ -237,13 +297,15 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
         // Sec. 4.2 on consecutive groups: partners 2^l with l < 4 are in the
         // wave's registers, those with l >= 4 are read from LDS.
 #pragma unroll
-        for (int j = 0; j < 16; j++) {
-            const int p = 16 * g + j;
-            load_chunk<R, LD>(row_ptr(st.in, p, rb), ln.off, ln.act, ln.nsym, x[j]);
-            if (p)
-                scale<R>(x[j], tb.B + (size_t)TS * p);
-            lds_put(p, x[j]);
-        }
+        for (int j = 0; j < 16; j++)
+            load_chunk<R, LD>(row_ptr(st.in, 16 * g + j, rb), ln.off, ln.act, ln.nsym, x[j]);
+        stage_tables();
+        pipelined<Tab, 16>([&](int j) { return row_tab<R>(p_B, vB, 16 * g + j); },
+                           [&](int j, const Tab &t) {
+                               if (16 * g + j)
+                                   scale<R>(x[j], t);
+                               lds_put(cb, j, x[j]);
+                           });
         __syncthreads();
         uint32_t z[16][NW];
 #pragma unroll
@@ -259,45 +321,48 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
         for (int lv = 0; lv < L2; lv++) {
             if (!((g >> lv) & 1)) {
-                const int pg = g + (1 << lv);
 #pragma unroll
                 for (int j = 0; j < 16; j++) {
                     uint32_t v[NW];
-                    lds_get(16 * pg + j, v);
+                    lds_get(cb, 16 * (1 << lv) + j, v);
 #pragma unroll
                     for (int w = 0; w < NW; w++)
                         z[j][w] ^= v[w];
                 }
             }
         }
-#pragma unroll
-        for (int j = 0; j < 16; j++) {
-            const int p = (int)fresh(16 * g + j);
-            if (p)
-                scale<R>(z[j], tb.Binv + (size_t)TS * p);
-            store_chunk<R, LD>(row_ptr(st.out, p, rb), ln.off, ln.act, ln.nsym, z[j]);
-        }
+        pipelined<Tab, 16>([&](int j) { return row_tab<R>(p_Binv, vBi, 16 * g + j); },
+                           [&](int j, const Tab &t) {
+                               const int p = (int)fresh(16 * g + j);
+                               if (p)
+                                   scale<R>(z[j], t);
+                               store_chunk<R, LD>(row_ptr(st.out, p, rb), ln.off, ln.act, ln.nsym, z[j]);
+                           });
         return;
     }
 
     // ---- phase 1 (consecutive groups): input and inverse levels 0..3
+    bool rcv[16];
 #pragma unroll
     for (int j = 0; j < 16; j++) {
         const int p = 16 * g + j;
         if (MODE == M_IFFT) {
             load_chunk<R, LD>(row_ptr(st.in, p, rb), ln.off, ln.act, ln.nsym, x[j]);
-        } else if (MODE == M_ENC) {
+        } else if (MODE == M_ENC || MODE == M_ENC2) {
             // rows k .. k'-1 are the zero padding of a shortened message
             load_chunk<R, LD>(row_ptr(st.in, p, rb), ln.off, ln.act && p < st.k, ln.nsym, x[j]);
         } else {
-            dec_load<R, LD>(x[j], p, st, ln, bits, rowtab);
+            rcv[j] = dec_fetch<R, LD>(x[j], p, st, ln, bits);
         }
     }
-    reg_levels<R, 4, true, (MODE == M_IFFT ? SH : SH_ZERO), false>(x, (uint32_t)(16 * g), 0,
-                                                                   MODE == M_IFFT ? a.l : 0u, tb);
+    stage_tables();
+    if (MODE == M_DEC)
+        pipelined<Tab, 16>([&](int j) { return row_tab<R>(rowtab, vRT, 16 * g + j); },
+                           [&](int j, const Tab &t) { dec_weigh<R>(x[j], rcv[j], t); });
+    reg_levels<R, 4, true, (MODE == M_IFFT ? SH : SH_ZERO), false>(x, (uint32_t)(16 * g), 0, twX);
 #pragma unroll
     for (int j = 0; j < 16; j++)
-        lds_put(16 * g + j, x[j]);
+        lds_put(cb, j, x[j]);
     __syncthreads();
 
     // ---- phase 2 (stride groups): inverse levels 4..L-1
@@ -306,9 +371,8 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
         const int r0 = wave * GPW + u;
 #pragma unroll
         for (int j = 0; j < NR2; j++)
-            lds_get(r0 + 16 * j, y[u][j]);
-        reg_levels<R, L2, true, (MODE == M_IFFT ? SH : SH_ZERO), true>(y[u], (uint32_t)r0, 4,
-                                                                      MODE == M_IFFT ? a.l : 0u, tb);
+            lds_get(my + RS * r0, 16 * j, y[u][j]);
+        reg_levels<R, L2, true, (MODE == M_IFFT ? SH : SH_ZERO), true>(y[u], (uint32_t)r0, 4, twX);
     }
 
     if (MODE == M_IFFT) {
@@ -322,11 +386,38 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
         return;
     }
 
+    if (MODE == M_ENC2) {
+        // the one parity block at shift 2^L, transformed in place
+        const TwLds<R, L> twY = {p_tw, 1u << L, vY};
+#pragma unroll
+        for (int u = 0; u < GPW; u++) {
+            const int r0 = wave * GPW + u;
+            reg_levels<R, L2, false, SH_ALIGNED, true>(y[u], (uint32_t)r0, 4, twY);
+#pragma unroll
+            for (int j = 0; j < NR2; j++)
+                lds_put(my + RS * r0, 16 * j, y[u][j]);
+        }
+        __syncthreads();
+        const int npar = st.n - st.k;
+#pragma unroll
+        for (int j = 0; j < 16; j++)
+            lds_get(cb, j, x[j]);
+        reg_levels<R, 4, false, SH_ALIGNED, false>(x, (uint32_t)(16 * g), 0, twY);
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            const int t = 16 * g + j;
+            if (t < npar)
+                store_chunk<R, LD>(row_ptr(st.out, fresh(t), rb), ln.off, ln.act, ln.nsym, x[j]);
+        }
+        return;
+    }
+
     if (MODE == M_ENC) {
-        const int nblocks = st.np / st.kp;
+        const int nblocks = st.np >> L;
         const int npar = st.n - st.k;
         for (int blk = 1; blk < nblocks; blk++) {
             const uint32_t lsh = (uint32_t)(blk << L);
+            const TwLds<R, L> twY = {p_tw, lsh, vY + NV * (H - 1) * (blk & 1)};
             if (blk > 1)
                 __syncthreads();      // the previous block's phase-3 reads are done
 #pragma unroll
@@ -338,19 +429,23 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
                     for (int w = 0; w < NW; w++)
                         z[j][w] = y[u][j][w];
-                reg_levels<R, L2, false, SH_ALIGNED, true>(z, (uint32_t)r0, 4, lsh, tb);
+                reg_levels<R, L2, false, SH_ALIGNED, true>(z, (uint32_t)r0, 4, twY);
 #pragma unroll
                 for (int j = 0; j < NR2; j++)
-                    lds_put(r0 + 16 * j, z[j]);
+                    lds_put(my + RS * r0, 16 * j, z[j]);
             }
             __syncthreads();
+            // the next block's factors go to the other buffer, last read by
+            // block blk - 1 before the barrier above
+            if (blk + 1 < nblocks)
+                stage_levels<R, L>(vY + NV * (H - 1) * ((blk + 1) & 1), p_tw, (uint32_t)((blk + 1) << L), tid, NT);
 #pragma unroll
             for (int j = 0; j < 16; j++)
-                lds_get(16 * g + j, x[j]);
-            reg_levels<R, 4, false, SH_ALIGNED, false>(x, (uint32_t)(16 * g), 0, lsh, tb);
+                lds_get(cb, j, x[j]);
+            reg_levels<R, 4, false, SH_ALIGNED, false>(x, (uint32_t)(16 * g), 0, twY);
 #pragma unroll
             for (int j = 0; j < 16; j++) {
-                const int t = (blk - 1) * (1 << L) + 16 * g + j;
+                const int t = (blk - 1) * H + 16 * g + j;
                 if (t < npar)
                     store_chunk<R, LD>(row_ptr(st.out, fresh(t), rb), ln.off, ln.act, ln.nsym, x[j]);
             }
@@ -362,13 +457,12 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
     for (int u = 0; u < GPW; u++) {
         const int r0 = wave * GPW + u;
-#pragma unroll
-        for (int j = 0; j < NR2; j++) {
-            const int p = r0 + 16 * j;
-            if (p)
-                scale<R>(y[u][j], tb.B + (size_t)TS * p);
-            lds_put(p, y[u][j]);
-        }
+        pipelined<Tab, NR2>([&](int j) { return row_tab<R>(p_B, vB, r0 + 16 * j); },
+                            [&](int j, const Tab &t) {
+                                if (r0 + 16 * j)
+                                    scale<R>(y[u][j], t);
+                                lds_put(my + RS * r0, 16 * j, y[u][j]);
+                            });
     }
     __syncthreads();
     uint32_t z[GPW][NR2][NW];
@@ -388,11 +482,10 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
         for (int lv = 0; lv < 4; lv++) {                 // partners 2^lv away
             if (!((r0 >> lv) & 1)) {
-                const int pr = r0 + (1 << lv);
 #pragma unroll
                 for (int j = 0; j < NR2; j++) {
                     uint32_t v[NW];
-                    lds_get(pr + 16 * j, v);
+                    lds_get(my + RS * r0, (1 << lv) + 16 * j, v);
 #pragma unroll
                     for (int w = 0; w < NW; w++)
                         z[u][j][w] ^= v[w];
@@ -404,25 +497,25 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
     for (int u = 0; u < GPW; u++) {
         const int r0 = wave * GPW + u;
-#pragma unroll
-        for (int j = 0; j < NR2; j++) {
-            const int p = r0 + 16 * j;
-            if (p)
-                scale<R>(z[u][j], tb.Binv + (size_t)TS * p);
-        }
-        reg_levels<R, L2, false, SH_ZERO, true>(z[u], (uint32_t)r0, 4, 0u, tb);
+        pipelined<Tab, NR2>([&](int j) { return row_tab<R>(p_Binv, vBi, r0 + 16 * j); },
+                            [&](int j, const Tab &t) {
+                                if (r0 + 16 * j)
+                                    scale<R>(z[u][j], t);
+                            });
+        reg_levels<R, L2, false, SH_ZERO, true>(z[u], (uint32_t)r0, 4, twX);
 #pragma unroll
         for (int j = 0; j < NR2; j++)
-            lds_put(r0 + 16 * j, z[u][j]);
+            lds_put(my + RS * r0, 16 * j, z[u][j]);
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < 16; j++)
-        lds_get(16 * g + j, x[j]);
-    reg_levels<R, 4, false, SH_ZERO, false>(x, (uint32_t)(16 * g), 0, 0u, tb);
-#pragma unroll
-    for (int j = 0; j < 16; j++)
-        dec_store<R, LD>(x[j], 16 * g + j, st, ln, bits, rowtab);
+        lds_get(cb, j, x[j]);
+    reg_levels<R, 4, false, SH_ZERO, false>(x, (uint32_t)(16 * g), 0, twX);
+    pipelined<Tab, 16>([&](int j) { return row_tab<R>(rowtab, vRT, 16 * g + j); },
+                       [&](int j, const Tab &t) {
+                           dec_store<R, LD>(x[j], 16 * g + j, st, ln, bits, [&](int) { return t; });
+                       });
 }
 
 // ------------------------------------------------------------------ launchers
@@ -434,12 +527,12 @@ static hipError_t launch_one(const FusedArgs &a, const KPtrs &k, int ntiles, hip
         return hipSuccess;
     if (L <= 4) {
         hipLaunchKernelGGL((k_small<R, (L <= 4 ? L : 4), MODE, SH, LD>), dim3(ntiles), dim3(64), 0, stream, a,
-                           k.tw, k.one, k.B, k.Binv, k.bits, k.rowtabs);
+                           k.tw, k.B, k.Binv, k.bits, k.rowtabs);
     } else {
         constexpr int LL = L > 4 ? L : 5;
-        const size_t lds = (size_t)(1u << LL) * 64 * Traits<R>::NW * 4;
-        hipLaunchKernelGGL((k_tiled<R, LL, MODE, SH, LD>), dim3(ntiles), dim3(64 << (LL - 4)), lds, stream, a,
-                           k.tw, k.one, k.B, k.Binv, k.bits, k.rowtabs);
+        const size_t lds = TiledLds<R, LL, MODE>::BYTES;
+        hipLaunchKernelGGL((k_tiled<R, LL, MODE, SH, LD>), dim3(ntiles), dim3(64 << (LL - 4)), lds, stream, a, k.tw,
+                           k.B, k.Binv, k.bits, k.rowtabs);
     }
     return hipGetLastError();
 }
@@ -449,9 +542,8 @@ static hipError_t prep_one()
 {
     if (L > 4) {
         constexpr int LL = L > 4 ? L : 5;
-        const int lds = (int)((1u << LL) * 64 * Traits<R>::NW * 4);
         return hipFuncSetAttribute((const void *)k_tiled<R, LL, MODE, SH, LD>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)TiledLds<R, LL, MODE>::BYTES);
     }
     return hipSuccess;
 }
@@ -498,6 +590,7 @@ static hipError_t launch_ld(int mode, int sh, int L, const FusedArgs &a, const K
                                 : launch_L<R, M_IFFT, SH_GENERAL, LD>(L, a, k, ntiles, s);
     case M_DERIV: return launch_L<R, M_DERIV, SH_ZERO, LD>(L, a, k, ntiles, s);
     case M_ENC: return launch_L<R, M_ENC, SH_ZERO, LD>(L, a, k, ntiles, s);
+    case M_ENC2: return launch_L<R, M_ENC2, SH_ZERO, LD>(L, a, k, ntiles, s);
     case M_DEC: return launch_L<R, M_DEC, SH_ZERO, LD>(L, a, k, ntiles, s);
     }
     return hipErrorInvalidValue;
@@ -511,6 +604,7 @@ static hipError_t fused_prepare_r()
     NB_PREP(M_FFT, SH_ZERO, LD_VEC) NB_PREP(M_FFT, SH_ALIGNED, LD_VEC) NB_PREP(M_FFT, SH_GENERAL, LD_VEC)
     NB_PREP(M_IFFT, SH_ZERO, LD_VEC) NB_PREP(M_IFFT, SH_ALIGNED, LD_VEC) NB_PREP(M_IFFT, SH_GENERAL, LD_VEC)
     NB_PREP(M_DERIV, SH_ZERO, LD_VEC) NB_PREP(M_ENC, SH_ZERO, LD_VEC) NB_PREP(M_DEC, SH_ZERO, LD_VEC)
+    NB_PREP(M_ENC2, SH_ZERO, LD_VEC) NB_PREP(M_ENC2, SH_ZERO, LD_SYM)
     NB_PREP(M_FFT, SH_ZERO, LD_SYM) NB_PREP(M_FFT, SH_ALIGNED, LD_SYM) NB_PREP(M_FFT, SH_GENERAL, LD_SYM)
     NB_PREP(M_IFFT, SH_ZERO, LD_SYM) NB_PREP(M_IFFT, SH_ALIGNED, LD_SYM) NB_PREP(M_IFFT, SH_GENERAL, LD_SYM)
     NB_PREP(M_DERIV, SH_ZERO, LD_SYM) NB_PREP(M_ENC, SH_ZERO, LD_SYM) NB_PREP(M_DEC, SH_ZERO, LD_SYM)

@@ -209,8 +209,7 @@ __global__ void k_locator(LocatorArgs a, const uint32_t *__restrict__ p_bits, ui
 
 hipError_t init_tables(int r, const uint32_t *d_basis, uint32_t *d_Wv, uint32_t *d_S, uint32_t *d_wp,
                        uint32_t *d_skew, uint32_t *d_B, uint32_t *d_Binv, uint32_t *d_exp, uint32_t *d_log,
-                       uint32_t *d_FL, uint32_t *d_tw_tab, uint32_t *d_B_tab, uint32_t *d_Binv_tab,
-                       uint32_t *d_one_val, uint32_t *d_one_tab, hipStream_t s)
+                       uint32_t *d_FL, uint32_t *d_tw_tab, uint32_t *d_B_tab, uint32_t *d_Binv_tab, hipStream_t s)
 {
     const uint32_t q = 1u << r;
     hipLaunchKernelGGL(k_init_basis, dim3(1), dim3(64), 0, s, r, d_basis, d_Wv, d_S, d_wp);
@@ -222,7 +221,6 @@ hipError_t init_tables(int r, const uint32_t *d_basis, uint32_t *d_Wv, uint32_t 
     hipLaunchKernelGGL(k_init_perm, dim3(256), dim3(256), 0, s, r, (const uint32_t *)d_skew, q - 1, d_tw_tab);
     hipLaunchKernelGGL(k_init_perm, dim3(256), dim3(256), 0, s, r, (const uint32_t *)d_B, q, d_B_tab);
     hipLaunchKernelGGL(k_init_perm, dim3(256), dim3(256), 0, s, r, (const uint32_t *)d_Binv, q, d_Binv_tab);
-    hipLaunchKernelGGL(k_init_perm, dim3(1), dim3(64), 0, s, r, (const uint32_t *)d_one_val, 1u, d_one_tab);
     return hipGetLastError();
 }
 

@@ -16,7 +16,6 @@ namespace nb {
 // Device-resident method tables (built once by rs_init).
 struct Tabs {
     const uint32_t *__restrict__ tw;     // perm tables of the skew factors, 2^r - 1 entries
-    const uint32_t *__restrict__ one;    // perm table of the constant 1
     const uint32_t *__restrict__ B;      // perm tables of B_j, 2^r entries (Sec. 4.2, eq. B)
     const uint32_t *__restrict__ Binv;   // perm tables of 1 / B_j
 };
@@ -24,7 +23,7 @@ struct Tabs {
 // Host-side bundle of every read-only pointer a kernel receives as a
 // separate parameter.
 struct KPtrs {
-    const uint32_t *tw, *one, *B, *Binv;
+    const uint32_t *tw, *B, *Binv;
     const uint32_t *bits;      // decode: point bitmaps, stripe s at DevStripe::bits_off
     const uint32_t *rowtabs;   // decode: locator perm tables, stripe s at DevStripe::rowtab_off
 };

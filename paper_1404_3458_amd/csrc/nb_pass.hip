@@ -26,10 +26,10 @@ __device__ __forceinline__ uint8_t *prow(uint8_t *base, uint32_t t, uint64_t rb)
 
 template <int R, int T, bool INV, bool GEN_L, int LD>
 __global__ __launch_bounds__(64) void k_pass(PassArgs a, const uint32_t *__restrict__ p_tw,
-                                             const uint32_t *__restrict__ p_one, const uint32_t *__restrict__ p_B)
+                                             const uint32_t *__restrict__ p_B)
 {
-    constexpr int NW = Traits<R>::NW, TS = Traits<R>::TS, NR = 1 << T;
-    const Tabs tb = {p_tw, p_one, p_B, nullptr};
+    constexpr int NW = Traits<R>::NW, NR = 1 << T;
+    const TwGlobal<R> tw = {p_tw, a.l};
     const uint32_t g = blockIdx.x / (uint32_t)a.nct;
     const int ct = (int)(blockIdx.x % (uint32_t)a.nct);
     const uint32_t base = group_base(g, a.lo, T);
@@ -44,14 +44,14 @@ __global__ __launch_bounds__(64) void k_pass(PassArgs a, const uint32_t *__restr
         else
             zero_vec<R>(x[j]);
         if (a.pre_B)
-            scale<R>(x[j], p_B + (size_t)TS * p);
+            scale<R>(x[j], row_tab<R>(p_B, (int)p));
     }
-    reg_levels<R, T, INV, (GEN_L ? SH_GENERAL : SH_ALIGNED), false>(x, base, a.lo, a.l, tb);
+    reg_levels<R, T, INV, (GEN_L ? SH_GENERAL : SH_ALIGNED), false>(x, base, a.lo, tw);
 #pragma unroll
     for (int j = 0; j < NR; j++) {
         const uint32_t p = fresh(base + ((uint32_t)j << a.lo));
         if (a.post_B)
-            scale<R>(x[j], p_B + (size_t)TS * p);
+            scale<R>(x[j], row_tab<R>(p_B, (int)p));
         if ((int)p >= a.dst_lo && (int)p < a.dst_hi)
             store_chunk<R, LD>(prow(a.dst, p - (uint32_t)a.dst_lo, rb), ln.off, ln.act, ln.nsym, x[j]);
     }
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(64) void k_pass(PassArgs a, const uint32_t *__restr
 template <int R, int T, int LD>
 __global__ __launch_bounds__(64) void k_dpart(DerivPassArgs a, const uint32_t *__restrict__ p_Binv)
 {
-    constexpr int NW = Traits<R>::NW, TS = Traits<R>::TS, NR = 1 << T;
+    constexpr int NW = Traits<R>::NW, NR = 1 << T;
     const uint32_t g = blockIdx.x / (uint32_t)a.nct;
     const int ct = (int)(blockIdx.x % (uint32_t)a.nct);
     const uint32_t base = group_base(g, a.lo, T);
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(64) void k_dpart(DerivPassArgs a, const uint32_t *_
                 for (int w = 0; w < NW; w++)
                     z[w] ^= y[j + (1 << lv)][w];
         if (a.last) {
-            scale<R>(z, p_Binv + (size_t)TS * p);
+            scale<R>(z, row_tab<R>(p_Binv, (int)p));
             store_chunk<R, LD>(prow(a.out, p, rb), ln.off, ln.act, ln.nsym, z);
         } else {
             store_chunk<R, LD>(prow(a.z, p, rb), ln.off, ln.act, ln.nsym, z);
@@ -99,7 +99,7 @@ template <int R, int LD>
 __global__ __launch_bounds__(64) void k_dec_gather(DecodeIOArgs a, const uint32_t *__restrict__ p_bits,
                                                    const uint32_t *__restrict__ p_rowtabs)
 {
-    constexpr int NW = Traits<R>::NW, TS = Traits<R>::TS;
+    constexpr int NW = Traits<R>::NW;
     const int p = (int)(blockIdx.x / (uint32_t)a.nct);
     const int ct = (int)(blockIdx.x % (uint32_t)a.nct);
     const DevStripe &st = a.st;
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(64) void k_dec_gather(DecodeIOArgs a, const uint32_
         load_chunk<R, LD>(prow(st.in, t, st.row_bytes), ln.off, ln.act, ln.nsym, raw);
         if (st.copy_survivors)
             store_chunk<R, LD>(prow(st.out, t, st.row_bytes), ln.off, ln.act, ln.nsym, raw);
-        Ops<R>::mac(v, raw, Ops<R>::prep(rowtab + (size_t)TS * p));
+        Ops<R>::mac(v, raw, row_tab<R>(rowtab, p));
     }
     store_chunk<R, LD>(prow(a.A, p, st.row_bytes), ln.off, ln.act, ln.nsym, v);
 }
@@ -125,7 +125,7 @@ template <int R, int LD>
 __global__ __launch_bounds__(64) void k_dec_scatter(DecodeIOArgs a, const uint32_t *__restrict__ p_bits,
                                                     const uint32_t *__restrict__ p_rowtabs)
 {
-    constexpr int NW = Traits<R>::NW, TS = Traits<R>::TS;
+    constexpr int NW = Traits<R>::NW;
     const int t = (int)(blockIdx.x / (uint32_t)a.nct);
     const int ct = (int)(blockIdx.x % (uint32_t)a.nct);
     const DevStripe &st = a.st;
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(64) void k_dec_scatter(DecodeIOArgs a, const uint32
     uint32_t v[NW], o[NW];
     load_chunk<R, LD>(prow(a.A, p, st.row_bytes), ln.off, ln.act, ln.nsym, v);
     zero_vec<R>(o);
-    Ops<R>::mac(o, v, Ops<R>::prep(rowtab + (size_t)TS * p));
+    Ops<R>::mac(o, v, row_tab<R>(rowtab, p));
     store_chunk<R, LD>(prow(st.out, t, st.row_bytes), ln.off, ln.act, ln.nsym, o);
 }
 
@@ -148,11 +148,11 @@ template <int R, bool INV, bool GEN_L, int LD>
 static hipError_t pass_T(int T, const PassArgs &a, const KPtrs &k, uint32_t nblocks, hipStream_t s)
 {
     switch (T) {
-    case 0: hipLaunchKernelGGL((k_pass<R, 0, INV, GEN_L, LD>), dim3(nblocks), dim3(64), 0, s, a, k.tw, k.one, k.B); break;
-    case 1: hipLaunchKernelGGL((k_pass<R, 1, INV, GEN_L, LD>), dim3(nblocks), dim3(64), 0, s, a, k.tw, k.one, k.B); break;
-    case 2: hipLaunchKernelGGL((k_pass<R, 2, INV, GEN_L, LD>), dim3(nblocks), dim3(64), 0, s, a, k.tw, k.one, k.B); break;
-    case 3: hipLaunchKernelGGL((k_pass<R, 3, INV, GEN_L, LD>), dim3(nblocks), dim3(64), 0, s, a, k.tw, k.one, k.B); break;
-    case 4: hipLaunchKernelGGL((k_pass<R, 4, INV, GEN_L, LD>), dim3(nblocks), dim3(64), 0, s, a, k.tw, k.one, k.B); break;
+    case 0: hipLaunchKernelGGL((k_pass<R, 0, INV, GEN_L, LD>), dim3(nblocks), dim3(64), 0, s, a, k.tw, k.B); break;
+    case 1: hipLaunchKernelGGL((k_pass<R, 1, INV, GEN_L, LD>), dim3(nblocks), dim3(64), 0, s, a, k.tw, k.B); break;
+    case 2: hipLaunchKernelGGL((k_pass<R, 2, INV, GEN_L, LD>), dim3(nblocks), dim3(64), 0, s, a, k.tw, k.B); break;
+    case 3: hipLaunchKernelGGL((k_pass<R, 3, INV, GEN_L, LD>), dim3(nblocks), dim3(64), 0, s, a, k.tw, k.B); break;
+    case 4: hipLaunchKernelGGL((k_pass<R, 4, INV, GEN_L, LD>), dim3(nblocks), dim3(64), 0, s, a, k.tw, k.B); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -33,44 +33,143 @@ enum { SH_ZERO = 0, SH_ALIGNED = 1, SH_GENERAL = 2 };
 
 // Skew factor W_i(omega_c + omega_l) / W_i(omega_{2^i}) for a block c (bits
 // <= i clear): by additivity (Lemma 1) it is the table entry of level i at
-// (c xor l) >> (i + 1), plus 1 when bit i of l is set (W_i(v_i) normalises to 1).
-template <int R, int SH>
-struct Twiddle {
+// (c xor l) >> (i + 1), plus 1 when bit i of l is set (W_i(v_i) normalises to
+// 1).  The "plus 1" is applied as an extra a += b in the butterfly, so a
+// factor source only ever yields plain table entries.
+
+// Factor source reading whole perm tables from global memory.
+template <int R>
+struct TwGlobal {
     static constexpr int TS = Traits<R>::TS;
-    uint32_t buf[SH == SH_GENERAL ? TS : 1];
-    __device__ __forceinline__ const uint32_t *get(const Tabs &tb, int i, uint32_t c, uint32_t l)
+    const uint32_t *__restrict__ tw;
+    uint32_t l;
+    __device__ __forceinline__ typename Ops<R>::Tab tab(int i, uint32_t c) const
     {
         const uint32_t off = (1u << R) - (1u << (R - i));
-        // an opaque index: the same factor loaded by two transforms of a kernel
-        // is loaded twice instead of being kept live in between
-        const uint32_t *t = tb.tw + (size_t)TS * fresh(off + ((c ^ l) >> (i + 1)));
-        if (SH == SH_GENERAL && ((l >> i) & 1u)) {
-#pragma unroll
-            for (int u = 0; u < TS; u++)
-                buf[u] = t[u] ^ tb.one[u];
-            return buf;
-        }
-        return t;
+        // an opaque index: the same factor fetched by two transforms of a
+        // kernel is fetched twice instead of being kept live in between
+        return Ops<R>::prep(tw + (size_t)TS * fresh(off + ((c ^ l) >> (i + 1))));
     }
 };
 
+// Factor source for a transform over 2^LT points whose V words were staged
+// in LDS by stage_levels (level i at entries 2^LT - 2^(LT-i) + q), with the
+// S words still read from global memory.
+template <int R, int LT>
+struct TwLds {
+    static constexpr int TS = Traits<R>::TS, NV = Ops<R>::NV;
+    const uint32_t *__restrict__ tw;
+    uint32_t l;
+    const uint32_t *vt;
+    __device__ __forceinline__ typename Ops<R>::Tab tab(int i, uint32_t c) const
+    {
+        const uint32_t off = (1u << R) - (1u << (R - i));
+        const uint32_t q = ((c ^ l) & ((1u << LT) - 1u)) >> (i + 1);
+        const uint32_t e = fresh((1u << LT) - (1u << (LT - i)) + q);
+        return Ops<R>::prep_lds(vt + NV * e, tw + (size_t)TS * fresh(off + ((c ^ l) >> (i + 1))));
+    }
+};
+
+// Cooperative copy (all threads of the block) of the V words of the factor
+// tables of a 2^LT-point transform at shift l into LDS, laid out as TwLds reads
+// them: level i holds the 2^(LT-i-1) entries starting at table index
+// 2^r - 2^(r-i) + ((l >> LT) << (LT - i - 1)).
+template <int R, int LT>
+__device__ __forceinline__ void stage_levels(uint32_t *vt, const uint32_t *__restrict__ tw, uint32_t l, int tid,
+                                             int nthreads)
+{
+    constexpr int TS = Traits<R>::TS, NV = Ops<R>::NV, H = 1 << LT;
+    constexpr int PER = NV / 2;            // 8-byte pieces per entry
+    for (int u = tid; u < (H - 1) * PER; u += nthreads) {
+        const int e = u / PER, w = u % PER;
+        const int m = H - 1 - e;                       // in [2^(LT-i-1), 2^(LT-i) - 1]
+        const int i = LT - 1 - (31 - __builtin_clz((unsigned)m));
+        const int q = e - (H - (H >> i));
+        const uint32_t g = (1u << R) - (1u << (R - i)) + ((l >> LT) << (LT - i - 1)) + (uint32_t)q;
+        const uint2 v = *reinterpret_cast<const uint2 *>(tw + (size_t)TS * g + 2 * w);
+        *reinterpret_cast<uint2 *>(vt + NV * e + 2 * w) = v;
+    }
+}
+
+// Cooperative copy of the V words of `count` consecutive perm tables.
+template <int R>
+__device__ __forceinline__ void stage_rows(uint32_t *vt, const uint32_t *__restrict__ src, int count, int tid,
+                                           int nthreads)
+{
+    constexpr int TS = Traits<R>::TS, NV = Ops<R>::NV, PER = NV / 2;
+    for (int u = tid; u < count * PER; u += nthreads) {
+        const int e = u / PER, w = u % PER;
+        const uint2 v = *reinterpret_cast<const uint2 *>(src + (size_t)TS * e + 2 * w);
+        *reinterpret_cast<uint2 *>(vt + NV * e + 2 * w) = v;
+    }
+}
+
+// Perm table of row j of a per-row table (B_j, 1/B_j or a locator table),
+// from global memory only or with the V words from LDS.
+template <int R>
+__device__ __forceinline__ typename Ops<R>::Tab row_tab(const uint32_t *__restrict__ g, int j)
+{
+    return Ops<R>::prep(g + (size_t)Traits<R>::TS * fresh((uint32_t)j));
+}
+template <int R>
+__device__ __forceinline__ typename Ops<R>::Tab row_tab(const uint32_t *__restrict__ g, const uint32_t *vt, int j)
+{
+    const uint32_t jj = fresh((uint32_t)j);
+    return Ops<R>::prep_lds(vt + Ops<R>::NV * jj, g + (size_t)Traits<R>::TS * jj);
+}
+
+// One butterfly; m1 (all ones or zero, wave-uniform) adds the "plus 1" of the
+// factor.
 template <int R, bool INV>
-__device__ __forceinline__ void bfly(uint32_t *a, uint32_t *b, const typename Ops<R>::Tab &T, bool zero)
+__device__ __forceinline__ void bfly(uint32_t *a, uint32_t *b, const typename Ops<R>::Tab &T, bool zero,
+                                     uint32_t m1)
 {
     constexpr int NW = Traits<R>::NW;
     if (!INV) {
         if (!zero)
             Ops<R>::mac(a, b, T);
 #pragma unroll
-        for (int w = 0; w < NW; w++)
+        for (int w = 0; w < NW; w++) {
+            a[w] ^= b[w] & m1;
             b[w] ^= a[w];
+        }
     } else {
 #pragma unroll
         for (int w = 0; w < NW; w++)
             b[w] ^= a[w];
         if (!zero)
             Ops<R>::mac(a, b, T);
+#pragma unroll
+        for (int w = 0; w < NW; w++)
+            a[w] ^= b[w] & m1;
     }
+}
+
+// Block k of the butterfly blocks of T levels on 2^T rows, in execution
+// order (levels T-1 .. 0 forward, 0 .. T-1 inverse; blocks by first row).
+template <int T, bool INV>
+constexpr int block_level(int k)
+{
+    for (int tt = 0; tt < T; tt++) {
+        const int t = INV ? tt : T - 1 - tt;
+        const int nb = (1 << T) >> (t + 1);
+        if (k < nb)
+            return t;
+        k -= nb;
+    }
+    return 0;
+}
+template <int T, bool INV>
+constexpr int block_row(int k)
+{
+    for (int tt = 0; tt < T; tt++) {
+        const int t = INV ? tt : T - 1 - tt;
+        const int nb = (1 << T) >> (t + 1);
+        if (k < nb)
+            return k * (2 << t);
+        k -= nb;
+    }
+    return 0;
 }
 
 // T levels on 2^T rows in registers; x[j] is global row base + (j << LO),
@@ -79,52 +178,50 @@ __device__ __forceinline__ void bfly(uint32_t *a, uint32_t *b, const typename Op
 // CT_BASE says that base has no bit at or above LO (so that block 0 of the
 // group is block 0 of the transform, known at compile time).  Elsewhere a
 // zero factor is simply multiplied (its table is all zero), which avoids a
-// data-dependent branch around the butterflies.
-template <int R, int T, bool INV, int SH, bool CT_BASE>
-__device__ __forceinline__ void reg_levels(uint32_t (*x)[Traits<R>::NW], uint32_t base, int LO, uint32_t l,
-                                           const Tabs &tb)
+// data-dependent branch around the butterflies.  TW is the factor source;
+// the factor of the next block is fetched while a block is computed.
+template <int R, int T, bool INV, int SH, bool CT_BASE, class TW>
+__device__ __forceinline__ void reg_levels(uint32_t (*x)[Traits<R>::NW], uint32_t base, int LO, const TW &tw)
 {
-    constexpr int NR = 1 << T;
-    Twiddle<R, SH> tw;
-#pragma unroll
-    for (int tt = 0; tt < T; tt++) {
-        const int t = INV ? tt : T - 1 - tt;
+    typedef typename Ops<R>::Tab Tab;
+    constexpr int NW = Traits<R>::NW, NB = (1 << T) - 1;
+    auto fetch = [&](int k) -> Tab {
+        const int t = block_level<T, INV>(k), blk = block_row<T, INV>(k);
+        if (SH == SH_ZERO && CT_BASE && blk == 0)
+            return Tab{};
         const int i = LO + t;
+        const uint32_t c = (base & ~((2u << i) - 1u)) | ((uint32_t)blk << LO);
+        return tw.tab(i, c);
+    };
+    auto work = [&](int k, const Tab &tab) {
+        const int t = block_level<T, INV>(k), blk = block_row<T, INV>(k);
+        const int i = LO + t;
+        const bool zero = SH == SH_ZERO && CT_BASE && blk == 0;
+        const uint32_t m1 = (SH == SH_GENERAL && ((tw.l >> i) & 1u)) ? ~0u : 0u;
 #pragma unroll
-        for (int blk = 0; blk < NR; blk += 2 << t) {
-            const bool zero = SH == SH_ZERO && CT_BASE && blk == 0;
-            if (zero) {
-                const typename Ops<R>::Tab tab = {};
-#pragma unroll
-                for (int m = 0; m < (1 << t); m++)
-                    bfly<R, INV>(x[blk + m], x[blk + m + (1 << t)], tab, true);
-            } else {
-                const uint32_t c = (base & ~((2u << i) - 1u)) | ((uint32_t)blk << LO);
-                const typename Ops<R>::Tab tab = Ops<R>::prep(tw.get(tb, i, c, l));
-#pragma unroll
-                for (int m = 0; m < (1 << t); m++)
-                    bfly<R, INV>(x[blk + m], x[blk + m + (1 << t)], tab, false);
-            }
-            // keep each block's factor table live only while it is used
-            __builtin_amdgcn_sched_barrier(0);
+        for (int m = 0; m < (1 << t); m++) {
+            bfly<R, INV>(x[blk + m], x[blk + m + (1 << t)], tab, zero, m1);
+            pin<NW>(x[blk + m]);
         }
-    }
+    };
+    if (NB > 0)
+        pipelined<Tab, NB>(fetch, work);
 }
 
-// x <- s_row * x for a row whose perm table is t.
+// x <- s_row * x for a row whose perm table is T.
 template <int R>
-__device__ __forceinline__ void scale(uint32_t *x, const uint32_t *t)
+__device__ __forceinline__ void scale(uint32_t *x, const typename Ops<R>::Tab &T)
 {
     constexpr int NW = Traits<R>::NW;
     uint32_t acc[NW];
 #pragma unroll
     for (int w = 0; w < NW; w++)
         acc[w] = 0;
-    Ops<R>::mac(acc, x, Ops<R>::prep(t));
+    Ops<R>::mac(acc, x, T);
 #pragma unroll
     for (int w = 0; w < NW; w++)
         x[w] = acc[w];
-    __builtin_amdgcn_sched_barrier(0);
+    pin<NW>(x);
 }
 
 // Stored row of point p of the mother code, -1 for a virtual zero point,

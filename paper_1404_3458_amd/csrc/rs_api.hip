@@ -17,7 +17,7 @@ namespace nb {
 hipError_t init_tables(int r, const uint32_t *d_basis, uint32_t *d_Wv, uint32_t *d_S, uint32_t *d_wp,
                        uint32_t *d_skew, uint32_t *d_B, uint32_t *d_Binv, uint32_t *d_exp, uint32_t *d_log,
                        uint32_t *d_FL, uint32_t *d_tw_tab, uint32_t *d_B_tab, uint32_t *d_Binv_tab,
-                       uint32_t *d_one_val, uint32_t *d_one_tab, hipStream_t s);
+                       hipStream_t s);
 hipError_t init_prepare(int r);
 hipError_t locator_launch(const LocatorArgs &a, const KPtrs &k, const uint32_t *fwht_L, const uint32_t *expt,
                           int nstripes, int max_np, hipStream_t s);
@@ -39,7 +39,8 @@ using namespace nb;
 
 namespace {
 
-enum { MODE_FFT = 0, MODE_IFFT = 1, MODE_DERIV = 2, MODE_ENC = 3, MODE_DEC = 4 };
+// MODE_ENC2: encode of a code with one parity block (n' = 2 k')
+enum { MODE_FFT = 0, MODE_IFFT = 1, MODE_DERIV = 2, MODE_ENC = 3, MODE_DEC = 4, MODE_ENC2 = 5 };
 constexpr int FUSED_MAX_L = 8;      // fused single-launch kernels cover h <= 256
 constexpr int NSLOTS = 4;           // pinned staging slots per stream
 
@@ -86,7 +87,7 @@ struct rs_ctx {
     uint32_t basis[16] = {};
     void *d_mem = nullptr;
     uint32_t *d_basis, *d_Wv, *d_S, *d_wp, *d_skew, *d_B, *d_Binv, *d_exp, *d_log, *d_FL;
-    uint32_t *d_tw_tab, *d_B_tab, *d_Binv_tab, *d_one_val, *d_one_tab;
+    uint32_t *d_tw_tab, *d_B_tab, *d_Binv_tab;
     KPtrs kp;           // method tables (masks / rowtabs filled per call)
     std::mutex mu;
     std::vector<Scratch *> scratch;
@@ -219,6 +220,7 @@ struct Plan {
     DevStripe ds;       // col0 / tile0 / offsets filled when launches are planned
     int L;              // lg of the transform size (k' for encode, n' for decode)
     int erasures;
+    bool decoding;
     bool aligned;       // rows and bases allow LD_VEC accesses
     size_t mask_src;    // offset of the stripe's mask in the caller's mask array
 };
@@ -277,6 +279,7 @@ int validate_stripe(rs_ctx *ctx, const rs_stripe_desc &d, bool decode, const uin
     pl.aligned = vec_aligned(ctx, d.in, d.out, d.row_bytes);
     pl.L = ilog2(decode ? np : kp);
     pl.erasures = 0;
+    pl.decoding = decode;
     if (decode) {
         if (!mask)
             return RS_EINVAL;
@@ -505,6 +508,14 @@ hipError_t fused_launch(int r, int mode, int sh, int ld, int L, const FusedArgs 
 
 // ------------------------------------------------------------------ codec driver
 
+// An encode whose mother code has a single parity block (n' = 2 k') runs a
+// kernel variant without the loop over parity blocks.
+bool one_parity_block(const Plan &p) { return !p.decoding && p.ds.np == 2 * p.ds.kp; }
+
+// Stripes of one fused launch share the transform size, the row access
+// variant and the kernel variant.
+int launch_key(const Plan &p, int ld) { return (p.L * 2 + ld) * 2 + (one_parity_block(p) ? 1 : 0); }
+
 // One launch unit: a column part of one stripe.
 struct Entry {
     int plan;
@@ -582,15 +593,15 @@ int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, in
             ents.push_back({act[q], cp});
     }
     std::stable_sort(ents.begin(), ents.end(), [&](const Entry &a, const Entry &b) {
-        const int ka = plans[a.plan].L * 2 + a.cp.ld, kb = plans[b.plan].L * 2 + b.cp.ld;
+        const int ka = launch_key(plans[a.plan], a.cp.ld), kb = launch_key(plans[b.plan], b.cp.ld);
         return ka < kb;
     });
     const int ne = (int)ents.size();
     std::vector<DevStripe> eds((size_t)ne);
     for (int j = 0; j < ne;) {
-        const int key = plans[ents[j].plan].L * 2 + ents[j].cp.ld;
+        const int key = launch_key(plans[ents[j].plan], ents[j].cp.ld);
         int e = j, tiles = 0;
-        while (e < ne && plans[ents[e].plan].L * 2 + ents[e].cp.ld == key) {
+        while (e < ne && launch_key(plans[ents[e].plan], ents[e].cp.ld) == key) {
             eds[e] = plans[ents[e].plan].ds;
             eds[e].col0 = ents[e].cp.col0;
             eds[e].tile0 = tiles;
@@ -656,9 +667,9 @@ int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, in
     }
     const DevStripe *d_ents = (const DevStripe *)dev;
     for (int j = 0; j < ne;) {
-        const int key = plans[ents[j].plan].L * 2 + ents[j].cp.ld;
+        const int key = launch_key(plans[ents[j].plan], ents[j].cp.ld);
         int e = j, tiles = 0;
-        while (e < ne && plans[ents[e].plan].L * 2 + ents[e].cp.ld == key) {
+        while (e < ne && launch_key(plans[ents[e].plan], ents[e].cp.ld) == key) {
             tiles += ents[e].cp.ntiles;
             e++;
         }
@@ -666,7 +677,8 @@ int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, in
         fa.stripes = d_ents + j;
         fa.nstripes = e - j;
         fa.l = 0;
-        if (dev_err(ctx, fused_launch(ctx->r, decode ? MODE_DEC : MODE_ENC, 0, ents[j].cp.ld,
+        const int mode = decode ? MODE_DEC : (one_parity_block(plans[ents[j].plan]) ? MODE_ENC2 : MODE_ENC);
+        if (dev_err(ctx, fused_launch(ctx->r, mode, 0, ents[j].cp.ld,
                                       plans[ents[j].plan].L, fa, kp, tiles, stream)))
             return RS_EDEVICE;
         j = e;
@@ -828,9 +840,8 @@ __attribute__((visibility("default"))) int rs_init(int r, const uint32_t *basis,
     const int ts = r == 16 ? TAB16 : TAB8;
     // dword counts of every table, one allocation
     const size_t n_basis = 16, n_Wv = 256, n_S = 256, n_wp = 16, n_skew = q, n_B = q, n_Binv = q, n_exp = q,
-                 n_log = q, n_FL = 2 * q, n_tw = ts * q, n_Bt = ts * q, n_Binvt = ts * q, n_one = 4, n_onet = 32;
-    const size_t sizes[] = {n_basis, n_Wv, n_S, n_wp, n_skew, n_B, n_Binv, n_exp, n_log, n_FL, n_tw, n_Bt, n_Binvt,
-                            n_one, n_onet};
+                 n_log = q, n_FL = 2 * q, n_tw = ts * q, n_Bt = ts * q, n_Binvt = ts * q;
+    const size_t sizes[] = {n_basis, n_Wv, n_S, n_wp, n_skew, n_B, n_Binv, n_exp, n_log, n_FL, n_tw, n_Bt, n_Binvt};
     size_t total = 0;
     for (size_t s : sizes)
         total += align_up(s * 4, 256);
@@ -839,22 +850,18 @@ __attribute__((visibility("default"))) int rs_init(int r, const uint32_t *basis,
         return RS_ENOMEM;
     }
     uint32_t **dst[] = {&ctx->d_basis, &ctx->d_Wv, &ctx->d_S, &ctx->d_wp, &ctx->d_skew, &ctx->d_B, &ctx->d_Binv,
-                        &ctx->d_exp, &ctx->d_log, &ctx->d_FL, &ctx->d_tw_tab, &ctx->d_B_tab, &ctx->d_Binv_tab,
-                        &ctx->d_one_val, &ctx->d_one_tab};
+                        &ctx->d_exp, &ctx->d_log, &ctx->d_FL, &ctx->d_tw_tab, &ctx->d_B_tab, &ctx->d_Binv_tab};
     size_t off = 0;
     for (size_t i = 0; i < sizeof(sizes) / sizeof(sizes[0]); i++) {
         *dst[i] = (uint32_t *)((uint8_t *)ctx->d_mem + off);
         off += align_up(sizes[i] * 4, 256);
     }
-    uint32_t hb[16] = {0}, one[4] = {1, 0, 0, 0};
+    uint32_t hb[16] = {0};
     std::memcpy(hb, b, sizeof(uint32_t) * r);
     hipError_t e = hipMemcpy(ctx->d_basis, hb, sizeof(hb), hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(ctx->d_one_val, one, sizeof(one), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
         e = init_tables(r, ctx->d_basis, ctx->d_Wv, ctx->d_S, ctx->d_wp, ctx->d_skew, ctx->d_B, ctx->d_Binv,
-                        ctx->d_exp, ctx->d_log, ctx->d_FL, ctx->d_tw_tab, ctx->d_B_tab, ctx->d_Binv_tab,
-                        ctx->d_one_val, ctx->d_one_tab, nullptr);
+                        ctx->d_exp, ctx->d_log, ctx->d_FL, ctx->d_tw_tab, ctx->d_B_tab, ctx->d_Binv_tab, nullptr);
     if (e == hipSuccess)
         e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -863,7 +870,6 @@ __attribute__((visibility("default"))) int rs_init(int r, const uint32_t *basis,
         return RS_EDEVICE;
     }
     ctx->kp.tw = ctx->d_tw_tab;
-    ctx->kp.one = ctx->d_one_tab;
     ctx->kp.B = ctx->d_B_tab;
     ctx->kp.Binv = ctx->d_Binv_tab;
     ctx->kp.bits = nullptr;
