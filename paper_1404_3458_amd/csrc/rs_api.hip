@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -42,14 +43,23 @@ namespace {
 // MODE_ENC2: encode of a code with one parity block (n' = 2 k')
 enum { MODE_FFT = 0, MODE_IFFT = 1, MODE_DERIV = 2, MODE_ENC = 3, MODE_DEC = 4, MODE_ENC2 = 5 };
 constexpr int FUSED_MAX_L = 8;      // fused single-launch kernels cover h <= 256
-constexpr int NSLOTS = 4;           // pinned staging slots per stream
-
-struct Slot {
-    void *host = nullptr;
+// Pinned host ring through which each call's descriptors reach the device.
+// Every upload occupies a byte range until the event recorded after its copy
+// completes; the host waits only when the ring is full, so it can run many
+// calls ahead of the device.
+struct Staging {
+    uint8_t *host = nullptr;
     size_t cap = 0;
-    hipEvent_t ev = nullptr;
-    bool recorded = false;
+    size_t head = 0;                 // next byte to hand out
+    struct Rec {
+        size_t begin, end;
+        hipEvent_t ev;
+    };
+    std::deque<Rec> live;            // uploads in flight, oldest first
+    std::vector<hipEvent_t> pool;    // completed events for reuse
 };
+
+constexpr size_t STAGING_MIN = (size_t)4 << 20;
 
 struct Scratch {
     hipStream_t stream = nullptr;
@@ -57,8 +67,7 @@ struct Scratch {
     size_t dev_cap = 0;
     void *big = nullptr;             // rows of the multi-pass pipelines
     size_t big_cap = 0;
-    Slot slots[NSLOTS];
-    int next = 0;
+    Staging stg;
 };
 
 int ilog2(long v)
@@ -133,12 +142,6 @@ Scratch *get_scratch(rs_ctx *ctx, hipStream_t s)
     if (!sc)
         return nullptr;
     sc->stream = s;
-    for (int i = 0; i < NSLOTS; i++) {
-        if (hipEventCreateWithFlags(&sc->slots[i].ev, hipEventDisableTiming) != hipSuccess) {
-            delete sc;
-            return nullptr;
-        }
-    }
     ctx->scratch.push_back(sc);
     return sc;
 }
@@ -164,34 +167,64 @@ int ensure_dev(Scratch *sc, void **buf, size_t *cap, size_t need)
     return RS_OK;
 }
 
-// Copy `bytes` of host data to the device arena through a pinned slot whose
-// previous copy is known to have completed.
+// Wait for the oldest in-flight upload of the ring and recycle its event.
+int staging_retire_oldest(Staging &g)
+{
+    Staging::Rec r = g.live.front();
+    g.live.pop_front();
+    const hipError_t e = hipEventSynchronize(r.ev);
+    g.pool.push_back(r.ev);
+    return e == hipSuccess ? RS_OK : RS_EDEVICE;
+}
+
+// Copy `bytes` of host data to `dst` (device) through the pinned ring.
 int stage_upload(Scratch *sc, const void *src, size_t bytes, void *dst)
 {
     if (!bytes)
         return RS_OK;
-    Slot &sl = sc->slots[sc->next];
-    sc->next = (sc->next + 1) % NSLOTS;
-    if (sl.recorded && hipEventSynchronize(sl.ev) != hipSuccess)
-        return RS_EDEVICE;
-    if (sl.cap < bytes) {
-        if (sl.host)
-            (void)hipHostFree(sl.host);
-        sl.host = nullptr;
-        sl.cap = 0;
-        size_t want = std::max(bytes, (size_t)1 << 16);
-        if (hipHostMalloc(&sl.host, want, hipHostMallocDefault) != hipSuccess) {
-            sl.host = nullptr;
+    Staging &g = sc->stg;
+    const size_t need = align_up(bytes, 256);
+    if (need > g.cap) {                           // grow: drain, then reallocate
+        while (!g.live.empty())
+            if (staging_retire_oldest(g))
+                return RS_EDEVICE;
+        if (g.host)
+            (void)hipHostFree(g.host);
+        g.host = nullptr;
+        g.cap = 0;
+        g.head = 0;
+        const size_t want = std::max(need, STAGING_MIN);
+        if (hipHostMalloc((void **)&g.host, want, hipHostMallocDefault) != hipSuccess) {
+            g.host = nullptr;
             return RS_ENOMEM;
         }
-        sl.cap = want;
+        g.cap = want;
     }
-    std::memcpy(sl.host, src, bytes);
-    if (hipMemcpyAsync(dst, sl.host, bytes, hipMemcpyHostToDevice, sc->stream) != hipSuccess)
+    const size_t begin = g.head + need <= g.cap ? g.head : 0;
+    auto overlaps = [&]() {
+        for (const Staging::Rec &r : g.live)
+            if (r.begin < begin + need && begin < r.end)
+                return true;
+        return false;
+    };
+    while (!g.live.empty() && overlaps())
+        if (staging_retire_oldest(g))
+            return RS_EDEVICE;
+    hipEvent_t ev = nullptr;
+    if (!g.pool.empty()) {
+        ev = g.pool.back();
+        g.pool.pop_back();
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
         return RS_EDEVICE;
-    if (hipEventRecord(sl.ev, sc->stream) != hipSuccess)
+    }
+    std::memcpy(g.host + begin, src, bytes);
+    if (hipMemcpyAsync(dst, g.host + begin, bytes, hipMemcpyHostToDevice, sc->stream) != hipSuccess ||
+        hipEventRecord(ev, sc->stream) != hipSuccess) {
+        g.pool.push_back(ev);
         return RS_EDEVICE;
-    sl.recorded = true;
+    }
+    g.live.push_back({begin, begin + need, ev});
+    g.head = begin + need;
     return RS_OK;
 }
 
@@ -889,12 +922,12 @@ __attribute__((visibility("default"))) void rs_free(rs_ctx *ctx)
             (void)hipFree(sc->dev);
         if (sc->big)
             (void)hipFree(sc->big);
-        for (int i = 0; i < NSLOTS; i++) {
-            if (sc->slots[i].host)
-                (void)hipHostFree(sc->slots[i].host);
-            if (sc->slots[i].ev)
-                (void)hipEventDestroy(sc->slots[i].ev);
-        }
+        for (const Staging::Rec &r : sc->stg.live)
+            (void)hipEventDestroy(r.ev);
+        for (hipEvent_t ev : sc->stg.pool)
+            (void)hipEventDestroy(ev);
+        if (sc->stg.host)
+            (void)hipHostFree(sc->stg.host);
         delete sc;
     }
     if (ctx->d_mem)

@@ -36,6 +36,18 @@ class StripeDesc(ctypes.Structure):
                 ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p)]
 
 
+class PreparedBatch:
+    """Descriptor array (and concatenated masks) of a batch call, kept alive
+    together with the pointers handed to the library."""
+
+    def __init__(self, arr, masks, count):
+        self.arr = arr
+        self.masks = masks
+        self.count = count
+        self.desc_ptr = ctypes.cast(arr, ctypes.c_void_p)
+        self.mask_ptr = masks.ctypes.data_as(ctypes.c_void_p) if masks is not None else None
+
+
 def load():
     """Load librs_nb.so (raises if it has not been built)."""
     global _lib
@@ -154,18 +166,18 @@ class Codec:
         return _check(load().rs_decode(self._ctx, n, k, mk.ctypes.data_as(ctypes.c_void_p), _ptr(shards),
                                        _ptr(out), row_bytes, _stream(stream)), "rs_decode")
 
-    def encode_batch(self, stripes, stream=None):
-        """stripes: list of (n, k, msg, parity[, row_bytes])."""
+    def prepare_encode_batch(self, stripes):
+        """Marshal a list of (n, k, msg, parity[, row_bytes]) once, for
+        repeated encode_batch calls on the same buffers."""
         arr = (StripeDesc * len(stripes))()
         for i, s in enumerate(stripes):
             n, k, msg, par = s[:4]
             rb = s[4] if len(s) > 4 else _rows(msg, k)[1]
             arr[i] = StripeDesc(n, k, rb, _ptr(msg), _ptr(par))
-        return _check(load().rs_encode_batch(self._ctx, ctypes.cast(arr, ctypes.c_void_p), len(stripes),
-                                             _stream(stream)), "rs_encode_batch")
+        return PreparedBatch(arr, None, len(stripes))
 
-    def decode_batch(self, stripes, stream=None):
-        """stripes: list of (n, k, mask, shards, out[, row_bytes])."""
+    def prepare_decode_batch(self, stripes):
+        """Marshal a list of (n, k, mask, shards, out[, row_bytes]) once."""
         arr = (StripeDesc * len(stripes))()
         masks = []
         for i, s in enumerate(stripes):
@@ -174,9 +186,18 @@ class Codec:
             arr[i] = StripeDesc(n, k, rb, _ptr(sh), _ptr(out if out is not None else sh))
             masks.append(np.asarray(mask, dtype=np.uint8).reshape(-1))
         allm = np.ascontiguousarray(np.concatenate(masks) if masks else np.zeros(0, np.uint8))
-        return _check(load().rs_decode_batch(self._ctx, ctypes.cast(arr, ctypes.c_void_p),
-                                             allm.ctypes.data_as(ctypes.c_void_p), len(stripes),
-                                             _stream(stream)), "rs_decode_batch")
+        return PreparedBatch(arr, allm, len(stripes))
+
+    def encode_batch(self, stripes, stream=None):
+        """stripes: list of (n, k, msg, parity[, row_bytes]) or a prepared batch."""
+        b = stripes if isinstance(stripes, PreparedBatch) else self.prepare_encode_batch(stripes)
+        return _check(load().rs_encode_batch(self._ctx, b.desc_ptr, b.count, _stream(stream)), "rs_encode_batch")
+
+    def decode_batch(self, stripes, stream=None):
+        """stripes: list of (n, k, mask, shards, out[, row_bytes]) or a prepared batch."""
+        b = stripes if isinstance(stripes, PreparedBatch) else self.prepare_decode_batch(stripes)
+        return _check(load().rs_decode_batch(self._ctx, b.desc_ptr, b.mask_ptr, b.count, _stream(stream)),
+                      "rs_decode_batch")
 
     # ------------------------------------------------------------ transforms
     def fft(self, h, l, data, row_bytes=None, stream=None):
