@@ -22,54 +22,6 @@ namespace nb {
 // M_ENC2: encode of a code with exactly one parity block (n' = 2 k').
 enum Mode { M_FFT = 0, M_IFFT = 1, M_DERIV = 2, M_ENC = 3, M_DEC = 4, M_ENC2 = 5 };
 
-__device__ __forceinline__ const uint8_t *row_ptr(const uint8_t *base, uint32_t t, uint64_t rb)
-{
-    return base + (uint64_t)t * rb;
-}
-__device__ __forceinline__ uint8_t *row_ptr(uint8_t *base, uint32_t t, uint64_t rb)
-{
-    return base + (uint64_t)t * rb;
-}
-
-// Decode step 2 (eq. hatF(l)), first half: fetch the received row of point
-// p (zeros when the point has none) and copy it to the output when decoding
-// out of place.  Returns whether the point was received.
-template <int R, int LD>
-__device__ __forceinline__ bool dec_fetch(uint32_t *raw, int p, const DevStripe &st, const Lane &ln,
-                                          const uint32_t *__restrict__ bits)
-{
-    const bool rcv = point_bit(bits, p);
-    const uint32_t tr = rcv ? (uint32_t)point_row(p, st) : 0u;
-    load_chunk<R, LD>(row_ptr(st.in, tr, st.row_bytes), ln.off, ln.act && rcv, ln.nsym, raw);
-    if (st.copy_survivors)
-        store_chunk<R, LD>(row_ptr(st.out, tr, st.row_bytes), ln.off, ln.act && rcv, ln.nsym, raw);
-    return rcv;
-}
-
-// Second half: x <- Pi(omega_p) x for a received point (x is zero otherwise).
-template <int R>
-__device__ __forceinline__ void dec_weigh(uint32_t *x, bool rcv, const typename Ops<R>::Tab &T)
-{
-    if (rcv)
-        scale<R>(x, T);
-}
-
-// Decode step 6 (eq. F(j)) for one point: erased stored rows get
-// Phi^d[p] / Pi'(omega_p); tabf(p) yields the point's perm table.
-template <int R, int LD, class TABF>
-__device__ __forceinline__ void dec_store(const uint32_t *v, int p_, const DevStripe &st, const Lane &ln,
-                                          const uint32_t *__restrict__ bits, const TABF &tabf)
-{
-    const int p = (int)fresh((uint32_t)p_);
-    if (point_bit(bits + bitmap_words(st.np), p)) {
-        const int t = point_row(p, st);
-        uint32_t o[Traits<R>::NW];
-        zero_vec<R>(o);
-        Ops<R>::mac(o, v, tabf(p));
-        store_chunk<R, LD>(row_ptr(st.out, (uint32_t)t, st.row_bytes), ln.off, ln.act, ln.nsym, o);
-    }
-}
-
 // Sec. 4.2 on rows all held in registers: d^d = B d, coefficient of X_j is
 // the sum of d^d_{j + 2^l} over the clear bits l of j, divided by B_j.
 template <int R, int L>

@@ -205,6 +205,68 @@ __global__ void k_locator(LocatorArgs a, const uint32_t *__restrict__ p_bits, ui
     }
 }
 
+// Locator for large n' (one stripe, many workgroups): the same two
+// Walsh-Hadamard transforms as k_locator, each split into a pass over
+// groups of 2^T1 consecutive points and a pass over groups of 2^T2 points at
+// stride 2^T1 (the transform's levels commute), on a global array v of n'
+// residues.  Kinds: 0 = indicator of erased points, then levels; 1 = levels,
+// then times FWHT(L_N); 2 = levels; 3 = levels, then the normalisation,
+// exponentials and per-point perm tables as k_locator writes them.
+__global__ __launch_bounds__(256) void k_loc_pass(LocPassArgs a, const uint32_t *__restrict__ p_bits,
+                                                  uint32_t *__restrict__ p_rowtabs,
+                                                  const uint32_t *__restrict__ fwht_L,
+                                                  const uint32_t *__restrict__ expt)
+{
+    __shared__ uint32_t v[256];
+    const DevStripe st = *a.stripe;
+    const int r = a.r, T = a.T, lo = a.lo, H = 1 << T;
+    const uint32_t M = (1u << r) - 1u;
+    const uint32_t *__restrict__ rxb = p_bits + st.bits_off;
+    const uint32_t gi = blockIdx.x;
+    const uint32_t gbase = (gi & ((1u << lo) - 1u)) | ((gi >> lo) << (lo + T));
+    auto erased = [&](uint32_t p) {
+        return !((rxb[p >> 5] >> (p & 31)) & 1u) && !((int)p >= st.k && (int)p < st.kp);
+    };
+    for (int j = threadIdx.x; j < H; j += blockDim.x) {
+        const uint32_t p = gbase + ((uint32_t)j << lo);
+        v[j] = a.kind == 0 ? (erased(p) ? 1u : 0u) : a.v[p];
+    }
+    __syncthreads();
+    for (int len = 1; len < H; len <<= 1) {
+        for (int idx = threadIdx.x; idx < H / 2; idx += blockDim.x) {
+            const int i = ((idx & ~(len - 1)) << 1) | (idx & (len - 1));
+            const uint32_t u = v[i], w = v[i + len];
+            v[i] = addm(u, w, M);
+            v[i + len] = subm(u, w, M);
+        }
+        __syncthreads();
+    }
+    int lgN = 0;
+    while ((1 << lgN) < st.np)
+        lgN++;
+    const int sh = (r - lgN) % r;
+    const int ts = r == 16 ? TAB16 : TAB8;
+    const uint32_t *FLN = fwht_L + (st.np - 1);
+    uint32_t *out = p_rowtabs + st.rowtab_off;
+    for (int j = threadIdx.x; j < H; j += blockDim.x) {
+        const uint32_t p = gbase + ((uint32_t)j << lo);
+        uint32_t x = v[j];
+        if (a.kind == 1)
+            x = mulm(x, FLN[p], r);
+        if (a.kind != 3) {
+            a.v[p] = x;
+            continue;
+        }
+        if (sh)
+            x = ((x << sh) | (x >> (r - sh))) & M;
+        const uint32_t e = erased(p) ? (M - x) % M : x % M;
+        uint32_t tab[TAB16];
+        build_perm_table(expt[e], r, tab);
+        for (int u = 0; u < ts; u++)
+            out[(size_t)ts * p + u] = tab[u];
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 
 hipError_t init_tables(int r, const uint32_t *d_basis, uint32_t *d_Wv, uint32_t *d_S, uint32_t *d_wp,
@@ -230,6 +292,13 @@ hipError_t init_prepare(int r)
     hipError_t e = hipFuncSetAttribute((const void *)k_init_fwhtL, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     hipError_t f = hipFuncSetAttribute((const void *)k_locator, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     return e != hipSuccess ? e : f;
+}
+
+hipError_t loc_pass_launch(const LocPassArgs &a, const KPtrs &k, const uint32_t *fwht_L, const uint32_t *expt,
+                           int ngroups, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_loc_pass, dim3(ngroups), dim3(256), 0, s, a, k.bits, (uint32_t *)k.rowtabs, fwht_L, expt);
+    return hipGetLastError();
 }
 
 hipError_t locator_launch(const LocatorArgs &a, const KPtrs &k, const uint32_t *fwht_L, const uint32_t *expt,

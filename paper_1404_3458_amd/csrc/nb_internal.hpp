@@ -81,11 +81,32 @@ struct DerivPassArgs {
     int32_t col0, first, last;
 };
 
-// Per-point gather / scatter of the multi-pass decoder.
-struct DecodeIOArgs {
-    DevStripe st;
-    uint8_t *A;               // n' scratch rows
-    int32_t nct;
+// One stripe (column part) of a launch of 8-level passes over a transform of
+// n' or k' = 2^N > 256 points.  Groups are 2^T rows gbase + (j << lo) of the
+// transform; tile t of the launch is group (t - tile0) / nct, column tile
+// (t - tile0) % nct.
+struct WideStripe {
+    DevStripe st;             // decode: shards, output, point bitmaps and tables
+    const uint8_t *src;       // rows read (row = point index); rows >= src_rows read as zero
+    uint8_t *dst;             // rows written; rows >= dst_rows are not written
+    const uint8_t *src2;      // decode derivative: partial sums read
+    uint8_t *dst2;            // decode derivative: partial sums written; encode: coefficients kept
+    int32_t src_rows, dst_rows;
+    int32_t tile0, nct;
+};
+
+struct WideArgs {
+    const WideStripe *stripes;
+    int32_t nstripes;
+    int32_t lo;               // groups are rows gbase + (j << lo)
+    int32_t blk;              // encode: parity block, transformed at shift blk * k'
+};
+
+// One pass of the multi-workgroup locator of one stripe (k_loc_pass).
+struct LocPassArgs {
+    const DevStripe *stripe;
+    uint32_t *v;              // n' residues
+    int32_t r, lo, T, kind;
 };
 
 struct LocatorArgs {

@@ -93,55 +93,6 @@ __global__ __launch_bounds__(64) void k_dpart(DerivPassArgs a, const uint32_t *_
     }
 }
 
-// Decode step 2 for the multi-pass decoder: A[p] = rx * Pi(omega_p) for
-// received points, 0 otherwise; surviving rows copied when out != in.
-template <int R, int LD>
-__global__ __launch_bounds__(64) void k_dec_gather(DecodeIOArgs a, const uint32_t *__restrict__ p_bits,
-                                                   const uint32_t *__restrict__ p_rowtabs)
-{
-    constexpr int NW = Traits<R>::NW;
-    const int p = (int)(blockIdx.x / (uint32_t)a.nct);
-    const int ct = (int)(blockIdx.x % (uint32_t)a.nct);
-    const DevStripe &st = a.st;
-    const Lane ln = lane_of<R, LD>(ct, (int)threadIdx.x, st.col0, st.ncols);
-    const uint32_t *__restrict__ bits = p_bits + st.bits_off;
-    const uint32_t *__restrict__ rowtab = p_rowtabs + st.rowtab_off;
-    uint32_t v[NW];
-    zero_vec<R>(v);
-    if (point_bit(bits, p)) {
-        const int t = point_row(p, st);
-        uint32_t raw[NW];
-        load_chunk<R, LD>(prow(st.in, t, st.row_bytes), ln.off, ln.act, ln.nsym, raw);
-        if (st.copy_survivors)
-            store_chunk<R, LD>(prow(st.out, t, st.row_bytes), ln.off, ln.act, ln.nsym, raw);
-        Ops<R>::mac(v, raw, row_tab<R>(rowtab, p));
-    }
-    store_chunk<R, LD>(prow(a.A, p, st.row_bytes), ln.off, ln.act, ln.nsym, v);
-}
-
-// Decode step 6 for the multi-pass decoder: erased stored row t of point p
-// gets A[p] / Pi'(omega_p).
-template <int R, int LD>
-__global__ __launch_bounds__(64) void k_dec_scatter(DecodeIOArgs a, const uint32_t *__restrict__ p_bits,
-                                                    const uint32_t *__restrict__ p_rowtabs)
-{
-    constexpr int NW = Traits<R>::NW;
-    const int t = (int)(blockIdx.x / (uint32_t)a.nct);
-    const int ct = (int)(blockIdx.x % (uint32_t)a.nct);
-    const DevStripe &st = a.st;
-    const uint32_t *__restrict__ bits = p_bits + st.bits_off;
-    const uint32_t *__restrict__ rowtab = p_rowtabs + st.rowtab_off;
-    const int p = t < st.k ? t : st.kp + (t - st.k);
-    if (!point_bit(bits + bitmap_words(st.np), p))
-        return;
-    const Lane ln = lane_of<R, LD>(ct, (int)threadIdx.x, st.col0, st.ncols);
-    uint32_t v[NW], o[NW];
-    load_chunk<R, LD>(prow(a.A, p, st.row_bytes), ln.off, ln.act, ln.nsym, v);
-    zero_vec<R>(o);
-    Ops<R>::mac(o, v, row_tab<R>(rowtab, p));
-    store_chunk<R, LD>(prow(st.out, t, st.row_bytes), ln.off, ln.act, ln.nsym, o);
-}
-
 // ---------------------------------------------------------------- launchers
 
 template <int R, bool INV, bool GEN_L, int LD>
@@ -200,27 +151,6 @@ hipError_t dpart_launch(int r, int ld, int T, const DerivPassArgs &a, const KPtr
     if (r == 16)
         return ld == LD_VEC ? dpart_T<16, LD_VEC>(T, a, k, nblocks, s) : dpart_T<16, LD_SYM>(T, a, k, nblocks, s);
     return ld == LD_VEC ? dpart_T<8, LD_VEC>(T, a, k, nblocks, s) : dpart_T<8, LD_SYM>(T, a, k, nblocks, s);
-}
-
-template <int R, int LD>
-static void dec_io_r(bool scatter, const DecodeIOArgs &a, const KPtrs &k, uint32_t nblocks, hipStream_t s)
-{
-    if (scatter)
-        hipLaunchKernelGGL((k_dec_scatter<R, LD>), dim3(nblocks), dim3(64), 0, s, a, k.bits, k.rowtabs);
-    else
-        hipLaunchKernelGGL((k_dec_gather<R, LD>), dim3(nblocks), dim3(64), 0, s, a, k.bits, k.rowtabs);
-}
-
-hipError_t dec_io_launch(int r, int ld, bool scatter, const DecodeIOArgs &a, const KPtrs &k, uint32_t nblocks,
-                         hipStream_t s)
-{
-    if (nblocks == 0)
-        return hipSuccess;
-    if (r == 16)
-        ld == LD_VEC ? dec_io_r<16, LD_VEC>(scatter, a, k, nblocks, s) : dec_io_r<16, LD_SYM>(scatter, a, k, nblocks, s);
-    else
-        ld == LD_VEC ? dec_io_r<8, LD_VEC>(scatter, a, k, nblocks, s) : dec_io_r<8, LD_SYM>(scatter, a, k, nblocks, s);
-    return hipGetLastError();
 }
 
 }  // namespace nb

@@ -1,0 +1,439 @@
+// nb_wide.hip -- passes of up to 8 levels for the codec on transforms over
+// h = 2^N > 256 points (GF(2^16) only: GF(2^8) never exceeds 256 points),
+// batched over stripes.
+//
+// The N levels are split into a low part of T1 = ceil(N/2) levels, applied
+// to groups of 2^T1 consecutive rows, and a high part of T2 = N - T1 levels,
+// applied to groups of 2^T2 rows at stride 2^T1 (Sec. 3.2 / 3.3: level i
+// pairs rows j and j + 2^i, so a group holding every row that differs in
+// bits lo .. lo+T-1 can apply those levels alone).  Inside a workgroup a
+// group of 2^T rows is handled like a whole small transform of the fused
+// kernels: 16-row register groups, an LDS transpose, the other levels on
+// stride-16 register groups, with the factors' vector words staged in LDS.
+//
+// Pass kinds (one launch each, over every stripe of the call with this N):
+//   encode (Algorithm 1; coefficients A, k' rows):
+//     W_E1   low levels of the inverse transform of the zero-padded message
+//     W_E2   high levels of that inverse, then the high levels of the forward
+//            transform of parity block 1 (shift k'); the coefficients are also
+//            kept when later blocks need them
+//     W_E2F  high levels of the forward transform of block blk >= 2
+//     W_E3   low levels of block blk's forward transform; parity rows written
+//   decode (Algorithm 2; n' rows):
+//     W_D1   step 2 (received rows times Pi) and low inverse levels
+//     W_D2   high inverse levels, d^d = B (.) coefficients (Sec. 4.2), and the
+//            derivative's partial sums over the high bits
+//     W_D3   the partial sums over the low bits, plus those of W_D2, over B_j
+//     W_D4   high forward levels
+//     W_D5   low forward levels and step 6 (erased rows over Pi')
+#include "nb_xform.hpp"
+
+namespace nb {
+
+enum WideKind { W_E1 = 0, W_E2 = 1, W_E2F = 2, W_E3 = 3, W_D1 = 4, W_D2 = 5, W_D3 = 6, W_D4 = 7, W_D5 = 8 };
+
+__device__ __forceinline__ int find_wide(const WideStripe *__restrict__ st, int n, int tile)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (st[mid].tile0 <= tile)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ const uint8_t *wrow(const uint8_t *b, uint32_t t, uint64_t rb) { return b + (uint64_t)t * rb; }
+__device__ __forceinline__ uint8_t *wrow(uint8_t *b, uint32_t t, uint64_t rb) { return b + (uint64_t)t * rb; }
+
+// LDS of a pass: the group tile, then the staged V words of the factor
+// tables (a second set for W_E2's forward part) and of the per-point tables.
+template <int T, int KIND>
+struct WideLds {
+    static constexpr int R = 16, H = 1 << T, NV = Ops<R>::NV, NW = Traits<R>::NW;
+    static constexpr int TILE = T > 4 ? H * 64 * NW : 0;
+    static constexpr int EX = KIND == W_D3 ? 0 : H - 1;
+    static constexpr int EX2 = KIND == W_E2 ? H - 1 : 0;
+    static constexpr int EB = (KIND == W_D2 || KIND == W_D3) ? H : 0;
+    static constexpr int ERT = (KIND == W_D1 || KIND == W_D5) ? H : 0;
+    static constexpr size_t BYTES = 4 * ((size_t)TILE + (size_t)NV * (EX + EX2 + EB + ERT));
+    static_assert(BYTES <= 160 * 1024, "pass tile and tables exceed the LDS of a workgroup");
+};
+
+#define NB_WIDE_THREADS(T) ((T) > 4 ? (64 << ((T) - 4)) : 64)
+
+template <int T, int KIND, int LD>
+__global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per_eu(4))) void k_wide(
+    WideArgs a, const uint32_t *__restrict__ p_tw, const uint32_t *__restrict__ p_B,
+    const uint32_t *__restrict__ p_Binv, const uint32_t *__restrict__ p_bits, const uint32_t *__restrict__ p_rowtabs)
+{
+    constexpr int R = 16;
+    typedef WideLds<T, KIND> LY;
+    typedef typename Ops<R>::Tab Tab;
+    constexpr int NW = Traits<R>::NW, NV = Ops<R>::NV, H = 1 << T;
+    constexpr int TA = T < 4 ? T : 4;              // levels of the consecutive (register) phase
+    constexpr int L2 = T > 4 ? T - 4 : 0;          // levels of the stride phase
+    constexpr int NR2 = 1 << L2;
+    constexpr int GPW = T > 4 ? 16 >> L2 : 1;
+    constexpr int NT = NB_WIDE_THREADS(T);
+    constexpr int NX = 1 << TA;                    // rows of a consecutive register group
+    constexpr bool INV_FIRST = KIND == W_E1 || KIND == W_E2 || KIND == W_D1 || KIND == W_D2;
+    constexpr bool FWD = KIND == W_E2 || KIND == W_E2F || KIND == W_E3 || KIND == W_D4 || KIND == W_D5;
+    constexpr int SHF = (KIND == W_D4 || KIND == W_D5) ? SH_ZERO : SH_ALIGNED;   // forward-part shift
+
+    extern __shared__ uint32_t lds[];
+    uint32_t *const vX = lds + LY::TILE;
+    uint32_t *const vX2 = vX + NV * LY::EX;
+    uint32_t *const vB = vX2 + NV * LY::EX2;
+    uint32_t *const vRT = vB + NV * LY::EB;
+
+    const int tid = (int)threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int tile = blockIdx.x;
+    const int s = find_wide(a.stripes, a.nstripes, tile);
+    const WideStripe ws = a.stripes[s];
+    const DevStripe &st = ws.st;
+    const int rel = tile - ws.tile0;
+    const uint32_t gi = (uint32_t)(rel / ws.nct);
+    const int ct = rel % ws.nct;
+    const uint32_t lo = (uint32_t)a.lo;
+    const uint32_t gbase = (gi & ((1u << lo) - 1u)) | ((gi >> lo) << (lo + T));
+    const Lane ln = lane_of<R, LD>(ct, lane, st.col0, st.ncols);
+    const uint64_t rb = st.row_bytes;
+    const uint32_t *__restrict__ bits = p_bits + st.bits_off;
+    const uint32_t *__restrict__ rowtab = p_rowtabs + st.rowtab_off;
+    auto grow = [&](int p) -> uint32_t { return gbase + ((uint32_t)p << lo); };
+
+    // the inverse part runs at shift 0; the forward part at shift blk * k'
+    // (encode) or 0 (decode)
+    const uint32_t lf = (KIND == W_E2) ? (uint32_t)st.kp
+                      : (KIND == W_E2F || KIND == W_E3) ? (uint32_t)a.blk * (uint32_t)st.kp : 0u;
+    const TwLds<R, T> twI = {p_tw, 0u, vX, lo, gbase};
+    const TwLds<R, T> twF = {p_tw, lf, KIND == W_E2 ? vX2 : vX, lo, gbase};
+
+    constexpr int RS = 64 * NW;
+    uint32_t *const my = lds + lane * NW;
+    auto lds_put = [&](uint32_t *base, int rows, const uint32_t *v) {
+        uint32_t *p = base + RS * rows;
+        *reinterpret_cast<uint2 *>(p) = make_uint2(v[0], v[1]);
+    };
+    auto lds_get = [&](const uint32_t *base, int rows, uint32_t *v) {
+        const uint2 t = *reinterpret_cast<const uint2 *>(base + RS * rows);
+        v[0] = t.x;
+        v[1] = t.y;
+    };
+    auto stage_tables = [&]() {
+        if (LY::EX)
+            stage_levels<R, T>(vX, p_tw, INV_FIRST ? 0u : lf, tid, NT, lo, gbase);
+        if (LY::EX2)
+            stage_levels<R, T>(vX2, p_tw, lf, tid, NT, lo, gbase);
+        if (KIND == W_D2)
+            stage_rows<R>(vB, p_B, H, tid, NT, lo, gbase);
+        if (KIND == W_D3)
+            stage_rows<R>(vB, p_Binv, H, tid, NT, lo, gbase);
+        if (LY::ERT)
+            stage_rows<R>(vRT, rowtab, H, tid, NT, lo, gbase);
+        __syncthreads();
+    };
+
+    const int g = wave;                             // consecutive register group of this wave
+    uint32_t *const cb = my + RS * 16 * g;
+    uint32_t x[NX][NW];                             // consecutive-phase registers (local rows NX g + j)
+    uint32_t y[GPW][NR2][NW];                       // stride-phase registers (local rows r0 + 16 j)
+    auto xrow = [&](int j) { return NX * g + j; };
+
+    // Rows of the data once it sits in stride registers (T > 4) or in x.
+    auto store_data = [&](uint8_t *d) {
+        if constexpr (T > 4) {
+#pragma unroll
+            for (int u = 0; u < GPW; u++)
+#pragma unroll
+                for (int j = 0; j < NR2; j++)
+                    store_chunk<R, LD>(wrow(d, fresh(grow(wave * GPW + u + 16 * j)), rb), ln.off, ln.act, ln.nsym,
+                                       y[u][j]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < NX; j++)
+                store_chunk<R, LD>(wrow(d, fresh(grow(j)), rb), ln.off, ln.act, ln.nsym, x[j]);
+        }
+    };
+
+    // ------------------------------------------------ input
+    bool rcv[NX];
+    if (INV_FIRST || KIND == W_D3 || T <= 4) {
+#pragma unroll
+        for (int j = 0; j < NX; j++) {
+            const uint32_t p = grow(xrow(j));
+            if (KIND == W_D1)
+                rcv[j] = dec_fetch<R, LD>(x[j], (int)p, st, ln, bits);
+            else
+                load_chunk<R, LD>(wrow(ws.src, p, rb), ln.off, ln.act && (int)p < ws.src_rows, ln.nsym, x[j]);
+        }
+    } else {
+        if constexpr (T > 4) {
+#pragma unroll
+            for (int u = 0; u < GPW; u++)
+#pragma unroll
+                for (int j = 0; j < NR2; j++) {
+                    const uint32_t p = grow(wave * GPW + u + 16 * j);
+                    load_chunk<R, LD>(wrow(ws.src, p, rb), ln.off, ln.act && (int)p < ws.src_rows, ln.nsym, y[u][j]);
+                }
+        }
+    }
+    stage_tables();
+
+    if (KIND == W_D3) {
+        // z_p = partial sums of W_D2 + sum over clear local bits l of p of
+        // y_{p + 2^l}; the coefficient is z_p / B_p (Sec. 4.2).
+        uint32_t z[NX][NW];
+#pragma unroll
+        for (int j = 0; j < NX; j++)
+            load_chunk<R, LD>(wrow(ws.src2, grow(xrow(j)), rb), ln.off, ln.act, ln.nsym, z[j]);
+#pragma unroll
+        for (int j = 0; j < NX; j++)
+#pragma unroll
+            for (int lv = 0; lv < TA; lv++)
+                if (!((j >> lv) & 1))
+#pragma unroll
+                    for (int w = 0; w < NW; w++)
+                        z[j][w] ^= x[j + (1 << lv)][w];
+        if constexpr (T > 4) {
+#pragma unroll
+            for (int j = 0; j < 16; j++)
+                lds_put(cb, j, x[j]);
+            __syncthreads();
+#pragma unroll
+            for (int lv = 0; lv < L2; lv++) {
+                if (!((g >> lv) & 1)) {
+#pragma unroll
+                    for (int j = 0; j < 16; j++) {
+                        uint32_t v[NW];
+                        lds_get(cb, 16 * (1 << lv) + j, v);
+#pragma unroll
+                        for (int w = 0; w < NW; w++)
+                            z[j][w] ^= v[w];
+                    }
+                }
+            }
+        }
+        pipelined<Tab, NX>([&](int j) { return row_tab<R>(p_Binv, vB, xrow(j), grow(xrow(j))); },
+                           [&](int j, const Tab &t) {
+                               const uint32_t p = grow(xrow(j));
+                               if (p)
+                                   scale<R>(z[j], t);
+                               store_chunk<R, LD>(wrow(ws.dst, fresh(p), rb), ln.off, ln.act, ln.nsym, z[j]);
+                           });
+        return;
+    }
+
+    if (INV_FIRST) {
+        if (KIND == W_D1)
+            pipelined<Tab, NX>([&](int j) { return row_tab<R>(rowtab, vRT, xrow(j), grow(xrow(j))); },
+                               [&](int j, const Tab &t) { dec_weigh<R>(x[j], rcv[j], t); });
+        reg_levels<R, TA, true, SH_ZERO, false>(x, (uint32_t)(NX * g), 0, twI);
+        if constexpr (T > 4) {
+#pragma unroll
+            for (int j = 0; j < 16; j++)
+                lds_put(cb, j, x[j]);
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < GPW; u++) {
+                const int r0 = wave * GPW + u;
+#pragma unroll
+                for (int j = 0; j < NR2; j++)
+                    lds_get(my + RS * r0, 16 * j, y[u][j]);
+                reg_levels<R, L2, true, SH_ZERO, false>(y[u], (uint32_t)r0, 4, twI);
+            }
+        }
+        if (KIND == W_E1 || KIND == W_D1) {
+            store_data(ws.dst);
+            return;
+        }
+        if (KIND == W_E2 && ws.dst2)                // coefficients read again by later blocks
+            store_data(ws.dst2);
+        if (KIND == W_D2) {
+            // d^d = B (.) coefficients, stored; then each point's partial sum
+            // over the clear local bits (the transform's high bits).  Each
+            // wave rewrites only the tile rows it read itself, so no barrier
+            // is needed before the exchange.
+            if constexpr (T > 4) {
+#pragma unroll
+                for (int u = 0; u < GPW; u++) {
+                    const int r0 = wave * GPW + u;
+                    pipelined<Tab, NR2>([&](int j) { return row_tab<R>(p_B, vB, r0 + 16 * j, grow(r0 + 16 * j)); },
+                                        [&](int j, const Tab &t) {
+                                            if (grow(r0 + 16 * j))
+                                                scale<R>(y[u][j], t);
+                                            lds_put(my + RS * r0, 16 * j, y[u][j]);
+                                        });
+                }
+                store_data(ws.dst);
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < GPW; u++) {
+                    const int r0 = wave * GPW + u;
+#pragma unroll
+                    for (int j = 0; j < NR2; j++) {
+                        uint32_t z[NW];
+                        zero_vec<R>(z);
+#pragma unroll
+                        for (int lv = 0; lv < L2; lv++)          // local partners 16 * 2^lv away
+                            if (!((j >> lv) & 1))
+#pragma unroll
+                                for (int w = 0; w < NW; w++)
+                                    z[w] ^= y[u][j + (1 << lv)][w];
+#pragma unroll
+                        for (int lv = 0; lv < 4; lv++) {         // local partners 2^lv away
+                            if (!((r0 >> lv) & 1)) {
+                                uint32_t v[NW];
+                                lds_get(my + RS * r0, (1 << lv) + 16 * j, v);
+#pragma unroll
+                                for (int w = 0; w < NW; w++)
+                                    z[w] ^= v[w];
+                            }
+                        }
+                        store_chunk<R, LD>(wrow(ws.dst2, fresh(grow(r0 + 16 * j)), rb), ln.off, ln.act, ln.nsym,
+                                           z);
+                    }
+                }
+            } else {
+                pipelined<Tab, NX>([&](int j) { return row_tab<R>(p_B, vB, j, grow(j)); },
+                                   [&](int j, const Tab &t) {
+                                       if (grow(j))
+                                           scale<R>(x[j], t);
+                                   });
+                store_data(ws.dst);
+#pragma unroll
+                for (int j = 0; j < NX; j++) {
+                    uint32_t z[NW];
+                    zero_vec<R>(z);
+#pragma unroll
+                    for (int lv = 0; lv < TA; lv++)
+                        if (!((j >> lv) & 1))
+#pragma unroll
+                            for (int w = 0; w < NW; w++)
+                                z[w] ^= x[j + (1 << lv)][w];
+                    store_chunk<R, LD>(wrow(ws.dst2, fresh(grow(j)), rb), ln.off, ln.act, ln.nsym, z);
+                }
+            }
+            return;
+        }
+        // W_E2 continues with the forward transform of parity block 1, whose
+        // highest levels start from the stride layout left in registers; each
+        // wave again rewrites only its own tile rows before the barrier.
+    }
+
+    if (FWD) {
+        if constexpr (T > 4) {
+#pragma unroll
+            for (int u = 0; u < GPW; u++) {
+                const int r0 = wave * GPW + u;
+                reg_levels<R, L2, false, SHF, false>(y[u], (uint32_t)r0, 4, twF);
+#pragma unroll
+                for (int j = 0; j < NR2; j++)
+                    lds_put(my + RS * r0, 16 * j, y[u][j]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < 16; j++)
+                lds_get(cb, j, x[j]);
+        }
+        reg_levels<R, TA, false, SHF, false>(x, (uint32_t)(NX * g), 0, twF);
+        if (KIND == W_D5) {
+            pipelined<Tab, NX>([&](int j) { return row_tab<R>(rowtab, vRT, xrow(j), grow(xrow(j))); },
+                               [&](int j, const Tab &t) {
+                                   dec_store<R, LD>(x[j], (int)grow(xrow(j)), st, ln, bits, [&](int) { return t; });
+                               });
+            return;
+        }
+#pragma unroll
+        for (int j = 0; j < NX; j++) {
+            const uint32_t p = grow(xrow(j));
+            if ((int)p < ws.dst_rows)
+                store_chunk<R, LD>(wrow(ws.dst, fresh(p), rb), ln.off, ln.act, ln.nsym, x[j]);
+        }
+    }
+}
+
+template <int T, int KIND, int LD>
+static hipError_t wide_launch_one(const WideArgs &a, const KPtrs &k, int ntiles, hipStream_t s)
+{
+    const size_t lds = WideLds<T, KIND>::BYTES;
+    hipLaunchKernelGGL((k_wide<T, KIND, LD>), dim3(ntiles), dim3(NB_WIDE_THREADS(T)), lds, s, a, k.tw, k.B, k.Binv,
+                       k.bits, k.rowtabs);
+    return hipGetLastError();
+}
+
+template <int T, int KIND, int LD>
+static hipError_t wide_prep_one()
+{
+    return hipFuncSetAttribute((const void *)k_wide<T, KIND, LD>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)WideLds<T, KIND>::BYTES);
+}
+
+template <int KIND, int LD>
+static hipError_t wide_launch_T(int T, const WideArgs &a, const KPtrs &k, int ntiles, hipStream_t s)
+{
+    switch (T) {
+    case 4: return wide_launch_one<4, KIND, LD>(a, k, ntiles, s);
+    case 5: return wide_launch_one<5, KIND, LD>(a, k, ntiles, s);
+    case 6: return wide_launch_one<6, KIND, LD>(a, k, ntiles, s);
+    case 7: return wide_launch_one<7, KIND, LD>(a, k, ntiles, s);
+    case 8: return wide_launch_one<8, KIND, LD>(a, k, ntiles, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int KIND, int LD>
+static hipError_t wide_prep_T()
+{
+    hipError_t e = hipSuccess, f;
+    if ((f = wide_prep_one<4, KIND, LD>()) != hipSuccess) e = f;
+    if ((f = wide_prep_one<5, KIND, LD>()) != hipSuccess) e = f;
+    if ((f = wide_prep_one<6, KIND, LD>()) != hipSuccess) e = f;
+    if ((f = wide_prep_one<7, KIND, LD>()) != hipSuccess) e = f;
+    if ((f = wide_prep_one<8, KIND, LD>()) != hipSuccess) e = f;
+    return e;
+}
+
+template <int LD>
+static hipError_t wide_launch_ld(int kind, int T, const WideArgs &a, const KPtrs &k, int ntiles, hipStream_t s)
+{
+    switch (kind) {
+    case W_E1: return wide_launch_T<W_E1, LD>(T, a, k, ntiles, s);
+    case W_E2: return wide_launch_T<W_E2, LD>(T, a, k, ntiles, s);
+    case W_E2F: return wide_launch_T<W_E2F, LD>(T, a, k, ntiles, s);
+    case W_E3: return wide_launch_T<W_E3, LD>(T, a, k, ntiles, s);
+    case W_D1: return wide_launch_T<W_D1, LD>(T, a, k, ntiles, s);
+    case W_D2: return wide_launch_T<W_D2, LD>(T, a, k, ntiles, s);
+    case W_D3: return wide_launch_T<W_D3, LD>(T, a, k, ntiles, s);
+    case W_D4: return wide_launch_T<W_D4, LD>(T, a, k, ntiles, s);
+    case W_D5: return wide_launch_T<W_D5, LD>(T, a, k, ntiles, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t wide_launch(int kind, int ld, int T, const WideArgs &a, const KPtrs &k, int ntiles, hipStream_t s)
+{
+    if (ntiles <= 0)
+        return hipSuccess;
+    return ld == LD_VEC ? wide_launch_ld<LD_VEC>(kind, T, a, k, ntiles, s)
+                        : wide_launch_ld<LD_SYM>(kind, T, a, k, ntiles, s);
+}
+
+hipError_t wide_prepare()
+{
+    hipError_t e = hipSuccess, f;
+#define NB_WPREP(K)                                                                                                \
+    if ((f = wide_prep_T<K, LD_VEC>()) != hipSuccess) e = f;                                                       \
+    if ((f = wide_prep_T<K, LD_SYM>()) != hipSuccess) e = f;
+    NB_WPREP(W_E1) NB_WPREP(W_E2) NB_WPREP(W_E2F) NB_WPREP(W_E3) NB_WPREP(W_D1) NB_WPREP(W_D2) NB_WPREP(W_D3)
+    NB_WPREP(W_D4) NB_WPREP(W_D5)
+#undef NB_WPREP
+    return e;
+}
+
+}  // namespace nb

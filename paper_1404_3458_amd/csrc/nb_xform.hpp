@@ -43,6 +43,7 @@ struct TwGlobal {
     static constexpr int TS = Traits<R>::TS;
     const uint32_t *__restrict__ tw;
     uint32_t l;
+    __device__ __forceinline__ uint32_t plus1(int i) const { return ((l >> i) & 1u) ? ~0u : 0u; }
     __device__ __forceinline__ typename Ops<R>::Tab tab(int i, uint32_t c) const
     {
         const uint32_t off = (1u << R) - (1u << (R - i));
@@ -52,54 +53,63 @@ struct TwGlobal {
     }
 };
 
-// Factor source for a transform over 2^LT points whose V words were staged
-// in LDS by stage_levels (level i at entries 2^LT - 2^(LT-i) + q), with the
-// S words still read from global memory.
+// Factor source for a group of 2^LT rows gbase + (j << lo) (gbase has no bit
+// in lo .. lo+LT-1) transformed at shift l, whose local levels i < LT are the
+// global levels lo + i.  The V words were staged in LDS by stage_levels
+// (local level i at entries 2^LT - 2^(LT-i) + q); the S words are read from
+// global memory.  A whole transform is the group lo = 0, gbase = 0.
 template <int R, int LT>
 struct TwLds {
     static constexpr int TS = Traits<R>::TS, NV = Ops<R>::NV;
     const uint32_t *__restrict__ tw;
     uint32_t l;
     const uint32_t *vt;
+    uint32_t lo = 0, gbase = 0;
+    __device__ __forceinline__ uint32_t plus1(int i) const { return ((l >> (lo + i)) & 1u) ? ~0u : 0u; }
     __device__ __forceinline__ typename Ops<R>::Tab tab(int i, uint32_t c) const
     {
-        const uint32_t off = (1u << R) - (1u << (R - i));
-        const uint32_t q = ((c ^ l) & ((1u << LT) - 1u)) >> (i + 1);
+        const int I = (int)lo + i;
+        const uint32_t off = (1u << R) - (1u << (R - I));
+        const uint32_t cg = gbase | (c << lo);
+        const uint32_t q = ((c ^ (l >> lo)) & ((1u << LT) - 1u)) >> (i + 1);
         const uint32_t e = fresh((1u << LT) - (1u << (LT - i)) + q);
-        return Ops<R>::prep_lds(vt + NV * e, tw + (size_t)TS * fresh(off + ((c ^ l) >> (i + 1))));
+        return Ops<R>::prep_lds(vt + NV * e, tw + (size_t)TS * fresh(off + ((cg ^ l) >> (I + 1))));
     }
 };
 
 // Cooperative copy (all threads of the block) of the V words of the factor
-// tables of a 2^LT-point transform at shift l into LDS, laid out as TwLds reads
-// them: level i holds the 2^(LT-i-1) entries starting at table index
-// 2^r - 2^(r-i) + ((l >> LT) << (LT - i - 1)).
+// tables TwLds reads: local level i holds the 2^(LT-i-1) entries starting at
+// table index 2^r - 2^(r-lo-i) + (((gbase ^ l) >> (lo + LT)) << (LT - i - 1)).
 template <int R, int LT>
 __device__ __forceinline__ void stage_levels(uint32_t *vt, const uint32_t *__restrict__ tw, uint32_t l, int tid,
-                                             int nthreads)
+                                             int nthreads, uint32_t lo = 0, uint32_t gbase = 0)
 {
     constexpr int TS = Traits<R>::TS, NV = Ops<R>::NV, H = 1 << LT;
     constexpr int PER = NV / 2;            // 8-byte pieces per entry
+    const uint32_t hi = (gbase ^ l) >> (lo + LT);
     for (int u = tid; u < (H - 1) * PER; u += nthreads) {
         const int e = u / PER, w = u % PER;
         const int m = H - 1 - e;                       // in [2^(LT-i-1), 2^(LT-i) - 1]
         const int i = LT - 1 - (31 - __builtin_clz((unsigned)m));
         const int q = e - (H - (H >> i));
-        const uint32_t g = (1u << R) - (1u << (R - i)) + ((l >> LT) << (LT - i - 1)) + (uint32_t)q;
+        const int I = (int)lo + i;
+        const uint32_t g = (1u << R) - (1u << (R - I)) + (hi << (LT - i - 1)) + (uint32_t)q;
         const uint2 v = *reinterpret_cast<const uint2 *>(tw + (size_t)TS * g + 2 * w);
         *reinterpret_cast<uint2 *>(vt + NV * e + 2 * w) = v;
     }
 }
 
-// Cooperative copy of the V words of `count` consecutive perm tables.
+// Cooperative copy of the V words of `count` perm tables: entries
+// first + (j << lo) of src for j < count.
 template <int R>
 __device__ __forceinline__ void stage_rows(uint32_t *vt, const uint32_t *__restrict__ src, int count, int tid,
-                                           int nthreads)
+                                           int nthreads, uint32_t lo = 0, uint32_t first = 0)
 {
     constexpr int TS = Traits<R>::TS, NV = Ops<R>::NV, PER = NV / 2;
     for (int u = tid; u < count * PER; u += nthreads) {
         const int e = u / PER, w = u % PER;
-        const uint2 v = *reinterpret_cast<const uint2 *>(src + (size_t)TS * e + 2 * w);
+        const size_t g = (size_t)first + ((size_t)e << lo);
+        const uint2 v = *reinterpret_cast<const uint2 *>(src + (size_t)TS * g + 2 * w);
         *reinterpret_cast<uint2 *>(vt + NV * e + 2 * w) = v;
     }
 }
@@ -116,6 +126,15 @@ __device__ __forceinline__ typename Ops<R>::Tab row_tab(const uint32_t *__restri
 {
     const uint32_t jj = fresh((uint32_t)j);
     return Ops<R>::prep_lds(vt + Ops<R>::NV * jj, g + (size_t)Traits<R>::TS * jj);
+}
+// The same for a table staged at a different position: LDS entry jl, global
+// entry jg.
+template <int R>
+__device__ __forceinline__ typename Ops<R>::Tab row_tab(const uint32_t *__restrict__ g, const uint32_t *vt, int jl,
+                                                        uint32_t jg)
+{
+    const uint32_t jj = fresh((uint32_t)jl);
+    return Ops<R>::prep_lds(vt + Ops<R>::NV * jj, g + (size_t)Traits<R>::TS * fresh(jg));
 }
 
 // One butterfly; m1 (all ones or zero, wave-uniform) adds the "plus 1" of the
@@ -195,9 +214,8 @@ __device__ __forceinline__ void reg_levels(uint32_t (*x)[Traits<R>::NW], uint32_
     };
     auto work = [&](int k, const Tab &tab) {
         const int t = block_level<T, INV>(k), blk = block_row<T, INV>(k);
-        const int i = LO + t;
         const bool zero = SH == SH_ZERO && CT_BASE && blk == 0;
-        const uint32_t m1 = (SH == SH_GENERAL && ((tw.l >> i) & 1u)) ? ~0u : 0u;
+        const uint32_t m1 = SH == SH_GENERAL ? tw.plus1(t + LO) : 0u;
 #pragma unroll
         for (int m = 0; m < (1 << t); m++) {
             bfly<R, INV>(x[blk + m], x[blk + m + (1 << t)], tab, zero, m1);
@@ -250,6 +268,54 @@ __device__ __forceinline__ void zero_vec(uint32_t *v)
 #pragma unroll
     for (int w = 0; w < Traits<R>::NW; w++)
         v[w] = 0;
+}
+
+__device__ __forceinline__ const uint8_t *row_ptr(const uint8_t *base, uint32_t t, uint64_t rb)
+{
+    return base + (uint64_t)t * rb;
+}
+__device__ __forceinline__ uint8_t *row_ptr(uint8_t *base, uint32_t t, uint64_t rb)
+{
+    return base + (uint64_t)t * rb;
+}
+
+// Decode step 2 (eq. hatF(l)), first half: fetch the received row of point
+// p (zeros when the point has none) and copy it to the output when decoding
+// out of place.  Returns whether the point was received.
+template <int R, int LD>
+__device__ __forceinline__ bool dec_fetch(uint32_t *raw, int p, const DevStripe &st, const Lane &ln,
+                                          const uint32_t *__restrict__ bits)
+{
+    const bool rcv = point_bit(bits, p);
+    const uint32_t tr = rcv ? (uint32_t)point_row(p, st) : 0u;
+    load_chunk<R, LD>(row_ptr(st.in, tr, st.row_bytes), ln.off, ln.act && rcv, ln.nsym, raw);
+    if (st.copy_survivors)
+        store_chunk<R, LD>(row_ptr(st.out, tr, st.row_bytes), ln.off, ln.act && rcv, ln.nsym, raw);
+    return rcv;
+}
+
+// Second half: x <- Pi(omega_p) x for a received point (x is zero otherwise).
+template <int R>
+__device__ __forceinline__ void dec_weigh(uint32_t *x, bool rcv, const typename Ops<R>::Tab &T)
+{
+    if (rcv)
+        scale<R>(x, T);
+}
+
+// Decode step 6 (eq. F(j)) for one point: erased stored rows get
+// Phi^d[p] / Pi'(omega_p); tabf(p) yields the point's perm table.
+template <int R, int LD, class TABF>
+__device__ __forceinline__ void dec_store(const uint32_t *v, int p_, const DevStripe &st, const Lane &ln,
+                                          const uint32_t *__restrict__ bits, const TABF &tabf)
+{
+    const int p = (int)fresh((uint32_t)p_);
+    if (point_bit(bits + bitmap_words(st.np), p)) {
+        const int t = point_row(p, st);
+        uint32_t o[Traits<R>::NW];
+        zero_vec<R>(o);
+        Ops<R>::mac(o, v, tabf(p));
+        store_chunk<R, LD>(row_ptr(st.out, (uint32_t)t, st.row_bytes), ln.off, ln.act, ln.nsym, o);
+    }
 }
 
 }  // namespace nb

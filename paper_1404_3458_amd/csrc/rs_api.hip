@@ -22,6 +22,8 @@ hipError_t init_tables(int r, const uint32_t *d_basis, uint32_t *d_Wv, uint32_t 
 hipError_t init_prepare(int r);
 hipError_t locator_launch(const LocatorArgs &a, const KPtrs &k, const uint32_t *fwht_L, const uint32_t *expt,
                           int nstripes, int max_np, hipStream_t s);
+hipError_t loc_pass_launch(const LocPassArgs &a, const KPtrs &k, const uint32_t *fwht_L, const uint32_t *expt,
+                           int ngroups, hipStream_t s);
 hipError_t fused_prepare_16();
 hipError_t fused_prepare_8();
 hipError_t fused_launch_16(int mode, int sh, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
@@ -32,8 +34,8 @@ hipError_t pass_launch(int r, int ld, int T, bool inv, bool gen_l, const PassArg
                        uint32_t nblocks, hipStream_t s);
 hipError_t dpart_launch(int r, int ld, int T, const DerivPassArgs &a, const KPtrs &k, uint32_t nblocks,
                         hipStream_t s);
-hipError_t dec_io_launch(int r, int ld, bool scatter, const DecodeIOArgs &a, const KPtrs &k, uint32_t nblocks,
-                         hipStream_t s);
+hipError_t wide_launch(int kind, int ld, int T, const WideArgs &a, const KPtrs &k, int ntiles, hipStream_t s);
+hipError_t wide_prepare();
 }  // namespace nb
 
 using namespace nb;
@@ -43,6 +45,12 @@ namespace {
 // MODE_ENC2: encode of a code with one parity block (n' = 2 k')
 enum { MODE_FFT = 0, MODE_IFFT = 1, MODE_DERIV = 2, MODE_ENC = 3, MODE_DEC = 4, MODE_ENC2 = 5 };
 constexpr int FUSED_MAX_L = 8;      // fused single-launch kernels cover h <= 256
+constexpr int LOC_ONE_WG_MAX = 4096; // larger mother codes use the multi-workgroup locator
+// pass kinds of nb_wide.hip
+enum { W_E1 = 0, W_E2 = 1, W_E2F = 2, W_E3 = 3, W_D1 = 4, W_D2 = 5, W_D3 = 6, W_D4 = 7, W_D5 = 8 };
+// scratch of the 8-level pass pipelines: stripes are processed in chunks
+// whose scratch fits this budget (a stripe larger than it runs alone)
+constexpr size_t WIDE_SCRATCH_BUDGET = (size_t)2 << 30;
 // Pinned host ring through which each call's descriptors reach the device.
 // Every upload occupies a byte range until the event recorded after its copy
 // completes; the host waits only when the ring is full, so it can run many
@@ -464,82 +472,12 @@ int big_scratch(Scratch *sc, size_t need, uint8_t **p)
     return rc;
 }
 
-int encode_large(rs_ctx *ctx, Scratch *sc, const Plan &pl)
-{
-    const DevStripe &ds = pl.ds;
-    const uint64_t rb = ds.row_bytes;
-    const int nblocks = ds.np / ds.kp;
-    uint8_t *A;
-    int rc = big_scratch(sc, (size_t)ds.kp * rb * (nblocks > 2 ? 2 : 1), &A);
-    if (rc)
-        return rc;
-    uint8_t *Bb = nblocks > 2 ? A + (size_t)ds.kp * rb : A;
-    // the scratch rows share the stripe's row length; they are aligned when the stripe is
-    rc = run_passes(ctx, sc->stream, true, false, pl.L, 0, ds.in, ds.k, A, nullptr, 0, 0, rb, ds.ncols,
-                    pl.aligned, false, false);
-    const int npar = ds.n - ds.k;
-    for (int blk = 1; !rc && blk < nblocks; blk++) {
-        const int first_par = (blk - 1) * ds.kp;
-        if (first_par >= npar)
-            break;
-        rc = run_passes(ctx, sc->stream, false, false, pl.L, (uint32_t)(blk * ds.kp), A, ds.kp, Bb,
-                        ds.out + (size_t)first_par * rb, 0, std::min(ds.kp, npar - first_par), rb, ds.ncols,
-                        pl.aligned, false, false);
-    }
-    return rc;
-}
-
-int decode_large(rs_ctx *ctx, Scratch *sc, const Plan &pl, const DevStripe &dsl, const KPtrs &kp)
-{
-    const DevStripe &ds = pl.ds;
-    const uint64_t rb = ds.row_bytes;
-    uint8_t *A;
-    int rc = big_scratch(sc, (size_t)ds.np * rb * 2, &A);
-    if (rc)
-        return rc;
-    uint8_t *Z = A + (size_t)ds.np * rb;
-    // step 2 (the locator has already run), step 3, step 4, step 5, step 6
-    for (const ColPart &cp : col_parts(pl.aligned, ds.ncols)) {
-        DecodeIOArgs io;
-        std::memset(&io, 0, sizeof(io));
-        io.st = dsl;
-        io.st.col0 = cp.col0;
-        io.A = A;
-        io.nct = cp.ntiles;
-        if (dev_err(ctx, dec_io_launch(ctx->r, cp.ld, false, io, kp, (uint32_t)(ds.np * cp.ntiles), sc->stream)))
-            return RS_EDEVICE;
-    }
-    rc = run_passes(ctx, sc->stream, true, false, pl.L, 0, A, ds.np, A, nullptr, 0, 0, rb, ds.ncols, pl.aligned,
-                    false, true);
-    if (!rc)
-        rc = run_deriv_passes(ctx, sc->stream, pl.L, A, Z, A, rb, ds.ncols, pl.aligned);
-    if (!rc)
-        rc = run_passes(ctx, sc->stream, false, false, pl.L, 0, A, ds.np, A, nullptr, 0, 0, rb, ds.ncols,
-                        pl.aligned, false, false);
-    for (const ColPart &cp : col_parts(pl.aligned, ds.ncols)) {
-        if (rc)
-            break;
-        DecodeIOArgs io;
-        std::memset(&io, 0, sizeof(io));
-        io.st = dsl;
-        io.st.col0 = cp.col0;
-        io.A = A;
-        io.nct = cp.ntiles;
-        if (dev_err(ctx, dec_io_launch(ctx->r, cp.ld, true, io, kp, (uint32_t)(ds.n * cp.ntiles), sc->stream)))
-            rc = RS_EDEVICE;
-    }
-    return rc;
-}
-
-// sh: 0 = shift zero, 1 = shift a nonzero multiple of h, 2 = any other shift
 hipError_t fused_launch(int r, int mode, int sh, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
                         hipStream_t s)
 {
     return r == 16 ? fused_launch_16(mode, sh, ld, L, a, k, ntiles, s)
                    : fused_launch_8(mode, sh, ld, L, a, k, ntiles, s);
 }
-
-// ------------------------------------------------------------------ codec driver
 
 // An encode whose mother code has a single parity block (n' = 2 k') runs a
 // kernel variant without the loop over parity blocks.
@@ -554,6 +492,174 @@ struct Entry {
     int plan;
     ColPart cp;
 };
+
+// ------------------------------------------------------------------ 8-level pass pipelines
+
+// One launch of the pass pipelines: descriptors [first, first + count) of
+// the uploaded array.
+struct WideLaunch {
+    int kind, ld, T, lo, blk;
+    size_t first, count;
+    int ntiles;
+};
+
+struct WidePlan {
+    std::vector<WideStripe> descs;
+    std::vector<WideLaunch> launches;
+    size_t scratch = 0;          // bytes of scratch the largest chunk needs
+};
+
+// Scratch rows a stripe needs (encode: coefficients unless they can live in
+// the parity rows, plus one parity block unless it is stored whole; decode:
+// n' transform rows and n' partial-sum rows).
+size_t wide_scratch_rows(const Plan &p)
+{
+    const DevStripe &d = p.ds;
+    if (p.decoding)
+        return 2 * (size_t)d.np;
+    const int npar = d.n - d.k;
+    const int nblocks = d.np / d.kp;
+    if (nblocks == 2 && npar == d.kp)
+        return 0;
+    return 2 * (size_t)d.kp;
+}
+
+// Split the wide stripes (plan indices, all with L > FUSED_MAX_L) into
+// chunks, lay out their scratch from `scratch_base` (null while sizing) and
+// list the launches: per chunk and transform size, every pass kind in order,
+// one launch per row-access variant.
+void plan_wide(const std::vector<Plan> &plans, const std::vector<int> &idx, bool decode, uint8_t *scratch_base,
+               WidePlan &wp)
+{
+    wp.descs.clear();
+    wp.launches.clear();
+    wp.scratch = 0;
+    // chunks in plan order
+    std::vector<std::pair<size_t, size_t>> chunks;     // [begin, end) into idx
+    size_t cur = 0, begin = 0;
+    for (size_t q = 0; q < idx.size(); q++) {
+        const Plan &p = plans[idx[q]];
+        const size_t need = wide_scratch_rows(p) * p.ds.row_bytes;
+        if (q > begin && cur + need > WIDE_SCRATCH_BUDGET) {
+            chunks.push_back({begin, q});
+            begin = q;
+            cur = 0;
+        }
+        cur += need;
+        wp.scratch = std::max(wp.scratch, cur);
+    }
+    if (begin < idx.size())
+        chunks.push_back({begin, idx.size()});
+
+    for (const auto &ch : chunks) {
+        // scratch of each stripe of the chunk
+        std::vector<uint8_t *> sA(ch.second - ch.first), sZ(ch.second - ch.first);
+        size_t off = 0;
+        for (size_t q = ch.first; q < ch.second; q++) {
+            const Plan &p = plans[idx[q]];
+            const size_t rows = wide_scratch_rows(p);
+            const size_t half = rows / 2 * p.ds.row_bytes;
+            sA[q - ch.first] = rows ? scratch_base + off : nullptr;
+            sZ[q - ch.first] = rows ? scratch_base + off + half : nullptr;
+            off += rows * p.ds.row_bytes;
+        }
+        // transform sizes present in the chunk
+        std::vector<int> Ns;
+        for (size_t q = ch.first; q < ch.second; q++)
+            if (std::find(Ns.begin(), Ns.end(), plans[idx[q]].L) == Ns.end())
+                Ns.push_back(plans[idx[q]].L);
+        std::sort(Ns.begin(), Ns.end());
+        for (int N : Ns) {
+            const int T1 = (N + 1) / 2, T2 = N - T1;
+            int max_blocks = 2;
+            for (size_t q = ch.first; q < ch.second; q++)
+                if (plans[idx[q]].L == N)
+                    max_blocks = std::max(max_blocks, plans[idx[q]].ds.np / plans[idx[q]].ds.kp);
+            // (kind, lo, T, blk) sequence
+            struct Step { int kind, lo, T, blk; };
+            std::vector<Step> steps;
+            if (decode) {
+                steps = {{W_D1, 0, T1, 0}, {W_D2, T1, T2, 0}, {W_D3, 0, T1, 0}, {W_D4, T1, T2, 0}, {W_D5, 0, T1, 0}};
+            } else {
+                steps = {{W_E1, 0, T1, 0}, {W_E2, T1, T2, 1}, {W_E3, 0, T1, 1}};
+                for (int b = 2; b < max_blocks; b++) {
+                    steps.push_back({W_E2F, T1, T2, b});
+                    steps.push_back({W_E3, 0, T1, b});
+                }
+            }
+            for (const Step &stp : steps) {
+                for (int ld = 0; ld < 2; ld++) {
+                    WideLaunch wl;
+                    wl.kind = stp.kind;
+                    wl.ld = ld;
+                    wl.T = stp.T;
+                    wl.lo = stp.lo;
+                    wl.blk = stp.blk;
+                    wl.first = wp.descs.size();
+                    int tiles = 0;
+                    for (size_t q = ch.first; q < ch.second; q++) {
+                        const Plan &p = plans[idx[q]];
+                        if (p.L != N)
+                            continue;
+                        const DevStripe &d = p.ds;
+                        const int npar = d.n - d.k;
+                        const int nblocks = d.np / d.kp;
+                        if (!decode && (stp.blk >= nblocks || (stp.blk - 1) * d.kp >= npar))
+                            continue;
+                        const uint64_t rb = d.row_bytes;
+                        uint8_t *A = sA[q - ch.first], *Z = sZ[q - ch.first];
+                        const bool in_parity = !decode && A == nullptr;   // (2k', k') code, not shortened
+                        uint8_t *coef = in_parity ? d.out : A;
+                        // parity block b goes straight to its rows when they are all stored
+                        auto block_buf = [&](int b) -> uint8_t * {
+                            if (in_parity)
+                                return d.out;
+                            return (size_t)b * d.kp <= (size_t)npar ? d.out + (size_t)(b - 1) * d.kp * rb : Z;
+                        };
+                        WideStripe w;
+                        std::memset(&w, 0, sizeof(w));
+                        w.st = d;
+                        w.src_rows = decode ? d.np : d.kp;
+                        w.dst_rows = decode ? d.np : d.kp;
+                        switch (stp.kind) {
+                        case W_E1: w.src = d.in; w.src_rows = d.k; w.dst = coef; break;
+                        case W_E2:
+                            w.src = coef;
+                            w.dst2 = nblocks > 2 ? coef : nullptr;
+                            w.dst = block_buf(1);
+                            break;
+                        case W_E2F: w.src = coef; w.dst = block_buf(stp.blk); break;
+                        case W_E3:
+                            w.src = block_buf(stp.blk);
+                            w.dst = d.out + (size_t)(stp.blk - 1) * d.kp * rb;
+                            w.dst_rows = std::min(d.kp, npar - (stp.blk - 1) * d.kp);
+                            break;
+                        case W_D1: w.dst = A; break;
+                        case W_D2: w.src = A; w.dst = A; w.dst2 = Z; break;
+                        case W_D3: w.src = A; w.src2 = Z; w.dst = A; break;
+                        case W_D4: w.src = A; w.dst = A; break;
+                        case W_D5: w.src = A; break;
+                        }
+                        for (const ColPart &cp : col_parts(p.aligned, d.ncols)) {
+                            if (cp.ld != ld)
+                                continue;
+                            WideStripe e = w;
+                            e.st.col0 = cp.col0;
+                            e.nct = cp.ntiles;
+                            e.tile0 = tiles;
+                            tiles += (1 << (N - stp.T)) * cp.ntiles;
+                            wp.descs.push_back(e);
+                        }
+                    }
+                    wl.count = wp.descs.size() - wl.first;
+                    wl.ntiles = tiles;
+                    if (wl.count)
+                        wp.launches.push_back(wl);
+                }
+            }
+        }
+    }
+}
 
 int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, int count, bool decode,
               hipStream_t stream)
@@ -643,17 +749,54 @@ int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, in
         }
         j = e;
     }
-    // Locator descriptors: one per active decode stripe.
-    std::vector<DevStripe> lds_((size_t)(decode ? m : 0));
-    for (int q = 0; decode && q < m; q++)
-        lds_[q] = plans[act[q]].ds;
+    // Locator descriptors: one per active decode stripe, those with a
+    // one-workgroup locator first; the others get a residue array each.
+    std::vector<DevStripe> lds_;
+    std::vector<size_t> locv_off;
+    size_t locv_words = 0;
+    int m_small = 0;
+    max_np = 1;
+    for (int pass = 0; decode && pass < 2; pass++)
+        for (int q = 0; q < m; q++) {
+            const DevStripe &d = plans[act[q]].ds;
+            if ((d.np <= LOC_ONE_WG_MAX) != (pass == 0))
+                continue;
+            lds_.push_back(d);
+            if (pass == 0) {
+                m_small++;
+                max_np = std::max(max_np, d.np);
+            } else {
+                locv_off.push_back(locv_words);
+                locv_words += (size_t)d.np;
+            }
+        }
 
-    // Device arena: [entries | locator stripes | point bitmaps | locator tables]
+    // Stripes over more than 256 points: 8-level pass pipelines.
+    std::vector<int> widx;
+    for (int q = 0; q < m; q++)
+        if (plans[act[q]].L > FUSED_MAX_L)
+            widx.push_back(act[q]);
+    WidePlan wp;
+    if (!widx.empty()) {
+        uint8_t *wscr = nullptr;
+        plan_wide(plans, widx, decode, nullptr, wp);
+        if (wp.scratch) {
+            const int rc = big_scratch(sc, wp.scratch, &wscr);
+            if (rc)
+                return rc;
+        }
+        plan_wide(plans, widx, decode, wscr, wp);
+    }
+
+    // Device arena: [entries | locator stripes | point bitmaps | pass
+    // descriptors | locator tables]
     const size_t off_loc = align_up(sizeof(DevStripe) * ne, 256);
     const size_t off_bits = align_up(off_loc + sizeof(DevStripe) * lds_.size(), 256);
-    const size_t off_rt = align_up(off_bits + bit_words * 4, 256);
+    const size_t off_wide = align_up(off_bits + bit_words * 4, 256);
+    const size_t off_rt = align_up(off_wide + sizeof(WideStripe) * wp.descs.size(), 256);
     const size_t host_bytes = off_rt;
-    const size_t dev_bytes = off_rt + rt_dwords * 4;
+    const size_t off_locv = align_up(off_rt + rt_dwords * 4, 256);
+    const size_t dev_bytes = off_locv + locv_words * 4;
     int rc = ensure_dev(sc, &sc->dev, &sc->dev_cap, dev_bytes);
     if (rc)
         return rc;
@@ -661,8 +804,10 @@ int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, in
     std::vector<uint8_t> host(host_bytes, 0);
     if (ne)
         std::memcpy(host.data(), eds.data(), sizeof(DevStripe) * ne);
+    if (!wp.descs.empty())
+        std::memcpy(host.data() + off_wide, wp.descs.data(), sizeof(WideStripe) * wp.descs.size());
     if (decode) {
-        std::memcpy(host.data() + off_loc, lds_.data(), sizeof(DevStripe) * m);
+        std::memcpy(host.data() + off_loc, lds_.data(), sizeof(DevStripe) * lds_.size());
         uint32_t *bits = (uint32_t *)(host.data() + off_bits);
         for (int q = 0; q < m; q++) {
             const Plan &p = plans[act[q]];
@@ -695,8 +840,22 @@ int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, in
         LocatorArgs la;
         la.stripes = (const DevStripe *)(dev + off_loc);
         la.r = ctx->r;
-        if (dev_err(ctx, locator_launch(la, kp, ctx->d_FL, ctx->d_exp, m, max_np, stream)))
+        if (dev_err(ctx, locator_launch(la, kp, ctx->d_FL, ctx->d_exp, m_small, max_np, stream)))
             return RS_EDEVICE;
+        for (size_t q = m_small; q < lds_.size(); q++) {
+            const int N = ilog2(lds_[q].np), T1 = (N + 1) / 2, T2 = N - T1;
+            LocPassArgs pa;
+            pa.stripe = la.stripes + q;
+            pa.v = (uint32_t *)(dev + off_locv) + locv_off[q - m_small];
+            pa.r = ctx->r;
+            for (int kind = 0; kind < 4; kind++) {
+                pa.kind = kind;
+                pa.lo = (kind & 1) ? T1 : 0;
+                pa.T = (kind & 1) ? T2 : T1;
+                if (dev_err(ctx, loc_pass_launch(pa, kp, ctx->d_FL, ctx->d_exp, 1 << (N - pa.T), stream)))
+                    return RS_EDEVICE;
+            }
+        }
     }
     const DevStripe *d_ents = (const DevStripe *)dev;
     for (int j = 0; j < ne;) {
@@ -716,13 +875,15 @@ int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, in
             return RS_EDEVICE;
         j = e;
     }
-    for (int q = 0; q < m; q++) {
-        const Plan &p = plans[act[q]];
-        if (p.L <= FUSED_MAX_L)
-            continue;
-        rc = decode ? decode_large(ctx, sc, p, lds_[q], kp) : encode_large(ctx, sc, p);
-        if (rc)
-            return rc;
+    const WideStripe *d_wide = (const WideStripe *)(dev + off_wide);
+    for (const WideLaunch &wl : wp.launches) {
+        WideArgs wa;
+        wa.stripes = d_wide + wl.first;
+        wa.nstripes = (int)wl.count;
+        wa.lo = wl.lo;
+        wa.blk = wl.blk;
+        if (dev_err(ctx, wide_launch(wl.kind, wl.ld, wl.T, wa, kp, wl.ntiles, stream)))
+            return RS_EDEVICE;
     }
     return RS_OK;
 }
@@ -863,7 +1024,8 @@ __attribute__((visibility("default"))) int rs_init(int r, const uint32_t *basis,
         hipError_t e1 = fused_prepare_16();
         hipError_t e2 = fused_prepare_8();
         hipError_t e3 = init_prepare(16);
-        prep_err = e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3);
+        hipError_t e4 = wide_prepare();
+        prep_err = e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : (e3 != hipSuccess ? e3 : e4));
     });
     if (prep_err != hipSuccess) {
         delete ctx;

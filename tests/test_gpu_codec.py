@@ -12,6 +12,9 @@ from gpu_util import first_diff, rand_rows, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 SHAPES16 = [(4, 2), (16, 8), (64, 48), (256, 128), (256, 224), (40, 7), (1024, 512), (4096, 2048)]
+# more than 256 points: 8-level pass pipelines (low / high level split 5+4 .. 7+6),
+# shortened mother codes, and codes with several parity blocks
+SHAPES16_WIDE = [(512, 256), (2048, 1024), (8192, 4096), (600, 500), (1000, 300), (2048, 512), (300, 200)]
 SHAPES8 = [(2, 1), (16, 8), (12, 8), (10, 3), (64, 48), (256, 128), (200, 100)]
 
 
@@ -31,7 +34,7 @@ def _encode_check(c, r, n, k, ncols, key):
     return msg, exp
 
 
-@pytest.mark.parametrize("n,k", SHAPES16)
+@pytest.mark.parametrize("n,k", SHAPES16 + SHAPES16_WIDE)
 def test_encode_r16(codec16, n, k):
     for ncols in _cols(n):
         _encode_check(codec16, 16, n, k, ncols, 1)
@@ -62,7 +65,7 @@ def _decode_check(c, r, n, k, ncols, e, key, inplace):
     assert (got == cw).all(), (r, n, k, ncols, e, first_diff(got, cw))
 
 
-@pytest.mark.parametrize("n,k", SHAPES16)
+@pytest.mark.parametrize("n,k", SHAPES16 + SHAPES16_WIDE)
 def test_decode_r16(codec16, n, k):
     for ncols in _cols(n):
         for e, inplace in ((n - k, True), ((n - k) // 2, False), (1, True)):
@@ -110,7 +113,8 @@ def test_c3_shape_encode_decode(codec16):
 
 
 def test_batch_mixed_shapes(codec16):
-    specs = [(16, 8, 1000), (64, 48, 514), (256, 224, 2050), (1024, 512, 300), (256, 128, 4096), (16, 8, 2)]
+    specs = [(16, 8, 1000), (64, 48, 514), (256, 224, 2050), (1024, 512, 300), (256, 128, 4096), (16, 8, 2),
+             (4096, 2048, 72), (512, 256, 6), (1000, 300, 520), (1024, 512, 8)]
     msgs, pars, exps = [], [], []
     for i, (n, k, rb) in enumerate(specs):
         m = rand_rows(k, rb, 55, i)
