@@ -40,6 +40,10 @@ CONFIGS = {
     "c3": dict(r=16, n=65536, k=32768, stripes=1, shard_bytes=256, erasures=32768,
                workload="GF(2^16) mod 0x1100B, (n,k)=(65536,32768), 1 stripe x 256 B shards, "
                         "encode + 32768 erasures + decode"),
+    "c4": dict(r=16, stripes=8192, mixed=True,
+               workload="GF(2^16) mod 0x1100B, 8192 stripes, (n,k) uniform over (16,8) (64,48) (256,224) "
+                        "(1024,512) (4096,2048), shards log-uniform 1-64 KiB, erasures uniform in [0,n-k]; "
+                        "encode + decode, batched plans replayed as a HIP graph vs per-stripe calls"),
 }
 
 
@@ -155,6 +159,172 @@ def cpu_baseline(cfg, sample_stripes, sample_cols, threads):
                       "%.2f s wall" % (sample_stripes, cols, nbytes, dt)}
 
 
+def run_mixed(args, cfg):
+    """The mixed-stripe workload: every stripe encoded and then decoded in
+    place per step, as one encode plan and one decode plan replayed in a HIP
+    graph; also timed as batched calls and as per-stripe calls, overall and
+    per (n, k) class."""
+    import numpy as np
+    import torch
+
+    from paper_1404_3458_amd import rs, synth
+
+    ns = args.stripes or cfg["stripes"]
+    shapes = synth.mixed_stripes(cfg["id"], ns)
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    offs, total = [], 0
+    for n, k, sb, e in shapes:
+        offs.append(total)
+        total += (n * sb + 255) // 256 * 256
+    buf = torch.empty(total, dtype=torch.uint8, device=dev)
+    cws = [buf[offs[s]:offs[s] + n * sb].view(n, sb) for s, (n, k, sb, e) in enumerate(shapes)]
+    for s, (n, k, sb, e) in enumerate(shapes):
+        synth.fill_random_torch(synth.key(cfg["id"], s, synth.DATA), cws[s][:k])
+    masks = [synth.erasure_mask(synth.key(cfg["id"], s, synth.ERASURE), n, e) for s, (n, k, sb, e) in
+             enumerate(shapes)]
+    codec = rs.Codec(16)
+    stream = torch.cuda.current_stream()
+    enc_list = [(n, k, cws[s][:k], cws[s][k:]) for s, (n, k, sb, e) in enumerate(shapes)]
+    dec_list = [(n, k, masks[s], cws[s], cws[s]) for s, (n, k, sb, e) in enumerate(shapes)]
+    enc_b, dec_b = codec.prepare_encode_batch(enc_list), codec.prepare_decode_batch(dec_list)
+    msg_bytes = sum(k * sb for n, k, sb, e in shapes)
+    cw_bytes = sum(n * sb for n, k, sb, e in shapes)
+
+    codec.encode_batch(enc_b)
+    torch.cuda.synchronize()
+    if not args.no_check:
+        # recovery of zeroed erasures on a sample of stripes of every class,
+        # and parity against the oracle on sampled columns of one per class
+        import oracle
+
+        sample = []
+        for c in synth.MIXED_CLASSES:
+            sample += [s for s, sh in enumerate(shapes) if sh[:2] == c][:3]
+        ref = {s: cws[s].clone() for s in sample}
+        for s, (n, k, sb, e) in enumerate(shapes):
+            if e:
+                cws[s][torch.from_numpy(masks[s]).bool().to(dev)] = 0
+        codec.decode_batch(dec_b)
+        torch.cuda.synchronize()
+        for s in sample:
+            assert torch.equal(cws[s], ref[s]), ("decode did not restore stripe", s, shapes[s])
+        for c in synth.MIXED_CLASSES:
+            s = next(t for t, sh in enumerate(shapes) if sh[:2] == c)
+            n, k, sb, e = shapes[s]
+            cols = list(range(0, sb // 2, max(1, sb // 2 // 8)))[:8]
+            host = cws[s].cpu().numpy().reshape(n, sb // 2, 2)[:, cols, :].reshape(n, len(cols) * 2)
+            assert (oracle.encode(16, n, k, np.ascontiguousarray(host[:k])) == host[k:]).all(), ("parity", c)
+        del ref
+
+    def timed(fn, reps):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a, b in evs:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / reps
+        return wall, np.array([a.elapsed_time(b) for a, b in evs])
+
+    def graph_of(plans):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for p_ in plans:
+                p_.launch()
+        return g
+
+    # batched plans in a graph (the measured configuration)
+    pe, pd = codec.plan_encode_batch(enc_b), codec.plan_decode_batch(dec_b)
+    g = graph_of([pe, pd])
+    for _ in range(args.warmup):
+        g.replay()
+    wall_g, ev_g = timed(g.replay, args.steps)
+    # batched calls (planned on every call)
+    for _ in range(max(1, args.warmup // 2)):
+        codec.encode_batch(enc_b)
+        codec.decode_batch(dec_b)
+    wall_b, ev_b = timed(lambda: (codec.encode_batch(enc_b), codec.decode_batch(dec_b)), max(2, args.steps // 2))
+
+    def per_stripe(idx):
+        for s in idx:
+            n, k, sb, e = shapes[s]
+            codec.encode(n, k, cws[s][:k], cws[s][k:])
+        for s in idx:
+            n, k, sb, e = shapes[s]
+            codec.decode(n, k, masks[s], cws[s])
+
+    per_class = {}
+    wall_ps_total = 0.0
+    for c in synth.MIXED_CLASSES:
+        idx = [s for s, sh in enumerate(shapes) if sh[:2] == c]
+        if not idx:
+            continue
+        cb = sum(shapes[s][1] * shapes[s][2] for s in idx)
+        pce = codec.plan_encode_batch([enc_list[s] for s in idx])
+        pcd = codec.plan_decode_batch([dec_list[s] for s in idx])
+        gc = graph_of([pce, pcd])
+        gc.replay()
+        wall_c, _ = timed(gc.replay, 3)
+        per_stripe(idx)
+        wall_p, _ = timed(lambda: per_stripe(idx), 1)
+        wall_ps_total += wall_p
+        per_class["%d,%d" % c] = {"stripes": len(idx), "msg_GB": round(cb / 1e9, 3),
+                                  "graph_ms": round(wall_c, 3), "per_stripe_ms": round(wall_p, 3),
+                                  "graph_msg_GBps": round(cb / wall_c / 1e6, 1),
+                                  "per_stripe_msg_GBps": round(cb / wall_p / 1e6, 1),
+                                  "factor": round(wall_p / wall_c, 2)}
+        pce.close()
+        pcd.close()
+        del gc
+    value = msg_bytes / (wall_g * 1e-3) / 1e9
+    hbm = 2 * cw_bytes / (wall_g * 1e-3) / 1e9        # encode n*S + decode n*S per stripe
+    mults = sum(sb // 2 * (paper_mults_per_column(n, k, False) + paper_mults_per_column(n, k, True))
+                for n, k, sb, e in shapes)
+    peak = mult_peak_per_s(16)
+    out = {
+        "metric": "RS encode/decode GB/s of message data (% HBM peak); batched vs per-stripe; p99",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall_g, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16",
+        "data": "synthetic (seeded splitmix64 bytes, shapes and erasure subsets)",
+        "config": {"workload": cfg["workload"], "field_bits": 16, "stripes": ns,
+                   "message_GB": round(msg_bytes / 1e9, 2), "codeword_GB": round(cw_bytes / 1e9, 2),
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": round(mults / (wall_g * 1e-3) / 1e12, 4),
+                     "peak": round(peak / 1e12, 4), "unit": "Tmul/s",
+                     "frac": round(mults / (wall_g * 1e-3) / peak, 4), "traffic": None,
+                     "kernel": "whole step (encode and decode plans of every class)",
+                     "algorithmic_mults_per_step": mults, "algorithmic_bytes_per_step": 2 * cw_bytes,
+                     "hbm_GBps": round(hbm, 1), "hbm_peak_GBps": HBM_PEAK_GBS,
+                     "hbm_frac": round(hbm / HBM_PEAK_GBS, 4)},
+        "cpu_baseline": None,
+        "detail": {
+            "graph_step_ms_p50": round(float(np.percentile(ev_g, 50)), 3),
+            "graph_step_ms_p99": round(float(np.percentile(ev_g, 99)), 3),
+            "batched_call_step_ms": round(wall_b, 3),
+            "batched_call_step_ms_p99": round(float(np.percentile(ev_b, 99)), 3),
+            "per_stripe_step_ms": round(wall_ps_total, 3),
+            "graph_over_per_stripe": round(wall_ps_total / wall_g, 2),
+            "batched_calls_over_per_stripe": round(wall_ps_total / wall_b, 2),
+            "per_class": per_class,
+        },
+    }
+    print(json.dumps(out))
+    pe.close()
+    pd.close()
+    codec.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +336,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-per-stripe", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--stripes", type=int, default=0, help="mixed workload: stripe count (default 8192)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy --steps times (the reference "
                          "kernel that scales the HBM byte counters)")
@@ -191,7 +362,9 @@ def main():
         return
 
     cfg = dict(CONFIGS[args.config])
-    cfg["id"] = {"c1": 1, "c2": 2, "c3": 3}[args.config]
+    cfg["id"] = {"c1": 1, "c2": 2, "c3": 3, "c4": 4}[args.config]
+    if cfg.get("mixed"):
+        return run_mixed(args, cfg)
     r, n, k, S, ns, e = cfg["r"], cfg["n"], cfg["k"], cfg["shard_bytes"], cfg["stripes"], cfg["erasures"]
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)

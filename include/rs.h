@@ -115,6 +115,25 @@ int rs_encode_batch(rs_ctx *ctx, const rs_stripe_desc *descs, int count, void *s
 int rs_decode_batch(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks,
                     int count, void *stream);
 
+/* Reusable batch plans (the batched calls above, planned once).  A plan
+ * validates its stripes, builds their descriptors and point bitmaps and
+ * allocates their scratch once, on the context's device; rs_plan_launch then
+ * queues only kernels and device-to-device copies (no host-to-device copy,
+ * no allocation), so a launch can be captured in a HIP graph and replayed.
+ * The buffers the descriptors name must stay valid for the plan's life; their
+ * contents may change between launches (a decode plan fixes the erasure
+ * pattern).  Launches of one plan must be ordered (one stream, or events):
+ * the plan's locator tables live in its own device memory.  Errors as for
+ * the batched calls; RS_ENOMEM if the plan's device memory cannot be
+ * allocated. */
+typedef struct rs_plan rs_plan;
+int rs_plan_encode_batch(rs_ctx *ctx, const rs_stripe_desc *descs, int count, rs_plan **out);
+int rs_plan_decode_batch(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, int count,
+                         rs_plan **out);
+int rs_plan_launch(rs_plan *plan, void *stream);
+/* Waits for the device, then frees the plan (NULL is a no-op). */
+void rs_plan_free(rs_plan *plan);
+
 /* Wait for all work of this context on `stream`; reports deferred device
  * errors. */
 int rs_sync(rs_ctx *ctx, void *stream);

@@ -661,13 +661,50 @@ void plan_wide(const std::vector<Plan> &plans, const std::vector<int> &idx, bool
     }
 }
 
-int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, int count, bool decode,
-              hipStream_t stream)
+// A codec call turned into device work: the image of its device arena
+// (descriptors, locator stripes, point bitmaps, pass descriptors; then room
+// for the locator tables and residues the kernels write) and the list of
+// launches.  Built on the host from the call's arguments; executed by
+// exec_codec on any stream, with the arena at any device address.
+struct FusedLaunch {
+    int mode, ld, L;
+    size_t first, count;       // entries of the descriptor array
+    int ntiles;
+};
+
+struct LocLarge {
+    size_t q;                  // index in the locator stripes
+    int N;
+    size_t v_off;              // dword offset of its residues
+};
+
+struct CodecPlan {
+    bool decode = false;
+    std::vector<uint8_t> host;                 // arena image (host_bytes)
+    size_t dev_bytes = 0;
+    size_t off_loc = 0, off_bits = 0, off_wide = 0, off_rt = 0, off_locv = 0;
+    std::vector<FusedLaunch> fused;
+    int m_small = 0, max_np = 1;
+    std::vector<LocLarge> loc_large;
+    WidePlan wp;
+    // decode stripes without erasures, copied when out != in
+    std::vector<std::pair<uint8_t *, const uint8_t *>> copies;
+    std::vector<size_t> copy_bytes;
+    bool empty() const { return fused.empty() && wp.launches.empty() && copies.empty() && m_small == 0 && loc_large.empty(); }
+};
+
+// Validate the call and build its plan.  `scratch` gives the scratch of the
+// 8-level passes: called with (nullptr, &need) to size it, then with a
+// buffer of that size.
+int build_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, int count, bool decode,
+                uint8_t *scratch, size_t *scratch_need, CodecPlan &cp)
 {
     if (!ctx || (count > 0 && !descs) || count < 0)
         return RS_EINVAL;
     if (decode && count > 0 && !masks)
         return RS_EINVAL;
+    cp = CodecPlan();
+    cp.decode = decode;
     std::vector<Plan> plans((size_t)count);
     size_t mask_total = 0;
     for (int i = 0; i < count; i++) {
@@ -679,15 +716,6 @@ int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, in
         if (decode)
             mask_total += (size_t)descs[i].n;
     }
-    DeviceGuard guard(ctx->device);
-    if (!guard.ok)
-        return RS_EDEVICE;
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    if (ctx->sticky)
-        return ctx->sticky;
-    Scratch *sc = get_scratch(ctx, stream);
-    if (!sc)
-        return RS_ENOMEM;
 
     // Active stripes: with columns and, for decode, at least one erasure.
     std::vector<int> act;
@@ -696,22 +724,19 @@ int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, in
         if (p.ds.ncols == 0)
             continue;
         if (decode && p.erasures == 0) {
-            if (p.ds.copy_survivors &&
-                dev_err(ctx, hipMemcpyAsync(p.ds.out, p.ds.in, (size_t)p.ds.n * p.ds.row_bytes,
-                                            hipMemcpyDeviceToDevice, stream)))
-                return RS_EDEVICE;
+            if (p.ds.copy_survivors) {
+                cp.copies.push_back({p.ds.out, p.ds.in});
+                cp.copy_bytes.push_back((size_t)p.ds.n * p.ds.row_bytes);
+            }
             continue;
         }
         act.push_back(i);
     }
-    if (act.empty())
-        return RS_OK;
     const int m = (int)act.size();
     const int ts = ctx->r == 16 ? TAB16 : TAB8;
 
     // Per-stripe device data (decode): point bitmaps and locator tables.
     size_t bit_words = 0, rt_dwords = 0;
-    int max_np = 1;
     for (int q = 0; q < m; q++) {
         Plan &p = plans[act[q]];
         if (decode) {
@@ -719,26 +744,25 @@ int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, in
             bit_words += 2 * (size_t)((p.ds.np + 31) / 32);
             p.ds.rowtab_off = rt_dwords;
             rt_dwords += (size_t)p.ds.np * ts;
-            max_np = std::max(max_np, p.ds.np);
         }
     }
-    // Launch entries for the fused path, grouped by (L, access variant).
+    // Fused-path entries, grouped by launch key.
     std::vector<Entry> ents;
     for (int q = 0; q < m; q++) {
         const Plan &p = plans[act[q]];
         if (p.L > FUSED_MAX_L)
             continue;
-        for (const ColPart &cp : col_parts(p.aligned, p.ds.ncols))
-            ents.push_back({act[q], cp});
+        for (const ColPart &c : col_parts(p.aligned, p.ds.ncols))
+            ents.push_back({act[q], c});
     }
-    std::stable_sort(ents.begin(), ents.end(), [&](const Entry &a, const Entry &b) {
-        const int ka = launch_key(plans[a.plan], a.cp.ld), kb = launch_key(plans[b.plan], b.cp.ld);
-        return ka < kb;
+    std::stable_sort(ents.begin(), ents.end(), [&](const Entry &x, const Entry &y) {
+        return launch_key(plans[x.plan], x.cp.ld) < launch_key(plans[y.plan], y.cp.ld);
     });
     const int ne = (int)ents.size();
     std::vector<DevStripe> eds((size_t)ne);
     for (int j = 0; j < ne;) {
-        const int key = launch_key(plans[ents[j].plan], ents[j].cp.ld);
+        const Plan &pj = plans[ents[j].plan];
+        const int key = launch_key(pj, ents[j].cp.ld);
         int e = j, tiles = 0;
         while (e < ne && launch_key(plans[ents[e].plan], ents[e].cp.ld) == key) {
             eds[e] = plans[ents[e].plan].ds;
@@ -747,136 +771,123 @@ int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, in
             tiles += ents[e].cp.ntiles;
             e++;
         }
+        FusedLaunch fl;
+        fl.mode = decode ? MODE_DEC : (one_parity_block(pj) ? MODE_ENC2 : MODE_ENC);
+        fl.ld = ents[j].cp.ld;
+        fl.L = pj.L;
+        fl.first = (size_t)j;
+        fl.count = (size_t)(e - j);
+        fl.ntiles = tiles;
+        cp.fused.push_back(fl);
         j = e;
     }
-    // Locator descriptors: one per active decode stripe, those with a
-    // one-workgroup locator first; the others get a residue array each.
+    // Locator descriptors: those with a one-workgroup locator first; the
+    // others get a residue array each.
     std::vector<DevStripe> lds_;
-    std::vector<size_t> locv_off;
     size_t locv_words = 0;
-    int m_small = 0;
-    max_np = 1;
     for (int pass = 0; decode && pass < 2; pass++)
         for (int q = 0; q < m; q++) {
             const DevStripe &d = plans[act[q]].ds;
             if ((d.np <= LOC_ONE_WG_MAX) != (pass == 0))
                 continue;
-            lds_.push_back(d);
             if (pass == 0) {
-                m_small++;
-                max_np = std::max(max_np, d.np);
+                cp.m_small++;
+                cp.max_np = std::max(cp.max_np, d.np);
             } else {
-                locv_off.push_back(locv_words);
+                cp.loc_large.push_back({lds_.size(), ilog2(d.np), locv_words});
                 locv_words += (size_t)d.np;
             }
+            lds_.push_back(d);
         }
-
     // Stripes over more than 256 points: 8-level pass pipelines.
     std::vector<int> widx;
     for (int q = 0; q < m; q++)
         if (plans[act[q]].L > FUSED_MAX_L)
             widx.push_back(act[q]);
-    WidePlan wp;
     if (!widx.empty()) {
-        uint8_t *wscr = nullptr;
-        plan_wide(plans, widx, decode, nullptr, wp);
-        if (wp.scratch) {
-            const int rc = big_scratch(sc, wp.scratch, &wscr);
-            if (rc)
-                return rc;
-        }
-        plan_wide(plans, widx, decode, wscr, wp);
+        plan_wide(plans, widx, decode, scratch, cp.wp);
+        if (scratch_need)
+            *scratch_need = cp.wp.scratch;
+    } else if (scratch_need) {
+        *scratch_need = 0;
     }
 
-    // Device arena: [entries | locator stripes | point bitmaps | pass
-    // descriptors | locator tables]
-    const size_t off_loc = align_up(sizeof(DevStripe) * ne, 256);
-    const size_t off_bits = align_up(off_loc + sizeof(DevStripe) * lds_.size(), 256);
-    const size_t off_wide = align_up(off_bits + bit_words * 4, 256);
-    const size_t off_rt = align_up(off_wide + sizeof(WideStripe) * wp.descs.size(), 256);
-    const size_t host_bytes = off_rt;
-    const size_t off_locv = align_up(off_rt + rt_dwords * 4, 256);
-    const size_t dev_bytes = off_locv + locv_words * 4;
-    int rc = ensure_dev(sc, &sc->dev, &sc->dev_cap, dev_bytes);
-    if (rc)
-        return rc;
-    uint8_t *dev = (uint8_t *)sc->dev;
-    std::vector<uint8_t> host(host_bytes, 0);
+    // Arena: [entries | locator stripes | point bitmaps | pass descriptors |
+    // locator tables | locator residues]; the first four are uploaded.
+    cp.off_loc = align_up(sizeof(DevStripe) * ne, 256);
+    cp.off_bits = align_up(cp.off_loc + sizeof(DevStripe) * lds_.size(), 256);
+    cp.off_wide = align_up(cp.off_bits + bit_words * 4, 256);
+    cp.off_rt = align_up(cp.off_wide + sizeof(WideStripe) * cp.wp.descs.size(), 256);
+    cp.off_locv = align_up(cp.off_rt + rt_dwords * 4, 256);
+    cp.dev_bytes = cp.off_locv + locv_words * 4;
+    cp.host.assign(cp.off_rt, 0);
     if (ne)
-        std::memcpy(host.data(), eds.data(), sizeof(DevStripe) * ne);
-    if (!wp.descs.empty())
-        std::memcpy(host.data() + off_wide, wp.descs.data(), sizeof(WideStripe) * wp.descs.size());
+        std::memcpy(cp.host.data(), eds.data(), sizeof(DevStripe) * ne);
+    if (!cp.wp.descs.empty())
+        std::memcpy(cp.host.data() + cp.off_wide, cp.wp.descs.data(), sizeof(WideStripe) * cp.wp.descs.size());
     if (decode) {
-        std::memcpy(host.data() + off_loc, lds_.data(), sizeof(DevStripe) * lds_.size());
-        uint32_t *bits = (uint32_t *)(host.data() + off_bits);
+        if (!lds_.empty())
+            std::memcpy(cp.host.data() + cp.off_loc, lds_.data(), sizeof(DevStripe) * lds_.size());
+        uint32_t *bits = (uint32_t *)(cp.host.data() + cp.off_bits);
         for (int q = 0; q < m; q++) {
             const Plan &p = plans[act[q]];
             const uint8_t *mk = masks + p.mask_src;
             const int W = (p.ds.np + 31) / 32;
             uint32_t *rx = bits + p.ds.bits_off, *er = rx + W;
-            for (int pt = 0; pt < p.ds.np; pt++) {
-                int t = -1;
-                if (pt < p.ds.k)
-                    t = pt;
-                else if (pt >= p.ds.kp && pt - p.ds.kp < p.ds.n - p.ds.k)
-                    t = p.ds.k + (pt - p.ds.kp);
-                if (t < 0)
-                    continue;
-                if (mk[t])
-                    er[pt >> 5] |= 1u << (pt & 31);
-                else
-                    rx[pt >> 5] |= 1u << (pt & 31);
+            // message rows are points 0..k-1, parity row t is point k' + t
+            for (int t = 0; t < p.ds.n; t++) {
+                const int pt = t < p.ds.k ? t : p.ds.kp + (t - p.ds.k);
+                uint32_t *w = mk[t] ? er : rx;
+                w[pt >> 5] |= 1u << (pt & 31);
             }
         }
     }
-    rc = stage_upload(sc, host.data(), host_bytes, dev);
-    if (rc)
-        return rc;
-    KPtrs kp = ctx->kp;
-    kp.bits = (const uint32_t *)(dev + off_bits);
-    kp.rowtabs = (const uint32_t *)(dev + off_rt);
+    return RS_OK;
+}
 
-    if (decode) {
-        LocatorArgs la;
-        la.stripes = (const DevStripe *)(dev + off_loc);
-        la.r = ctx->r;
-        if (dev_err(ctx, locator_launch(la, kp, ctx->d_FL, ctx->d_exp, m_small, max_np, stream)))
+// Queue a built plan on `stream` with its arena at `dev` (the uploaded part
+// already in place).  Launches kernels and device-to-device copies only.
+int exec_codec(rs_ctx *ctx, const CodecPlan &cp, uint8_t *dev, hipStream_t stream)
+{
+    for (size_t i = 0; i < cp.copies.size(); i++)
+        if (dev_err(ctx, hipMemcpyAsync(cp.copies[i].first, cp.copies[i].second, cp.copy_bytes[i],
+                                        hipMemcpyDeviceToDevice, stream)))
             return RS_EDEVICE;
-        for (size_t q = m_small; q < lds_.size(); q++) {
-            const int N = ilog2(lds_[q].np), T1 = (N + 1) / 2, T2 = N - T1;
+    KPtrs kp = ctx->kp;
+    kp.bits = (const uint32_t *)(dev + cp.off_bits);
+    kp.rowtabs = (const uint32_t *)(dev + cp.off_rt);
+    if (cp.decode) {
+        LocatorArgs la;
+        la.stripes = (const DevStripe *)(dev + cp.off_loc);
+        la.r = ctx->r;
+        if (dev_err(ctx, locator_launch(la, kp, ctx->d_FL, ctx->d_exp, cp.m_small, cp.max_np, stream)))
+            return RS_EDEVICE;
+        for (const LocLarge &ll : cp.loc_large) {
+            const int T1 = (ll.N + 1) / 2, T2 = ll.N - T1;
             LocPassArgs pa;
-            pa.stripe = la.stripes + q;
-            pa.v = (uint32_t *)(dev + off_locv) + locv_off[q - m_small];
+            pa.stripe = la.stripes + ll.q;
+            pa.v = (uint32_t *)(dev + cp.off_locv) + ll.v_off;
             pa.r = ctx->r;
             for (int kind = 0; kind < 4; kind++) {
                 pa.kind = kind;
                 pa.lo = (kind & 1) ? T1 : 0;
                 pa.T = (kind & 1) ? T2 : T1;
-                if (dev_err(ctx, loc_pass_launch(pa, kp, ctx->d_FL, ctx->d_exp, 1 << (N - pa.T), stream)))
+                if (dev_err(ctx, loc_pass_launch(pa, kp, ctx->d_FL, ctx->d_exp, 1 << (ll.N - pa.T), stream)))
                     return RS_EDEVICE;
             }
         }
     }
     const DevStripe *d_ents = (const DevStripe *)dev;
-    for (int j = 0; j < ne;) {
-        const int key = launch_key(plans[ents[j].plan], ents[j].cp.ld);
-        int e = j, tiles = 0;
-        while (e < ne && launch_key(plans[ents[e].plan], ents[e].cp.ld) == key) {
-            tiles += ents[e].cp.ntiles;
-            e++;
-        }
+    for (const FusedLaunch &fl : cp.fused) {
         FusedArgs fa;
-        fa.stripes = d_ents + j;
-        fa.nstripes = e - j;
+        fa.stripes = d_ents + fl.first;
+        fa.nstripes = (int)fl.count;
         fa.l = 0;
-        const int mode = decode ? MODE_DEC : (one_parity_block(plans[ents[j].plan]) ? MODE_ENC2 : MODE_ENC);
-        if (dev_err(ctx, fused_launch(ctx->r, mode, 0, ents[j].cp.ld,
-                                      plans[ents[j].plan].L, fa, kp, tiles, stream)))
+        if (dev_err(ctx, fused_launch(ctx->r, fl.mode, 0, fl.ld, fl.L, fa, kp, fl.ntiles, stream)))
             return RS_EDEVICE;
-        j = e;
     }
-    const WideStripe *d_wide = (const WideStripe *)(dev + off_wide);
-    for (const WideLaunch &wl : wp.launches) {
+    const WideStripe *d_wide = (const WideStripe *)(dev + cp.off_wide);
+    for (const WideLaunch &wl : cp.wp.launches) {
         WideArgs wa;
         wa.stripes = d_wide + wl.first;
         wa.nstripes = (int)wl.count;
@@ -886,6 +897,46 @@ int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, in
             return RS_EDEVICE;
     }
     return RS_OK;
+}
+
+int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, int count, bool decode,
+              hipStream_t stream)
+{
+    if (!ctx)
+        return RS_EINVAL;
+    CodecPlan cp;
+    size_t need = 0;
+    int rc = build_codec(ctx, descs, masks, count, decode, nullptr, &need, cp);
+    if (rc)
+        return rc;
+    if (cp.empty())
+        return RS_OK;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return RS_EDEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->sticky)
+        return ctx->sticky;
+    Scratch *sc = get_scratch(ctx, stream);
+    if (!sc)
+        return RS_ENOMEM;
+    if (need) {
+        uint8_t *scr = nullptr;
+        rc = big_scratch(sc, need, &scr);
+        if (rc)
+            return rc;
+        rc = build_codec(ctx, descs, masks, count, decode, scr, nullptr, cp);
+        if (rc)
+            return rc;
+    }
+    rc = ensure_dev(sc, &sc->dev, &sc->dev_cap, cp.dev_bytes);
+    if (rc)
+        return rc;
+    uint8_t *dev = (uint8_t *)sc->dev;
+    rc = stage_upload(sc, cp.host.data(), cp.host.size(), dev);
+    if (rc)
+        return rc;
+    return exec_codec(ctx, cp, dev, stream);
 }
 
 int run_xform(rs_ctx *ctx, int mode, int h, uint32_t l, void *data, size_t rb, hipStream_t stream)
@@ -1150,6 +1201,103 @@ __attribute__((visibility("default"))) int nb_derivative(rs_ctx *ctx, int h, voi
                                                          void *stream)
 {
     return run_xform(ctx, MODE_DERIV, h, 0, data, row_bytes, (hipStream_t)stream);
+}
+
+struct rs_plan {
+    rs_ctx *ctx = nullptr;
+    CodecPlan cp;
+    uint8_t *arena = nullptr;
+    uint8_t *scratch = nullptr;
+};
+
+static int plan_batch(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, int count, bool decode,
+                      rs_plan **out)
+{
+    if (!ctx || !out)
+        return RS_EINVAL;
+    *out = nullptr;
+    rs_plan *pl = new (std::nothrow) rs_plan();
+    if (!pl)
+        return RS_ENOMEM;
+    pl->ctx = ctx;
+    size_t need = 0;
+    int rc = build_codec(ctx, descs, masks, count, decode, nullptr, &need, pl->cp);
+    DeviceGuard guard(ctx->device);
+    if (!rc && !guard.ok)
+        rc = RS_EDEVICE;
+    if (!rc && need) {
+        if (hipMalloc((void **)&pl->scratch, need) != hipSuccess) {
+            pl->scratch = nullptr;
+            rc = RS_ENOMEM;
+        } else {
+            rc = build_codec(ctx, descs, masks, count, decode, pl->scratch, nullptr, pl->cp);
+        }
+    }
+    if (!rc && pl->cp.dev_bytes) {
+        if (hipMalloc((void **)&pl->arena, pl->cp.dev_bytes) != hipSuccess) {
+            pl->arena = nullptr;
+            rc = RS_ENOMEM;
+        } else if (!pl->cp.host.empty() &&
+                   hipMemcpy(pl->arena, pl->cp.host.data(), pl->cp.host.size(), hipMemcpyHostToDevice) !=
+                       hipSuccess) {
+            rc = RS_EDEVICE;
+        }
+    }
+    if (rc) {
+        if (pl->arena)
+            (void)hipFree(pl->arena);
+        if (pl->scratch)
+            (void)hipFree(pl->scratch);
+        delete pl;
+        return rc;
+    }
+    pl->cp.host.clear();
+    pl->cp.host.shrink_to_fit();
+    *out = pl;
+    return RS_OK;
+}
+
+__attribute__((visibility("default"))) int rs_plan_encode_batch(rs_ctx *ctx, const rs_stripe_desc *descs, int count,
+                                                                rs_plan **out)
+{
+    return plan_batch(ctx, descs, nullptr, count, false, out);
+}
+
+__attribute__((visibility("default"))) int rs_plan_decode_batch(rs_ctx *ctx, const rs_stripe_desc *descs,
+                                                                const uint8_t *masks, int count, rs_plan **out)
+{
+    return plan_batch(ctx, descs, masks, count, true, out);
+}
+
+__attribute__((visibility("default"))) int rs_plan_launch(rs_plan *plan, void *stream)
+{
+    if (!plan)
+        return RS_EINVAL;
+    rs_ctx *ctx = plan->ctx;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return RS_EDEVICE;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (ctx->sticky)
+            return ctx->sticky;
+    }
+    if (plan->cp.empty())
+        return RS_OK;
+    return exec_codec(ctx, plan->cp, plan->arena, (hipStream_t)stream);
+}
+
+__attribute__((visibility("default"))) void rs_plan_free(rs_plan *plan)
+{
+    if (!plan)
+        return;
+    DeviceGuard guard(plan->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (plan->arena)
+        (void)hipFree(plan->arena);
+    if (plan->scratch)
+        (void)hipFree(plan->scratch);
+    delete plan;
 }
 
 __attribute__((visibility("default"))) int rs_sync(rs_ctx *ctx, void *stream)

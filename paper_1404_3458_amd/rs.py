@@ -11,6 +11,7 @@ from __future__ import annotations
 import ctypes
 import os
 import re
+import weakref
 
 import numpy as np
 
@@ -48,6 +49,29 @@ class PreparedBatch:
         self.mask_ptr = masks.ctypes.data_as(ctypes.c_void_p) if masks is not None else None
 
 
+class Plan:
+    """An rs_plan: launch() queues the planned batch on a stream (capturable
+    in a HIP graph); close() frees it."""
+
+    def __init__(self, codec, handle):
+        self._codec = codec          # keeps the context alive
+        self._h = handle
+
+    def launch(self, stream=None):
+        return _check(load().rs_plan_launch(self._h, _stream(stream)), "rs_plan_launch")
+
+    def close(self):
+        if self._h:
+            load().rs_plan_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def load():
     """Load librs_nb.so (raises if it has not been built)."""
     global _lib
@@ -66,6 +90,10 @@ def load():
             "nb_derivative": (i32, [vp, i32, vp, sz, vp]),
             "rs_encode_batch": (i32, [vp, vp, i32, vp]),
             "rs_decode_batch": (i32, [vp, vp, vp, i32, vp]),
+            "rs_plan_encode_batch": (i32, [vp, vp, i32, ctypes.POINTER(vp)]),
+            "rs_plan_decode_batch": (i32, [vp, vp, vp, i32, ctypes.POINTER(vp)]),
+            "rs_plan_launch": (i32, [vp, vp]),
+            "rs_plan_free": (None, [vp]),
             "rs_sync": (i32, [vp, vp]),
             "rs_get_table": (i32, [vp, i32, vp, sz]),
             "rs_strerror": (ctypes.c_char_p, [i32]),
@@ -130,6 +158,7 @@ class Codec:
         lib = load()
         self.r = r
         self._ctx = ctypes.c_void_p()
+        self._plans = weakref.WeakSet()
         b = None
         if basis is not None:
             self._basis = np.ascontiguousarray(np.asarray(basis, dtype=np.uint32))
@@ -137,6 +166,9 @@ class Codec:
         _check(lib.rs_init(r, b, ctypes.byref(self._ctx)), "rs_init")
 
     def close(self):
+        """Free the context (and any plan still open on it first)."""
+        for pl in list(self._plans):
+            pl.close()
         if self._ctx:
             load().rs_free(self._ctx)
             self._ctx = ctypes.c_void_p()
@@ -198,6 +230,25 @@ class Codec:
         b = stripes if isinstance(stripes, PreparedBatch) else self.prepare_decode_batch(stripes)
         return _check(load().rs_decode_batch(self._ctx, b.desc_ptr, b.mask_ptr, b.count, _stream(stream)),
                       "rs_decode_batch")
+
+    def plan_encode_batch(self, stripes):
+        """A reusable plan of encode_batch(stripes) (rs_plan_encode_batch)."""
+        b = stripes if isinstance(stripes, PreparedBatch) else self.prepare_encode_batch(stripes)
+        h = ctypes.c_void_p()
+        _check(load().rs_plan_encode_batch(self._ctx, b.desc_ptr, b.count, ctypes.byref(h)), "rs_plan_encode_batch")
+        pl = Plan(self, h)
+        self._plans.add(pl)
+        return pl
+
+    def plan_decode_batch(self, stripes):
+        """A reusable plan of decode_batch(stripes) (rs_plan_decode_batch)."""
+        b = stripes if isinstance(stripes, PreparedBatch) else self.prepare_decode_batch(stripes)
+        h = ctypes.c_void_p()
+        _check(load().rs_plan_decode_batch(self._ctx, b.desc_ptr, b.mask_ptr, b.count, ctypes.byref(h)),
+               "rs_plan_decode_batch")
+        pl = Plan(self, h)
+        self._plans.add(pl)
+        return pl
 
     # ------------------------------------------------------------ transforms
     def fft(self, h, l, data, row_bytes=None, stream=None):

@@ -121,3 +121,26 @@ def uniform_float(k: int, count: int) -> np.ndarray:
     """count floats uniform on [0, 1)."""
     v = u64(k, count)
     return (v >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+
+
+# (n, k) classes of the mixed-stripe workload
+MIXED_CLASSES = ((16, 8), (64, 48), (256, 224), (1024, 512), (4096, 2048))
+
+
+def mixed_stripes(cfg_id: int, count: int, classes=MIXED_CLASSES, smin: int = 1024, smax: int = 65536):
+    """Shapes of a mixed batch: per stripe (n, k, shard_bytes, erasures) with
+    the class uniform over ``classes``, the shard length log-uniform on
+    [smin, smax] rounded to an even byte count, and the erasure count uniform
+    on [0, n - k].  Erasure positions come from :func:`erasure_mask` with key
+    (cfg_id, stripe, ERASURE)."""
+    cls = uniform_int(key(cfg_id, SHAPE), count, 0, len(classes) - 1)
+    u = uniform_float(key(cfg_id, SIZE), count)
+    f = uniform_float(key(cfg_id, ERASURE), count)
+    out = []
+    for i in range(count):
+        n, k = classes[int(cls[i])]
+        sb = 2 * int(round(smin * (smax / smin) ** float(u[i]) / 2))
+        sb = min(max(sb, smin), smax)
+        e = int(np.floor(f[i] * (n - k + 1)))
+        out.append((n, k, sb, min(e, n - k)))
+    return out

@@ -184,3 +184,91 @@ def test_corrupted_survivor_is_not_detected(codec16):
     got = to_host(d)
     assert not (got == cw).all()
     assert (got == oracle.decode(16, n, k, mask, rx)).all()
+
+
+PLAN_SPECS = [(16, 8, 1000), (64, 48, 514), (256, 128, 4096), (256, 224, 2050), (1024, 512, 300), (512, 256, 6),
+              (4096, 2048, 72), (1000, 300, 520)]
+
+
+def _plan_buffers(specs, key):
+    msgs, pars = [], []
+    for i, (n, k, rb) in enumerate(specs):
+        msgs.append(to_dev(rand_rows(k, rb, 60, key, i)))
+        pars.append(torch.zeros((n - k, rb), dtype=torch.uint8, device="cuda"))
+    return msgs, pars
+
+
+def _refill(msgs, key):
+    for i, m in enumerate(msgs):
+        m.copy_(to_dev(rand_rows(m.shape[0], m.shape[1], 61, key, i)))
+
+
+def _check_parity(specs, msgs, pars):
+    for i, (n, k, rb) in enumerate(specs):
+        exp = oracle.encode(16, n, k, to_host(msgs[i]))
+        got = to_host(pars[i])
+        assert (got == exp).all(), (specs[i], first_diff(got, exp))
+
+
+def test_plan_encode_reuse_and_graph_replay(codec16):
+    specs = PLAN_SPECS
+    msgs, pars = _plan_buffers(specs, 1)
+    plan = codec16.plan_encode_batch([(n, k, msgs[i], pars[i]) for i, (n, k, _) in enumerate(specs)])
+    plan.launch()
+    torch.cuda.synchronize()
+    _check_parity(specs, msgs, pars)
+    _refill(msgs, 2)                          # the plan reads the buffers' current contents
+    plan.launch()
+    torch.cuda.synchronize()
+    _check_parity(specs, msgs, pars)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.launch()
+    for rep in range(3):
+        _refill(msgs, 10 + rep)               # eager work between replays
+        for p_ in pars:
+            p_.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        _check_parity(specs, msgs, pars)
+    plan.close()
+
+
+def test_plan_decode_reuse_and_graph_replay(codec16):
+    specs = PLAN_SPECS
+    items, cws, rxs = [], [], []
+    for i, (n, k, rb) in enumerate(specs):
+        msg = rand_rows(k, rb, 62, i)
+        cw = np.concatenate([msg, oracle.encode(16, n, k, msg)])
+        e = [n - k, 0, 1, (n - k) // 2][i % 4]
+        mask = synth.erasure_mask(synth.key(63, i), n, e)
+        rx = cw.copy()
+        rx[mask == 1] = 0x5A
+        ds = to_dev(rx)
+        do = ds if i % 2 == 0 else torch.zeros_like(ds)
+        items.append((n, k, mask, ds, do))
+        cws.append(cw)
+        rxs.append(rx)
+    plan = codec16.plan_decode_batch(items)
+
+    def reset_and_check(run):
+        for i, it in enumerate(items):
+            it[3].copy_(to_dev(rxs[i]))
+            if it[4] is not it[3]:
+                it[4].zero_()
+        torch.cuda.synchronize()
+        run()
+        torch.cuda.synchronize()
+        for i, it in enumerate(items):
+            got = to_host(it[4])
+            assert (got == cws[i]).all(), (specs[i], first_diff(got, cws[i]))
+
+    reset_and_check(plan.launch)
+    reset_and_check(plan.launch)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.launch()
+    for _ in range(3):
+        reset_and_check(g.replay)
+    plan.close()

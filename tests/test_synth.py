@@ -32,3 +32,16 @@ def test_erasure_mask_weight_and_determinism():
 def test_uniform_int_range():
     v = synth.uniform_int(synth.key(9), 10000, 3, 7)
     assert v.min() == 3 and v.max() == 7
+
+
+def test_mixed_stripes_shapes():
+    sh = synth.mixed_stripes(4, 2000)
+    assert sh == synth.mixed_stripes(4, 2000)           # reproducible
+    classes = {(n, k) for n, k, _, _ in sh}
+    assert classes == set(synth.MIXED_CLASSES)
+    for n, k, sb, e in sh:
+        assert 1024 <= sb <= 65536 and sb % 2 == 0
+        assert 0 <= e <= n - k
+    # log-uniform: about half the shards below the geometric mean 8 KiB
+    below = sum(1 for _, _, sb, _ in sh if sb < 8192)
+    assert 850 < below < 1150
