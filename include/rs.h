@@ -134,6 +134,42 @@ int rs_plan_launch(rs_plan *plan, void *stream);
 /* Waits for the device, then frees the plan (NULL is a no-op). */
 void rs_plan_free(rs_plan *plan);
 
+/* Serving: a request loop with continuous batching.  Requests are admitted
+ * first-in first-out while the bytes they keep in flight (codeword rows,
+ * scratch of codes over more than 256 points, locator tables) fit the budget;
+ * admitted requests are grouped into encode and decode batches (at most
+ * max_batch requests each) and queued on one of nstreams streams of default
+ * priority, so batches formed while others run overlap on the device.  A
+ * scheduler thread owned by the server does the grouping, launching and
+ * completion tracking; results are bit-identical to the single calls.
+ * Completion times are CLOCK_MONOTONIC nanoseconds taken when the batch's
+ * event is observed complete.  Buffers must stay valid until the request's
+ * completion is returned; requests whose buffers overlap are the caller's
+ * race.  A request larger than the budget is admitted alone. */
+typedef struct rs_server rs_server;
+enum { RS_OP_ENCODE = 0, RS_OP_DECODE = 1 };
+typedef struct rs_request {
+    int32_t op;             /* RS_OP_ENCODE or RS_OP_DECODE */
+    rs_stripe_desc desc;    /* as in the batched calls */
+    const uint8_t *mask;    /* decode: n bytes, host, copied by rs_server_submit */
+    uint64_t tag;           /* returned with the completion */
+} rs_request;
+typedef struct rs_completion {
+    uint64_t tag;
+    int32_t status;         /* RS_OK or the error of the batch */
+    int64_t t_done_ns;
+} rs_completion;
+int rs_server_create(rs_ctx *ctx, size_t budget_bytes, int max_batch, int nstreams, rs_server **out);
+/* Validates (as the single calls do) and queues; never blocks on the device. */
+int rs_server_submit(rs_server *srv, const rs_request *req);
+/* Returns up to `max` completions (count >= 0), waiting up to timeout_ms
+ * (0: do not wait, < 0: until at least one) when none is ready. */
+int rs_server_poll(rs_server *srv, rs_completion *out, int max, int timeout_ms);
+/* Requests submitted and not yet returned by rs_server_poll. */
+int rs_server_pending(rs_server *srv);
+/* Finishes every queued request, then frees the server (NULL is a no-op). */
+void rs_server_free(rs_server *srv);
+
 /* Wait for all work of this context on `stream`; reports deferred device
  * errors. */
 int rs_sync(rs_ctx *ctx, void *stream);

@@ -72,6 +72,65 @@ class Plan:
             pass
 
 
+RS_OP_ENCODE, RS_OP_DECODE = 0, 1
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("desc", StripeDesc), ("mask", ctypes.c_void_p), ("tag", ctypes.c_uint64)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("t_done_ns", ctypes.c_int64)]
+
+
+class Server:
+    """An rs_server: continuous batching of encode/decode requests with FIFO
+    admission by a device-memory budget, over `nstreams` streams.
+    Completion times are time.monotonic_ns() values."""
+
+    def __init__(self, codec, budget_bytes, max_batch=256, nstreams=2):
+        self._codec = codec
+        self._h = ctypes.c_void_p()
+        _check(load().rs_server_create(codec._ctx, int(budget_bytes), max_batch, nstreams, ctypes.byref(self._h)),
+               "rs_server_create")
+        self._buf = (Completion * 4096)()
+
+    def submit(self, op, n, k, src, dst, mask=None, tag=0, row_bytes=None):
+        """op RS_OP_ENCODE: src = k message rows, dst = n - k parity rows;
+        RS_OP_DECODE: src = n shards, dst = n output rows (may be src)."""
+        if row_bytes is None:
+            row_bytes = _rows(src, k if op == RS_OP_ENCODE else n)[1]
+        req = Request(op, StripeDesc(n, k, row_bytes, _ptr(src), _ptr(dst)), None, tag)
+        mk = None
+        if op == RS_OP_DECODE:
+            mk = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+            assert mk.shape == (n,)
+            req.mask = mk.ctypes.data_as(ctypes.c_void_p)
+        return _check(load().rs_server_submit(self._h, ctypes.cast(ctypes.pointer(req), ctypes.c_void_p)),
+                      "rs_server_submit")
+
+    def poll(self, timeout_ms=0):
+        """List of (tag, status, t_done_ns) of completed requests."""
+        n = load().rs_server_poll(self._h, ctypes.cast(self._buf, ctypes.c_void_p), len(self._buf), int(timeout_ms))
+        if n < 0:
+            raise RSError(n, "rs_server_poll")
+        return [(self._buf[i].tag, self._buf[i].status, self._buf[i].t_done_ns) for i in range(n)]
+
+    def pending(self):
+        return load().rs_server_pending(self._h)
+
+    def close(self):
+        if self._h:
+            load().rs_server_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def load():
     """Load librs_nb.so (raises if it has not been built)."""
     global _lib
@@ -94,6 +153,11 @@ def load():
             "rs_plan_decode_batch": (i32, [vp, vp, vp, i32, ctypes.POINTER(vp)]),
             "rs_plan_launch": (i32, [vp, vp]),
             "rs_plan_free": (None, [vp]),
+            "rs_server_create": (i32, [vp, sz, i32, i32, ctypes.POINTER(vp)]),
+            "rs_server_submit": (i32, [vp, vp]),
+            "rs_server_poll": (i32, [vp, vp, i32, i32]),
+            "rs_server_pending": (i32, [vp]),
+            "rs_server_free": (None, [vp]),
             "rs_sync": (i32, [vp, vp]),
             "rs_get_table": (i32, [vp, i32, vp, sz]),
             "rs_strerror": (ctypes.c_char_p, [i32]),
