@@ -272,3 +272,30 @@ def test_plan_decode_reuse_and_graph_replay(codec16):
     for _ in range(3):
         reset_and_check(g.replay)
     plan.close()
+
+
+@pytest.mark.parametrize("n,k,ns,ncols", [(256, 128, 40, 16384 + 3), (128, 64, 24, 16384), (64, 40, 30, 9000)])
+def test_decode_many_tiles(codec16, n, k, ns, ncols):
+    # more tiles than workgroups resident on the device: the decode loops
+    # over tiles and fetches the next tile's rows while finishing one
+    rb = 2 * ncols
+    cw = torch.empty((ns, n, rb), dtype=torch.uint8, device="cuda")
+    for s in range(ns):
+        synth.fill_random_torch(synth.key(80, n, s), cw[s, :k])
+    codec16.encode_batch([(n, k, cw[s, :k], cw[s, k:]) for s in range(ns)])
+    torch.cuda.synchronize()
+    cols = sorted({0, 1, ncols - 1} | set(int(c) for c in synth.uniform_int(synth.key(81, n), 12, 0, ncols - 1)))
+    for s in (0, ns - 1):
+        host = to_host(cw[s]).reshape(n, ncols, 2)[:, cols, :].reshape(n, 2 * len(cols))
+        assert (oracle.encode(16, n, k, np.ascontiguousarray(host[:k])) == host[k:]).all()
+    ref = cw.clone()
+    masks = []
+    for s in range(ns):
+        e = [n - k, (n - k) // 2, 1][s % 3]
+        m = synth.erasure_mask(synth.key(82, n, s), n, e)
+        cw[s][torch.from_numpy(m).bool().cuda()] = 0
+        masks.append(m)
+    codec16.decode_batch([(n, k, masks[s], cw[s], cw[s]) for s in range(ns)])
+    torch.cuda.synchronize()
+    for s in range(ns):
+        assert torch.equal(cw[s], ref[s]), s
