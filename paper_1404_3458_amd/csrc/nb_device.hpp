@@ -304,6 +304,9 @@ template <int R, int LD>
 __device__ __forceinline__ void load_chunk(const uint8_t *row_, uint32_t off, bool act, int nsym, uint32_t *v)
 {
     const gu8 *row = (const gu8 *)row_ + off;
+    // LD_SYM: a full chunk is read with the widest accesses its address
+    // allows (the same for every lane of a row); a partial one per symbol
+    const uint32_t mis = (uint32_t)(uintptr_t)row & 3u;
     if (R == 16) {
         uint32_t w0 = 0, w1 = 0;
         if (act) {
@@ -311,63 +314,86 @@ __device__ __forceinline__ void load_chunk(const uint8_t *row_, uint32_t off, bo
                 const uint64_t t = *(const gu64 *)row;
                 w0 = (uint32_t)t;
                 w1 = (uint32_t)(t >> 32);
+            } else if (nsym == 4 && mis == 0) {
+                w0 = *(const gu32 *)row;
+                w1 = *(const gu32 *)(row + 4);
+            } else if (nsym == 4) {               // 2 mod 4: 2 + 4 + 2 bytes
+                const uint32_t lo = *(const gu16 *)row;
+                const uint32_t mid = *(const gu32 *)(row + 2);
+                const uint32_t hi = *(const gu16 *)(row + 6);
+                w0 = lo | (mid << 16);
+                w1 = (mid >> 16) | (hi << 16);
             } else {
                 const gu16 *r16 = (const gu16 *)row;
                 const uint32_t s0 = r16[0];
                 const uint32_t s1 = nsym > 1 ? (uint32_t)r16[1] : 0u;
                 const uint32_t s2 = nsym > 2 ? (uint32_t)r16[2] : 0u;
-                const uint32_t s3 = nsym > 3 ? (uint32_t)r16[3] : 0u;
                 w0 = s0 | (s1 << 16);
-                w1 = s2 | (s3 << 16);
+                w1 = s2;
             }
         }
         Ops<16>::unpack(w0, w1, v);
     } else {
         uint32_t w = 0;
         if (act) {
-            if (LD == LD_VEC) {
+            if (LD == LD_VEC || (nsym == 4 && mis == 0)) {
                 w = *(const gu32 *)row;
+            } else if (nsym == 4 && mis == 2) {
+                w = (uint32_t) * (const gu16 *)row | ((uint32_t) * (const gu16 *)(row + 2) << 16);
+            } else if (nsym == 4) {               // odd: 1 + 2 + 1 bytes
+                w = (uint32_t)row[0] | ((uint32_t) * (const gu16 *)(row + 1) << 8) | ((uint32_t)row[3] << 24);
             } else {
                 w = row[0];
                 if (nsym > 1) w |= (uint32_t)row[1] << 8;
                 if (nsym > 2) w |= (uint32_t)row[2] << 16;
-                if (nsym > 3) w |= (uint32_t)row[3] << 24;
             }
         }
         v[0] = w;
     }
 }
-
 template <int R, int LD>
 __device__ __forceinline__ void store_chunk(uint8_t *row_, uint32_t off, bool act, int nsym, const uint32_t *v)
 {
     if (!act)
         return;
     gu8 *row = (gu8 *)row_ + off;
+    const uint32_t mis = (uint32_t)(uintptr_t)row & 3u;
     if (R == 16) {
         uint32_t w0, w1;
         Ops<16>::pack(v, w0, w1);
         if (LD == LD_VEC) {
             *(gu64 *)row = (uint64_t)w0 | ((uint64_t)w1 << 32);
+        } else if (nsym == 4 && mis == 0) {
+            *(gu32 *)row = w0;
+            *(gu32 *)(row + 4) = w1;
+        } else if (nsym == 4) {
+            *(gu16 *)row = (uint16_t)w0;
+            *(gu32 *)(row + 2) = (w0 >> 16) | (w1 << 16);
+            *(gu16 *)(row + 6) = (uint16_t)(w1 >> 16);
         } else {
             gu16 *r16 = (gu16 *)row;
             r16[0] = (uint16_t)w0;
             if (nsym > 1) r16[1] = (uint16_t)(w0 >> 16);
             if (nsym > 2) r16[2] = (uint16_t)w1;
-            if (nsym > 3) r16[3] = (uint16_t)(w1 >> 16);
         }
     } else {
-        if (LD == LD_VEC) {
-            *(gu32 *)row = v[0];
+        const uint32_t w = v[0];
+        if (LD == LD_VEC || (nsym == 4 && mis == 0)) {
+            *(gu32 *)row = w;
+        } else if (nsym == 4 && mis == 2) {
+            *(gu16 *)row = (uint16_t)w;
+            *(gu16 *)(row + 2) = (uint16_t)(w >> 16);
+        } else if (nsym == 4) {
+            row[0] = (uint8_t)w;
+            *(gu16 *)(row + 1) = (uint16_t)(w >> 8);
+            row[3] = (uint8_t)(w >> 24);
         } else {
-            row[0] = (uint8_t)v[0];
-            if (nsym > 1) row[1] = (uint8_t)(v[0] >> 8);
-            if (nsym > 2) row[2] = (uint8_t)(v[0] >> 16);
-            if (nsym > 3) row[3] = (uint8_t)(v[0] >> 24);
+            row[0] = (uint8_t)w;
+            if (nsym > 1) row[1] = (uint8_t)(w >> 8);
+            if (nsym > 2) row[2] = (uint8_t)(w >> 16);
         }
     }
 }
-
 // Per-lane view of a tile: byte offset of the lane's chunk, whether the lane
 // holds real columns, and how many of its 4 symbols exist.
 struct Lane {

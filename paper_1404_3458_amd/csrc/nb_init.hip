@@ -6,6 +6,8 @@
 #include "nb_device.hpp"
 #include "nb_internal.hpp"
 
+#include <algorithm>
+
 namespace nb {
 
 // One thread.  Wv[i*r + j] = W_i(v_j) through W_0(x) = x and
@@ -306,7 +308,10 @@ hipError_t locator_launch(const LocatorArgs &a, const KPtrs &k, const uint32_t *
 {
     if (nstripes <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_locator, dim3(nstripes), dim3(1024), (size_t)max_np * 2, s, a, k.bits,
+    // one butterfly per thread and level for the largest stripe (the kernel
+    // loops over points and butterflies with the block's stride)
+    const int threads = std::min(1024, std::max(64, (max_np / 2 + 63) / 64 * 64));
+    hipLaunchKernelGGL(k_locator, dim3(nstripes), dim3(threads), (size_t)max_np * 2, s, a, k.bits,
                        (uint32_t *)k.rowtabs, fwht_L, expt);
     return hipGetLastError();
 }

@@ -132,15 +132,35 @@ def test_derivative_r8_every_size(codec8, lg):
 
 
 def test_unaligned_rows(codec16):
-    # 3 symbols per row (6 bytes: rows not 8-byte aligned) and a buffer offset by 2 bytes
-    for h in (16, 64, 512):
-        data = rand_rows(h, 6, 43, h)
-        big = torch.zeros(h * 6 + 2, dtype=torch.uint8, device="cuda")
+    # rows of 3, 5 and 515 symbols (6, 10, 1030 bytes: not 8-byte multiples,
+    # so full chunks start 2 mod 4 on every other row) in a buffer offset by
+    # 2 bytes; and the derivative, which reads and writes the same rows
+    for h, rb in ((16, 6), (64, 6), (512, 6), (16, 10), (256, 1030), (1024, 10)):
+        data = rand_rows(h, rb, 43, h, rb)
+        big = torch.zeros(h * rb + 2, dtype=torch.uint8, device="cuda")
         big[2:] = to_dev(data.reshape(-1))
-        codec16.fft(h, 5, big.data_ptr() + 2, row_bytes=6)
-        got = to_host(big[2:]).reshape(h, 6)
+        codec16.fft(h, 5, big.data_ptr() + 2, row_bytes=rb)
+        got = to_host(big[2:]).reshape(h, rb)
         exp = oracle.fft_rows(16, data.copy(), 5)
-        assert (got == exp).all(), h
+        assert (got == exp).all(), (h, rb, first_diff(got, exp))
+        big[2:] = to_dev(data.reshape(-1))
+        codec16.derivative(h, big.data_ptr() + 2, row_bytes=rb)
+        got = to_host(big[2:]).reshape(h, rb)
+        exp = data.copy()
+        oracle.deriv_rows(16, exp)
+        assert (got == exp).all(), (h, rb, first_diff(got, exp))
+
+
+def test_unaligned_rows_r8(codec8):
+    # byte rows at every alignment: 4-symbol chunks starting 0, 1, 2, 3 mod 4
+    for h, rb in ((16, 5), (64, 7), (256, 13), (128, 1027)):
+        data = rand_rows(h, rb, 44, h, rb)
+        big = torch.zeros(h * rb + 1, dtype=torch.uint8, device="cuda")
+        big[1:] = to_dev(data.reshape(-1))
+        codec8.ifft(h, 3, big.data_ptr() + 1, row_bytes=rb)
+        got = to_host(big[1:]).reshape(h, rb)
+        exp = oracle.ifft_rows(8, data.copy(), 3)
+        assert (got == exp).all(), (h, rb, first_diff(got, exp))
 
 
 def test_custom_basis():
