@@ -24,6 +24,9 @@ _SRC = os.path.join(_HERE, "nb_oracle.c")
 _LIB = os.path.join(_HERE, "libnb_oracle.so")
 _lock = threading.Lock()
 _lib = None
+# Test infrastructure: a prebuilt variant of the library to load instead
+# (used to check that the pins reject deliberately broken oracles).
+_LIB_OVERRIDE = os.environ.get("NB_ORACLE_LIB")
 
 ERR_TOOMANY = -2
 
@@ -43,8 +46,11 @@ def _load():
     global _lib
     with _lock:
         if _lib is None:
-            build()
-            lib = ctypes.CDLL(_LIB)
+            if _LIB_OVERRIDE:
+                lib = ctypes.CDLL(_LIB_OVERRIDE)
+            else:
+                build()
+                lib = ctypes.CDLL(_LIB)
             u32, i32, sz = ctypes.c_uint32, ctypes.c_int, ctypes.c_size_t
             p = ctypes.c_void_p
             sig = {
