@@ -140,60 +140,64 @@ __device__ __forceinline__ uint32_t prm(uint32_t hi, uint32_t lo, uint32_t sel)
 constexpr int VW16 = 8;     // V words per table, r = 16
 constexpr int VW8 = 2;      // V words per table, r = 8
 
+constexpr int SW16 = 12;    // S words per table, r = 16
+constexpr int SW8 = 3;      // S words per table, r = 8
+
 // A constant's perm table as the multiply reads it: the V words in vector
-// registers (read from LDS, or copied from scalar registers by the compiler)
-// and the S words through a scalar-load pointer to the full table.
-template <int NV>
+// registers (read from LDS, or copied from scalar registers) and the S words
+// in scalar registers (uniform loads).
+template <int NV, int NS>
 struct TabT {
     uint32_t v[NV];
-    const uint32_t *__restrict__ t;
+    uint32_t s[NS];
 };
-typedef TabT<VW16> Tab16;
-typedef TabT<VW8> Tab8;
+typedef TabT<VW16, SW16> Tab16;
+typedef TabT<VW8, SW8> Tab8;
 
-// a ^= s * b for 4 symbols, r = 16.
+// a ^= s * b for 4 symbols, r = 16 (S word u is table word 8 + u).
 __device__ __forceinline__ void mac16(uint32_t &aL, uint32_t &aH, uint32_t bL, uint32_t bH, const Tab16 &T)
 {
     const uint32_t m3 = 0x07070707u, m2 = 0x03030303u;
     const uint32_t s0 = bL & m3, s1 = (bL >> 3) & m3, s2 = (bL >> 6) & m2;
     const uint32_t s3 = bH & m3, s4 = (bH >> 3) & m3, s5 = (bH >> 6) & m2;
-    const uint32_t *__restrict__ t = T.t;
-    const uint32_t *v = T.v;
-    aL = xor3(aL, prm(t[8], v[0], s0), prm(t[10], v[2], s1));
-    aH = xor3(aH, prm(t[9], v[1], s0), prm(t[11], v[3], s1));
-    aL = xor3(aL, prm(s2, t[16], s2), prm(t[12], v[4], s3));
-    aH = xor3(aH, prm(s2, t[17], s2), prm(t[13], v[5], s3));
-    aL = xor3(aL, prm(t[14], v[6], s4), prm(s5, t[18], s5));
-    aH = xor3(aH, prm(t[15], v[7], s4), prm(s5, t[19], s5));
+    const uint32_t *v = T.v, *t = T.s;
+    aL = xor3(aL, prm(t[0], v[0], s0), prm(t[2], v[2], s1));
+    aH = xor3(aH, prm(t[1], v[1], s0), prm(t[3], v[3], s1));
+    aL = xor3(aL, prm(s2, t[8], s2), prm(t[4], v[4], s3));
+    aH = xor3(aH, prm(s2, t[9], s2), prm(t[5], v[5], s3));
+    aL = xor3(aL, prm(t[6], v[6], s4), prm(s5, t[10], s5));
+    aH = xor3(aH, prm(t[7], v[7], s4), prm(s5, t[11], s5));
 }
 
-// a ^= s * b for 4 symbols, r = 8.
+// a ^= s * b for 4 symbols, r = 8 (S word u is table word 2 + u).
 __device__ __forceinline__ void mac8(uint32_t &a, uint32_t b, const Tab8 &T)
 {
     const uint32_t m3 = 0x07070707u, m2 = 0x03030303u;
     const uint32_t s0 = b & m3, s1 = (b >> 3) & m3, s2 = (b >> 6) & m2;
-    const uint32_t *__restrict__ t = T.t;
-    a = xor3(a, prm(t[2], T.v[0], s0), prm(t[3], T.v[1], s1));
-    a ^= prm(s2, t[4], s2);
+    a = xor3(a, prm(T.s[0], T.v[0], s0), prm(T.s[1], T.v[1], s1));
+    a ^= prm(s2, T.s[2], s2);
 }
 
-// Table from global memory only (V words taken from the scalar loads).
-template <int NV>
-__device__ __forceinline__ TabT<NV> tab_global(const uint32_t *__restrict__ t)
+// Table read whole from global memory with uniform loads.
+template <int NV, int NS>
+__device__ __forceinline__ TabT<NV, NS> tab_global(const uint32_t *__restrict__ t)
 {
-    TabT<NV> r;
+    TabT<NV, NS> r;
 #pragma unroll
     for (int u = 0; u < NV; u++)
         r.v[u] = t[u];
-    r.t = t;
+#pragma unroll
+    for (int u = 0; u < NS; u++)
+        r.s[u] = t[NV + u];
     return r;
 }
 
-// Table with the V words read from LDS (all lanes read the same address).
-template <int NV>
-__device__ __forceinline__ TabT<NV> tab_lds(const uint32_t *lds_v, const uint32_t *__restrict__ t)
+// Table with the V words read from LDS (all lanes read the same address) and
+// the S words read from global memory with uniform loads.
+template <int NV, int NS>
+__device__ __forceinline__ TabT<NV, NS> tab_lds(const uint32_t *lds_v, const uint32_t *__restrict__ t)
 {
-    TabT<NV> r;
+    TabT<NV, NS> r;
     if (NV == 8) {
         const uint4 a = *reinterpret_cast<const uint4 *>(lds_v);
         const uint4 b = *reinterpret_cast<const uint4 *>(lds_v + 4);
@@ -204,17 +208,34 @@ __device__ __forceinline__ TabT<NV> tab_lds(const uint32_t *lds_v, const uint32_
         r.v[0] = a.x;
         r.v[NV > 1 ? 1 : 0] = a.y;
     }
-    r.t = t;
+#pragma unroll
+    for (int u = 0; u < NS; u++)
+        r.s[u] = t[NV + u];
     return r;
+}
+
+// Marks a table as needed here: its loads complete at this point of the
+// program (a wait is placed here), not where the multiply first uses it.
+template <int NV, int NS>
+__device__ __forceinline__ void touch(const TabT<NV, NS> &T)
+{
+    if (NV == 8)
+        asm volatile("" ::"v"(T.v[0]), "v"(T.v[1]), "v"(T.v[2 % NV]), "v"(T.v[3 % NV]), "v"(T.v[4 % NV]),
+                     "v"(T.v[5 % NV]), "v"(T.v[6 % NV]), "v"(T.v[7 % NV]));
+    else
+        asm volatile("" ::"v"(T.v[0]), "v"(T.v[NV - 1]));
+#pragma unroll
+    for (int u = 0; u < NS; u++)
+        asm volatile("" ::"s"(T.s[u]));
 }
 
 template <int R> struct Ops;
 
 template <> struct Ops<16> {
-    static constexpr int NW = 2, NV = VW16;
+    static constexpr int NW = 2, NV = VW16, NS = SW16;
     typedef Tab16 Tab;
-    __device__ static __forceinline__ Tab prep(const uint32_t *t) { return tab_global<NV>(t); }
-    __device__ static __forceinline__ Tab prep_lds(const uint32_t *v, const uint32_t *t) { return tab_lds<NV>(v, t); }
+    __device__ static __forceinline__ Tab prep(const uint32_t *t) { return tab_global<NV, NS>(t); }
+    __device__ static __forceinline__ Tab prep_lds(const uint32_t *v, const uint32_t *t) { return tab_lds<NV, NS>(v, t); }
     __device__ static __forceinline__ void mac(uint32_t *a, const uint32_t *b, const Tab &T)
     {
         mac16(a[0], a[1], b[0], b[1], T);
@@ -233,10 +254,10 @@ template <> struct Ops<16> {
 };
 
 template <> struct Ops<8> {
-    static constexpr int NW = 1, NV = VW8;
+    static constexpr int NW = 1, NV = VW8, NS = SW8;
     typedef Tab8 Tab;
-    __device__ static __forceinline__ Tab prep(const uint32_t *t) { return tab_global<NV>(t); }
-    __device__ static __forceinline__ Tab prep_lds(const uint32_t *v, const uint32_t *t) { return tab_lds<NV>(v, t); }
+    __device__ static __forceinline__ Tab prep(const uint32_t *t) { return tab_global<NV, NS>(t); }
+    __device__ static __forceinline__ Tab prep_lds(const uint32_t *v, const uint32_t *t) { return tab_lds<NV, NS>(v, t); }
     __device__ static __forceinline__ void mac(uint32_t *a, const uint32_t *b, const Tab &T)
     {
         mac8(a[0], b[0], T);
@@ -290,9 +311,15 @@ __device__ __forceinline__ void pipelined(const F &fetch, const W &work)
     Tab cur = fetch(0);
 #pragma unroll
     for (int k = 0; k < N; k++) {
+        // wait for table k (fetched a block ago) before issuing table k + 1,
+        // so that the wait, which covers every outstanding scalar and LDS
+        // load, never includes the fetch that should overlap block k
+        touch(cur);
+        asm volatile("" ::: "memory");
         Tab nxt = cur;
         if (k + 1 < N)
             nxt = fetch(k + 1);
+        asm volatile("" ::: "memory");
         work(k, cur);
         cur = nxt;
     }

@@ -144,6 +144,141 @@ struct TiledLds {
     static_assert(BYTES <= 160 * 1024, "tile and tables exceed the LDS of a workgroup");
 };
 
+// Algorithm 2 steps 2-6 on one tile of 2^L points whose received rows are
+// in x (zeros for the other points) and whose tables are staged: the
+// weighting by Pi, the inverse transform (16-row register groups, LDS
+// transpose, stride-16 groups), the derivative across both groupings, the
+// forward transform and the division of erased rows by Pi'.  `hook` runs
+// right after the last read of the tile region (each wave then owns its 16
+// consecutive rows of it until the function returns).
+template <int R, int L>
+struct DecTile {
+    typedef TiledLds<R, L, M_DEC> LY;
+    typedef typename Ops<R>::Tab Tab;
+    static constexpr int NW = Traits<R>::NW, NV = Ops<R>::NV, H = 1 << L;
+    static constexpr int L2 = L - 4, NR2 = 1 << L2, GPW = 16 >> L2, RS = 64 * NW;
+    uint32_t *lds;
+    const uint32_t *__restrict__ p_tw;
+    const uint32_t *__restrict__ p_B;
+    const uint32_t *__restrict__ p_Binv;
+    int wave, lane;
+
+    __device__ __forceinline__ uint32_t *vX() const { return lds + LY::TILE; }
+    __device__ __forceinline__ uint32_t *vB() const { return vX() + NV * LY::EX; }
+    __device__ __forceinline__ uint32_t *vBi() const { return vB() + NV * LY::EB; }
+    __device__ __forceinline__ uint32_t *vRT() const { return vBi() + NV * LY::EB; }
+    __device__ __forceinline__ uint32_t *slot(int row) const { return lds + (size_t)row * RS + lane * NW; }
+    __device__ __forceinline__ void put(int row, const uint32_t *v) const
+    {
+        uint32_t *p = slot(row);
+        if (NW == 2)
+            *reinterpret_cast<uint2 *>(p) = make_uint2(v[0], v[NW - 1]);
+        else
+            p[0] = v[0];
+    }
+    __device__ __forceinline__ void get(int row, uint32_t *v) const
+    {
+        const uint32_t *p = slot(row);
+        if (NW == 2) {
+            const uint2 t = *reinterpret_cast<const uint2 *>(p);
+            v[0] = t.x;
+            v[NW - 1] = t.y;
+        } else {
+            v[0] = p[0];
+        }
+    }
+
+    template <int LD, class HOOK>
+    __device__ __forceinline__ void run(uint32_t (*x)[Traits<R>::NW], const bool *rcv, const DevStripe &st,
+                                        const Lane &ln, const uint32_t *__restrict__ bits,
+                                        const uint32_t *__restrict__ rowtab, const HOOK &hook) const
+    {
+        const int g = wave;
+        const TwLds<R, L> twX = {p_tw, 0u, vX()};
+        uint32_t *const vb = vB(), *const vbi = vBi(), *const vrt = vRT();
+        // step 2 and the inverse levels 0..3 on the consecutive group
+        pipelined<Tab, 16>([&](int j) { return row_tab<R>(rowtab, vrt, 16 * g + j); },
+                           [&](int j, const Tab &t) { dec_weigh<R>(x[j], rcv[j], t); });
+        reg_levels<R, 4, true, SH_ZERO, false>(x, (uint32_t)(16 * g), 0, twX);
+#pragma unroll
+        for (int j = 0; j < 16; j++)
+            put(16 * g + j, x[j]);
+        __syncthreads();
+        // inverse levels 4..L-1 on the stride groups, then d^d = B (.) coefficients
+        uint32_t y[GPW][NR2][NW];
+#pragma unroll
+        for (int u = 0; u < GPW; u++) {
+            const int r0 = wave * GPW + u;
+#pragma unroll
+            for (int j = 0; j < NR2; j++)
+                get(r0 + 16 * j, y[u][j]);
+            reg_levels<R, L2, true, SH_ZERO, true>(y[u], (uint32_t)r0, 4, twX);
+            pipelined<Tab, NR2>([&](int j) { return row_tab<R>(p_B, vb, r0 + 16 * j); },
+                                [&](int j, const Tab &t) {
+                                    if (r0 + 16 * j)
+                                        scale<R>(y[u][j], t);
+                                    put(r0 + 16 * j, y[u][j]);
+                                });
+        }
+        __syncthreads();
+        // step 4: partners 16 * 2^lv away are in registers, 2^lv away in LDS
+        uint32_t z[GPW][NR2][NW];
+#pragma unroll
+        for (int u = 0; u < GPW; u++) {
+            const int r0 = wave * GPW + u;
+#pragma unroll
+            for (int j = 0; j < NR2; j++) {
+                zero_vec<R>(z[u][j]);
+#pragma unroll
+                for (int lv = 0; lv < L2; lv++)
+                    if (!((j >> lv) & 1))
+#pragma unroll
+                        for (int w = 0; w < NW; w++)
+                            z[u][j][w] ^= y[u][j + (1 << lv)][w];
+            }
+#pragma unroll
+            for (int lv = 0; lv < 4; lv++) {
+                if (!((r0 >> lv) & 1)) {
+#pragma unroll
+                    for (int j = 0; j < NR2; j++) {
+                        uint32_t v[NW];
+                        get(r0 + (1 << lv) + 16 * j, v);
+#pragma unroll
+                        for (int w = 0; w < NW; w++)
+                            z[u][j][w] ^= v[w];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // coefficients over B_j, step 5's levels L-1..4
+#pragma unroll
+        for (int u = 0; u < GPW; u++) {
+            const int r0 = wave * GPW + u;
+            pipelined<Tab, NR2>([&](int j) { return row_tab<R>(p_Binv, vbi, r0 + 16 * j); },
+                                [&](int j, const Tab &t) {
+                                    if (r0 + 16 * j)
+                                        scale<R>(z[u][j], t);
+                                });
+            reg_levels<R, L2, false, SH_ZERO, true>(z[u], (uint32_t)r0, 4, twX);
+#pragma unroll
+            for (int j = 0; j < NR2; j++)
+                put(r0 + 16 * j, z[u][j]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 16; j++)
+            get(16 * g + j, x[j]);
+        hook();
+        // levels 3..0 and step 6
+        reg_levels<R, 4, false, SH_ZERO, false>(x, (uint32_t)(16 * g), 0, twX);
+        pipelined<Tab, 16>([&](int j) { return row_tab<R>(rowtab, vrt, 16 * g + j); },
+                           [&](int j, const Tab &t) {
+                               dec_store<R, LD>(x[j], 16 * g + j, st, ln, bits, [&](int) { return t; });
+                           });
+    }
+};
+
 template <int R, int L, int MODE, int SH, int LD>
 __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4))) void k_tiled(NB_FUSED_PARAMS)
 {
@@ -308,9 +443,11 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
         }
     }
     stage_tables();
-    if (MODE == M_DEC)
-        pipelined<Tab, 16>([&](int j) { return row_tab<R>(rowtab, vRT, 16 * g + j); },
-                           [&](int j, const Tab &t) { dec_weigh<R>(x[j], rcv[j], t); });
+    if (MODE == M_DEC) {
+        const DecTile<R, L> dt = {lds, p_tw, p_B, p_Binv, wave, lane};
+        dt.template run<LD>(x, rcv, st, ln, bits, rowtab, [] {});
+        return;
+    }
     reg_levels<R, 4, true, (MODE == M_IFFT ? SH : SH_ZERO), false>(x, (uint32_t)(16 * g), 0, twX);
 #pragma unroll
     for (int j = 0; j < 16; j++)
@@ -405,69 +542,6 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
         return;
     }
 
-    // ---- M_DEC: step 4 (derivative) across the two groupings, then step 5.
-#pragma unroll
-    for (int u = 0; u < GPW; u++) {
-        const int r0 = wave * GPW + u;
-        pipelined<Tab, NR2>([&](int j) { return row_tab<R>(p_B, vB, r0 + 16 * j); },
-                            [&](int j, const Tab &t) {
-                                if (r0 + 16 * j)
-                                    scale<R>(y[u][j], t);
-                                lds_put(my + RS * r0, 16 * j, y[u][j]);
-                            });
-    }
-    __syncthreads();
-    uint32_t z[GPW][NR2][NW];
-#pragma unroll
-    for (int u = 0; u < GPW; u++) {
-        const int r0 = wave * GPW + u;
-#pragma unroll
-        for (int j = 0; j < NR2; j++) {
-            zero_vec<R>(z[u][j]);
-#pragma unroll
-            for (int lv = 0; lv < L2; lv++)              // partners 16 * 2^lv away
-                if (!((j >> lv) & 1))
-#pragma unroll
-                    for (int w = 0; w < NW; w++)
-                        z[u][j][w] ^= y[u][j + (1 << lv)][w];
-        }
-#pragma unroll
-        for (int lv = 0; lv < 4; lv++) {                 // partners 2^lv away
-            if (!((r0 >> lv) & 1)) {
-#pragma unroll
-                for (int j = 0; j < NR2; j++) {
-                    uint32_t v[NW];
-                    lds_get(my + RS * r0, (1 << lv) + 16 * j, v);
-#pragma unroll
-                    for (int w = 0; w < NW; w++)
-                        z[u][j][w] ^= v[w];
-                }
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < GPW; u++) {
-        const int r0 = wave * GPW + u;
-        pipelined<Tab, NR2>([&](int j) { return row_tab<R>(p_Binv, vBi, r0 + 16 * j); },
-                            [&](int j, const Tab &t) {
-                                if (r0 + 16 * j)
-                                    scale<R>(z[u][j], t);
-                            });
-        reg_levels<R, L2, false, SH_ZERO, true>(z[u], (uint32_t)r0, 4, twX);
-#pragma unroll
-        for (int j = 0; j < NR2; j++)
-            lds_put(my + RS * r0, 16 * j, z[u][j]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 16; j++)
-        lds_get(cb, j, x[j]);
-    reg_levels<R, 4, false, SH_ZERO, false>(x, (uint32_t)(16 * g), 0, twX);
-    pipelined<Tab, 16>([&](int j) { return row_tab<R>(rowtab, vRT, 16 * g + j); },
-                       [&](int j, const Tab &t) {
-                           dec_store<R, LD>(x[j], 16 * g + j, st, ln, bits, [&](int) { return t; });
-                       });
 }
 
 // ------------------------------------------------------------------ launchers

@@ -274,10 +274,12 @@ def test_plan_decode_reuse_and_graph_replay(codec16):
     plan.close()
 
 
-@pytest.mark.parametrize("n,k,ns,ncols", [(256, 128, 40, 16384 + 3), (128, 64, 24, 16384), (64, 40, 30, 9000)])
-def test_decode_many_tiles(codec16, n, k, ns, ncols):
-    # more tiles than workgroups resident on the device: the decode loops
-    # over tiles and fetches the next tile's rows while finishing one
+@pytest.mark.parametrize("n,k,ns,ncols,inplace", [(256, 128, 40, 16384 + 3, True), (128, 64, 24, 16384, True),
+                                                  (64, 40, 30, 9000, True), (256, 128, 40, 16384, True),
+                                                  (256, 200, 24, 8192, False)])
+def test_decode_many_tiles(codec16, n, k, ns, ncols, inplace):
+    # more tiles than workgroups resident on the device, whole and ragged
+    # tiles, in place and out of place
     rb = 2 * ncols
     cw = torch.empty((ns, n, rb), dtype=torch.uint8, device="cuda")
     for s in range(ns):
@@ -295,7 +297,11 @@ def test_decode_many_tiles(codec16, n, k, ns, ncols):
         m = synth.erasure_mask(synth.key(82, n, s), n, e)
         cw[s][torch.from_numpy(m).bool().cuda()] = 0
         masks.append(m)
-    codec16.decode_batch([(n, k, masks[s], cw[s], cw[s]) for s in range(ns)])
+    rx = cw.clone()
+    out = cw if inplace else torch.zeros_like(cw)
+    codec16.decode_batch([(n, k, masks[s], cw[s], out[s]) for s in range(ns)])
     torch.cuda.synchronize()
     for s in range(ns):
-        assert torch.equal(cw[s], ref[s]), s
+        assert torch.equal(out[s], ref[s]), s
+        if not inplace:
+            assert torch.equal(cw[s], rx[s]), s          # input untouched
