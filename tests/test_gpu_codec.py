@@ -274,22 +274,27 @@ def test_plan_decode_reuse_and_graph_replay(codec16):
     plan.close()
 
 
-@pytest.mark.parametrize("n,k,ns,ncols,inplace", [(256, 128, 40, 16384 + 3, True), (128, 64, 24, 16384, True),
-                                                  (64, 40, 30, 9000, True), (256, 128, 40, 16384, True),
-                                                  (256, 200, 24, 8192, False)])
-def test_decode_many_tiles(codec16, n, k, ns, ncols, inplace):
-    # more tiles than workgroups resident on the device, whole and ragged
-    # tiles, in place and out of place
-    rb = 2 * ncols
+@pytest.mark.parametrize("r,n,k,ns,ncols,inplace", [(16, 256, 128, 40, 16384 + 3, True), (16, 128, 64, 24, 16384, True),
+                                                    (16, 64, 40, 30, 9000, True), (16, 256, 128, 40, 16384, True),
+                                                    (16, 256, 200, 24, 8192, False), (16, 256, 128, 24, 8192, False),
+                                                    (16, 200, 100, 21, 8192 + 5, False), (8, 256, 128, 24, 8192, True),
+                                                    (8, 240, 120, 22, 8192 + 3, False)])
+def test_decode_many_tiles(request, r, n, k, ns, ncols, inplace):
+    # more tiles than workgroups resident on the device (for 2^8 points:
+    # the streamed kernel, with runs of tiles that cross stripes), whole and
+    # ragged tiles, aligned and unaligned rows, in place and out of place
+    codec = request.getfixturevalue("codec%d" % r)
+    sb = r // 8
+    rb = sb * ncols
     cw = torch.empty((ns, n, rb), dtype=torch.uint8, device="cuda")
     for s in range(ns):
         synth.fill_random_torch(synth.key(80, n, s), cw[s, :k])
-    codec16.encode_batch([(n, k, cw[s, :k], cw[s, k:]) for s in range(ns)])
+    codec.encode_batch([(n, k, cw[s, :k], cw[s, k:]) for s in range(ns)])
     torch.cuda.synchronize()
     cols = sorted({0, 1, ncols - 1} | set(int(c) for c in synth.uniform_int(synth.key(81, n), 12, 0, ncols - 1)))
     for s in (0, ns - 1):
-        host = to_host(cw[s]).reshape(n, ncols, 2)[:, cols, :].reshape(n, 2 * len(cols))
-        assert (oracle.encode(16, n, k, np.ascontiguousarray(host[:k])) == host[k:]).all()
+        host = to_host(cw[s]).reshape(n, ncols, sb)[:, cols, :].reshape(n, sb * len(cols))
+        assert (oracle.encode(r, n, k, np.ascontiguousarray(host[:k])) == host[k:]).all()
     ref = cw.clone()
     masks = []
     for s in range(ns):
@@ -299,7 +304,7 @@ def test_decode_many_tiles(codec16, n, k, ns, ncols, inplace):
         masks.append(m)
     rx = cw.clone()
     out = cw if inplace else torch.zeros_like(cw)
-    codec16.decode_batch([(n, k, masks[s], cw[s], out[s]) for s in range(ns)])
+    codec.decode_batch([(n, k, masks[s], cw[s], out[s]) for s in range(ns)])
     torch.cuda.synchronize()
     for s in range(ns):
         assert torch.equal(out[s], ref[s]), s
