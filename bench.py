@@ -163,6 +163,27 @@ def cpu_baseline(cfg, sample_stripes, sample_cols, threads):
                       "%.2f s wall" % (sample_stripes, cols, nbytes, dt)}
 
 
+def schedule_for(args, codec, shapes):
+    """Pass-pipeline schedules for a mixed workload, set in `codec`: a saved
+    table (--schedule), the defaults (--no-tune), or the autotuner run on
+    seeded batches of the workload's (n, k) classes with row lengths at the
+    deciles of its shard lengths (setup, outside every timed region)."""
+    from paper_1404_3458_amd import tune
+
+    t0 = time.perf_counter()
+    if args.schedule:
+        tab, src = tune.load(args.schedule, codec), "file " + os.path.basename(args.schedule)
+    elif args.no_tune:
+        return {"source": "default (T1 = ceil(N/2))"}
+    else:
+        sbs = sorted(sb for n, k, sb, e in shapes)
+        rbs = tuple(sorted({sbs[int(q * (len(sbs) - 1))] for q in (0.1, 0.3, 0.5, 0.7, 0.9)}))
+        tab = tune.tune(codec, sorted({(n, k) for n, k, sb, e in shapes}), row_bytes=rbs)
+        src = "autotuned"
+    return {"source": src, "setup_s": round(time.perf_counter() - t0, 2), "T1": tune.summary(tab),
+            "candidate_ms": {"%s:%d" % (e["op"], e["N"]): e.get("ms") for e in tab["entries"]}}
+
+
 def run_mixed(args, cfg):
     """The mixed-stripe workload: every stripe encoded and then decoded in
     place per step, as one encode plan and one decode plan replayed in a HIP
@@ -188,6 +209,7 @@ def run_mixed(args, cfg):
     masks = [synth.erasure_mask(synth.key(cfg["id"], s, synth.ERASURE), n, e) for s, (n, k, sb, e) in
              enumerate(shapes)]
     codec = rs.Codec(16)
+    sched = schedule_for(args, codec, shapes)
     stream = torch.cuda.current_stream()
     enc_list = [(n, k, cws[s][:k], cws[s][k:]) for s, (n, k, sb, e) in enumerate(shapes)]
     dec_list = [(n, k, masks[s], cws[s], cws[s]) for s, (n, k, sb, e) in enumerate(shapes)]
@@ -321,6 +343,7 @@ def run_mixed(args, cfg):
             "graph_over_per_stripe": round(wall_ps_total / wall_g, 2),
             "batched_calls_over_per_stripe": round(wall_ps_total / wall_b, 2),
             "per_class": per_class,
+            "schedule": sched,
         },
     }
     print(json.dumps(out))
@@ -354,6 +377,7 @@ def run_serving(args, cfg):
     masks = [synth.erasure_mask(synth.key(cfg["id"], s, synth.ERASURE), n, e) for s, (n, k, sb, e) in
              enumerate(shapes)]
     codec = rs.Codec(16)
+    sched = schedule_for(args, codec, shapes)
     codec.encode_batch([(n, k, cws[s][:k], cws[s][k:]) for s, (n, k, sb, e) in enumerate(shapes)])
     torch.cuda.synchronize()
     srv = rs.Server(codec, cfg["budget"], max_batch=512, nstreams=3)
@@ -441,7 +465,7 @@ def run_serving(args, cfg):
                    "parallelism": "single GPU"},
         "roofline": None,
         "cpu_baseline": None,
-        "detail": {"saturated": sat, "poisson": loads,
+        "detail": {"saturated": sat, "poisson": loads, "schedule": sched,
                    "note": "step = one request at the saturated rate; latency = completion - scheduled arrival"},
     }
     print(json.dumps(out))
@@ -460,6 +484,8 @@ def main():
     ap.add_argument("--no-per-stripe", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--stripes", type=int, default=0, help="mixed workload: stripe count (default 8192)")
+    ap.add_argument("--schedule", default="", help="mixed workloads: schedule table (JSON) instead of autotuning")
+    ap.add_argument("--no-tune", action="store_true", help="mixed workloads: default schedules")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy --steps times (the reference "
                          "kernel that scales the HBM byte counters)")

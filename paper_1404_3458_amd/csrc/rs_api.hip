@@ -7,6 +7,7 @@
 #include "nb_internal.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
@@ -109,6 +110,8 @@ struct rs_ctx {
     std::mutex mu;
     std::vector<Scratch *> scratch;
     int sticky = RS_OK;
+    // schedules of the pass pipelines: T1 per (op, N); 0 = ceil(N / 2)
+    std::atomic<int> sched_T1[2][17] = {};
 };
 
 namespace {
@@ -529,7 +532,7 @@ size_t wide_scratch_rows(const Plan &p)
 // list the launches: per chunk and transform size, every pass kind in order,
 // one launch per row-access variant.
 void plan_wide(const std::vector<Plan> &plans, const std::vector<int> &idx, bool decode, uint8_t *scratch_base,
-               WidePlan &wp)
+               const int *sched_T1, WidePlan &wp)
 {
     wp.descs.clear();
     wp.launches.clear();
@@ -570,7 +573,7 @@ void plan_wide(const std::vector<Plan> &plans, const std::vector<int> &idx, bool
                 Ns.push_back(plans[idx[q]].L);
         std::sort(Ns.begin(), Ns.end());
         for (int N : Ns) {
-            const int T1 = (N + 1) / 2, T2 = N - T1;
+            const int T1 = sched_T1[N] ? sched_T1[N] : (N + 1) / 2, T2 = N - T1;
             int max_blocks = 2;
             for (size_t q = ch.first; q < ch.second; q++)
                 if (plans[idx[q]].L == N)
@@ -805,7 +808,10 @@ int build_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, 
         if (plans[act[q]].L > FUSED_MAX_L)
             widx.push_back(act[q]);
     if (!widx.empty()) {
-        plan_wide(plans, widx, decode, scratch, cp.wp);
+        int t1[17];
+        for (int N = 0; N < 17; N++)
+            t1[N] = ctx->sched_T1[decode ? 1 : 0][N].load(std::memory_order_relaxed);
+        plan_wide(plans, widx, decode, scratch, t1, cp.wp);
         if (scratch_need)
             *scratch_need = cp.wp.scratch;
     } else if (scratch_need) {
@@ -1042,6 +1048,47 @@ bool basis_independent(int r, const uint32_t *b)
     return rank == r;
 }
 
+// A pass-pipeline schedule is valid for transforms over 2^N > 256 points
+// (GF(2^16)) when both pass kinds get 4..8 levels; T1 = 0 is the default.
+bool schedule_ok(int r, int op, int N, int T1)
+{
+    if (r != 16 || (op != RS_OP_ENCODE && op != RS_OP_DECODE) || N <= FUSED_MAX_L || N > 16)
+        return false;
+    return T1 == 0 || (T1 >= 4 && T1 <= 8 && N - T1 >= 4 && N - T1 <= 8);
+}
+
+// RS_NB_SCHEDULE: comma-separated "enc:N:T1" / "dec:N:T1" entries.
+bool apply_schedule_env(rs_ctx *ctx)
+{
+    const char *env = std::getenv("RS_NB_SCHEDULE");
+    if (!env || !*env)
+        return true;
+    const char *p = env;
+    while (*p) {
+        int op;
+        if (!std::strncmp(p, "enc:", 4))
+            op = RS_OP_ENCODE;
+        else if (!std::strncmp(p, "dec:", 4))
+            op = RS_OP_DECODE;
+        else
+            return false;
+        p += 4;
+        char *end;
+        const long N = std::strtol(p, &end, 10);
+        if (end == p || *end != ':')
+            return false;
+        p = end + 1;
+        const long T1 = std::strtol(p, &end, 10);
+        if (end == p || (*end && *end != ','))
+            return false;
+        p = *end ? end + 1 : end;
+        if (N < 0 || N > 16 || !schedule_ok(ctx->r, op, (int)N, (int)T1))
+            return false;
+        ctx->sched_T1[op][N].store((int)T1);
+    }
+    return true;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI
@@ -1065,6 +1112,10 @@ __attribute__((visibility("default"))) int rs_init(int r, const uint32_t *basis,
         return RS_ENOMEM;
     ctx->r = r;
     std::memcpy(ctx->basis, b, sizeof(uint32_t) * r);
+    if (!apply_schedule_env(ctx)) {
+        delete ctx;
+        return RS_EINVAL;
+    }
     if (hipGetDevice(&ctx->device) != hipSuccess) {
         delete ctx;
         return RS_EDEVICE;
@@ -1121,6 +1172,29 @@ __attribute__((visibility("default"))) int rs_init(int r, const uint32_t *basis,
     ctx->kp.bits = nullptr;
     ctx->kp.rowtabs = nullptr;
     *out = ctx;
+    return RS_OK;
+}
+
+__attribute__((visibility("default"))) int rs_schedule_set(rs_ctx *ctx, int op, int N, int T1)
+{
+    if (!ctx)
+        return RS_EINVAL;
+    if (ctx->r != 16 || N <= FUSED_MAX_L || N > 16)
+        return RS_ESHAPE;
+    if (!schedule_ok(ctx->r, op, N, T1))
+        return RS_EINVAL;
+    ctx->sched_T1[op][N].store(T1);
+    return RS_OK;
+}
+
+__attribute__((visibility("default"))) int rs_schedule_get(rs_ctx *ctx, int op, int N, int *T1)
+{
+    if (!ctx || !T1 || (op != RS_OP_ENCODE && op != RS_OP_DECODE))
+        return RS_EINVAL;
+    if (ctx->r != 16 || N <= FUSED_MAX_L || N > 16)
+        return RS_ESHAPE;
+    const int t = ctx->sched_T1[op][N].load();
+    *T1 = t ? t : (N + 1) / 2;
     return RS_OK;
 }
 

@@ -158,6 +158,8 @@ def load():
             "rs_server_poll": (i32, [vp, vp, i32, i32]),
             "rs_server_pending": (i32, [vp]),
             "rs_server_free": (None, [vp]),
+            "rs_schedule_set": (i32, [vp, i32, i32, i32]),
+            "rs_schedule_get": (i32, [vp, i32, i32, ctypes.POINTER(i32)]),
             "rs_sync": (i32, [vp, vp]),
             "rs_get_table": (i32, [vp, i32, vp, sz]),
             "rs_strerror": (ctypes.c_char_p, [i32]),
@@ -330,6 +332,17 @@ class Codec:
             _, row_bytes = _rows(data, h)
         return _check(load().nb_derivative(self._ctx, h, _ptr(data), row_bytes, _stream(stream)),
                       "nb_derivative")
+
+    # ------------------------------------------------------------ schedules
+    def set_schedule(self, op, N, T1):
+        """Low-level count T1 of the pass pipelines for transforms over 2^N
+        points (op RS_OP_ENCODE: N = lg k'; RS_OP_DECODE: N = lg n'); 0 = default."""
+        return _check(load().rs_schedule_set(self._ctx, op, N, T1), "rs_schedule_set")
+
+    def get_schedule(self, op, N):
+        t = ctypes.c_int()
+        _check(load().rs_schedule_get(self._ctx, op, N, ctypes.byref(t)), "rs_schedule_get")
+        return t.value
 
     # ------------------------------------------------------------ misc
     def sync(self, stream=None):
