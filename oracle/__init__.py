@@ -86,6 +86,13 @@ def _load():
                 "orc_locator_direct": (i32, [i32, p, i32, p, p]),
                 "orc_decode": (i32, [i32, p, i32, i32, p, p, p, sz, sz, i32]),
                 "orc_decode_lagrange": (i32, [i32, p, i32, i32, p, p, p, sz, sz]),
+                "orc_poly_mul": (i32, [i32, i32, p, i32, p, p]),
+                "orc_from_monomial": (i32, [i32, p, i32, p, p]),
+                "orc_degree": (i32, [i32, p]),
+                "orc_polymul_fft": (i32, [i32, p, i32, u32, p, p, p]),
+                "orc_polymul_rows": (i32, [i32, p, i32, u32, p, p, p, sz, sz]),
+                "orc_degree_rows": (i32, [i32, i32, p, sz, sz, p]),
+                "orc_convert_rows": (i32, [i32, p, i32, i32, p, sz, sz]),
             }
             for name, (res, args) in sig.items():
                 fn = getattr(lib, name)
@@ -362,3 +369,66 @@ def locator_direct(r, erased, basis=None):
     out = np.zeros(len(e), dtype=np.uint32)
     _check(_load().orc_locator_direct(r, _ptr(b), len(e), _ptr(e), _ptr(out)), "locator_direct")
     return out
+
+
+# ---------------------------------------------------------------- polynomial operations (Sec. 5)
+def poly_mul(r, a, b):
+    """Monomial-basis product (schoolbook)."""
+    a, b = _u32(a), _u32(b)
+    out = np.zeros(len(a) + len(b) - 1, dtype=np.uint32)
+    _check(_load().orc_poly_mul(r, len(a), _ptr(a), len(b), _ptr(b), _ptr(out)), "poly_mul")
+    return out
+
+
+def from_monomial(r, mono, basis=None):
+    """Novel-basis coefficients of a polynomial given in the monomial basis."""
+    b = _basis(basis)
+    m = _u32(mono)
+    out = np.zeros(len(m), dtype=np.uint32)
+    _check(_load().orc_from_monomial(r, _ptr(b), len(m), _ptr(m), _ptr(out)), "from_monomial")
+    return out
+
+
+def degree(d):
+    d = _u32(d)
+    return _load().orc_degree(len(d), _ptr(d))
+
+
+def polymul(r, a, b, l=0, basis=None):
+    """Sec. 5 product of two novel-basis polynomials of h coefficients: 2h coefficients."""
+    bs = _basis(basis)
+    a, b = _u32(a), _u32(b)
+    assert len(a) == len(b)
+    out = np.zeros(2 * len(a), dtype=np.uint32)
+    _check(_load().orc_polymul_fft(r, _ptr(bs), len(a), l, _ptr(a), _ptr(b), _ptr(out)), "polymul")
+    return out
+
+
+def polymul_rows(r, a, b, l=0, basis=None, ncols=None):
+    """Column-wise polymul of row-major stripes a, b (h rows): 2h rows."""
+    bs = _basis(basis)
+    a, b = _rows(a), _rows(b)
+    assert a.shape == b.shape
+    out = np.zeros((2 * a.shape[0], a.shape[1]), dtype=np.uint8)
+    nc = a.shape[1] // (r // 8) if ncols is None else ncols
+    _check(_load().orc_polymul_rows(r, _ptr(bs), a.shape[0], l, _ptr(a), _ptr(b), _ptr(out), a.strides[0], nc),
+           "polymul_rows")
+    return out
+
+
+def degree_rows(r, data, ncols=None):
+    d = _rows(data)
+    nc = d.shape[1] // (r // 8) if ncols is None else ncols
+    out = np.zeros(nc, dtype=np.int32)
+    _check(_load().orc_degree_rows(r, d.shape[0], _ptr(d), d.strides[0], nc, _ptr(out)), "degree_rows")
+    return out
+
+
+def convert_rows(r, data, to_monomial, basis=None, ncols=None):
+    """In place, column by column: novel -> monomial basis (to_monomial) or back."""
+    bs = _basis(basis)
+    d = _rows(data)
+    nc = d.shape[1] // (r // 8) if ncols is None else ncols
+    _check(_load().orc_convert_rows(r, _ptr(bs), d.shape[0], 1 if to_monomial else 0, _ptr(d), d.strides[0], nc),
+           "convert_rows")
+    return d

@@ -887,3 +887,176 @@ ORC_EXPORT int orc_decode_lagrange(int r, const uint32_t *basis, int n, int k, c
     free(kpt); free(krow);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Polynomial operations in the novel basis (Sec. 5, Table 1).         */
+/* ------------------------------------------------------------------ */
+
+/* Product in the monomial basis, schoolbook: out has la + lb - 1 entries. */
+ORC_EXPORT int orc_poly_mul(int r, int la, const uint32_t *a, int lb, const uint32_t *b, uint32_t *out)
+{
+    if (!field_ok(r) || la < 1 || lb < 1 || !a || !b || !out)
+        return -1;
+    poly_mul(r, a, la, b, lb, out);
+    return 0;
+}
+
+/* Row i of the table holds the i + 1 monomial coefficients of X_i
+ * (Definition 1), i < h; entries above the diagonal are zero. */
+static uint32_t *x_table(int r, const uint32_t *basis, int h)
+{
+    uint32_t *t = calloc((size_t)h * (size_t)h, sizeof(uint32_t));
+    if (!t)
+        return NULL;
+    for (int i = 0; i < h; i++)
+        if (orc_X_monomial(r, basis, (uint32_t)i, t + (size_t)i * h)) {
+            free(t);
+            return NULL;
+        }
+    return t;
+}
+
+/* Monomial coefficients of sum_i d_i X_i from the table (as orc_to_monomial). */
+static void to_mono_tab(int r, int h, const uint32_t *xt, const uint32_t *d, uint32_t *mono)
+{
+    memset(mono, 0, sizeof(uint32_t) * (size_t)h);
+    for (int i = 0; i < h; i++)
+        if (d[i])
+            for (int t = 0; t <= i; t++)
+                mono[t] ^= orc_mul(r, d[i], xt[(size_t)i * h + t]);
+}
+
+/* The inverse: X_i has degree exactly i (its factors are the nonzero-leading
+ * W_j-hat), so the expansion is triangular; from the highest degree down,
+ * d_j is the remaining coefficient of x^j over the leading coefficient of
+ * X_j, and d_j X_j is then subtracted. */
+static void from_mono_tab(int r, int h, const uint32_t *xt, const uint32_t *mono, uint32_t *d, uint32_t *work)
+{
+    memcpy(work, mono, sizeof(uint32_t) * (size_t)h);
+    for (int j = h - 1; j >= 0; j--) {
+        const uint32_t *xj = xt + (size_t)j * h;
+        d[j] = orc_mul(r, work[j], orc_inv(r, xj[j]));
+        if (d[j])
+            for (int t = 0; t <= j; t++)
+                work[t] ^= orc_mul(r, d[j], xj[t]);
+    }
+}
+
+/* Novel-basis coefficients (h entries) of a polynomial of degree < h given
+ * by its h monomial coefficients. */
+ORC_EXPORT int orc_from_monomial(int r, const uint32_t *basis, int h, const uint32_t *mono, uint32_t *d)
+{
+    if (!field_ok(r) || h < 1 || h > (1 << r) || !mono || !d)
+        return -1;
+    uint32_t *xt = x_table(r, basis, h);
+    uint32_t *work = calloc((size_t)h, sizeof(uint32_t));
+    if (!xt || !work) {
+        free(xt); free(work);
+        return -1;
+    }
+    from_mono_tab(r, h, xt, mono, d, work);
+    free(xt); free(work);
+    return 0;
+}
+
+/* Degree of [D_h](x) (Sec. 5): the largest j with d_j != 0, since
+ * deg X_j = j; -1 for the zero polynomial. */
+ORC_EXPORT int orc_degree(int h, const uint32_t *d)
+{
+    if (h < 1 || !d)
+        return -2;
+    for (int j = h - 1; j >= 0; j--)
+        if (d[j])
+            return j;
+    return -1;
+}
+
+/* Sec. 5, product of [A_h] and [B_h]: both padded with zeros to 2h
+ * coefficients, transformed by Psi_2h^l (Sec. 3.2), multiplied point by
+ * point, and transformed back by the inverse (Sec. 3.3).  out: 2h entries,
+ * the novel-basis coefficients of the product (the last one is zero). */
+ORC_EXPORT int orc_polymul_fft(int r, const uint32_t *basis, int h, uint32_t l, const uint32_t *a, const uint32_t *b,
+                               uint32_t *out)
+{
+    const int H = 2 * h;
+    if (h < 1 || !xform_args_ok(r, H, l) || !a || !b || !out)
+        return -1;
+    uint32_t *f = make_factors(r, basis, H, l);
+    uint32_t *tb = calloc((size_t)H, sizeof(uint32_t));
+    if (!f || !tb) {
+        free(f); free(tb);
+        return -1;
+    }
+    memset(out, 0, sizeof(uint32_t) * (size_t)H);
+    memcpy(out, a, sizeof(uint32_t) * (size_t)h);
+    memcpy(tb, b, sizeof(uint32_t) * (size_t)h);
+    fft_core(r, basis, H, l, f, out, NULL);
+    fft_core(r, basis, H, l, f, tb, NULL);
+    for (int j = 0; j < H; j++)
+        out[j] = orc_mul(r, out[j], tb[j]);
+    ifft_core(r, basis, H, l, f, out, NULL);
+    free(f); free(tb);
+    return 0;
+}
+
+/* Column-wise variants over row-major stripes (row t at data + t * stride):
+ * a and b have h rows, out 2h rows. */
+ORC_EXPORT int orc_polymul_rows(int r, const uint32_t *basis, int h, uint32_t l, const uint8_t *a,
+                                const uint8_t *b, uint8_t *out, size_t stride, size_t ncols)
+{
+    if (h < 1 || !a || !b || !out)
+        return -1;
+    uint32_t *va = calloc((size_t)h, sizeof(uint32_t)), *vb = calloc((size_t)h, sizeof(uint32_t));
+    uint32_t *vo = calloc((size_t)2 * h, sizeof(uint32_t));
+    int rc = (va && vb && vo) ? 0 : -1;
+    for (size_t c = 0; c < ncols && !rc; c++) {
+        for (int t = 0; t < h; t++) {
+            va[t] = get_sym(r, a + (size_t)t * stride, c);
+            vb[t] = get_sym(r, b + (size_t)t * stride, c);
+        }
+        rc = orc_polymul_fft(r, basis, h, l, va, vb, vo);
+        for (int t = 0; t < 2 * h && !rc; t++)
+            put_sym(r, out + (size_t)t * stride, c, vo[t]);
+    }
+    free(va); free(vb); free(vo);
+    return rc;
+}
+
+ORC_EXPORT int orc_degree_rows(int r, int h, const uint8_t *data, size_t stride, size_t ncols, int32_t *deg)
+{
+    if (!field_ok(r) || h < 1 || !data || !deg)
+        return -1;
+    for (size_t c = 0; c < ncols; c++) {
+        deg[c] = -1;
+        for (int j = h - 1; j >= 0; j--)
+            if (get_sym(r, data + (size_t)j * stride, c)) {
+                deg[c] = j;
+                break;
+            }
+    }
+    return 0;
+}
+
+/* In place, column by column: novel -> monomial (to_mono != 0) or back. */
+ORC_EXPORT int orc_convert_rows(int r, const uint32_t *basis, int h, int to_mono, uint8_t *data, size_t stride,
+                                size_t ncols)
+{
+    if (!field_ok(r) || h < 1 || h > (1 << r) || !data)
+        return -1;
+    uint32_t *xt = x_table(r, basis, h);
+    uint32_t *v = calloc((size_t)h, sizeof(uint32_t)), *o = calloc((size_t)h, sizeof(uint32_t));
+    uint32_t *work = calloc((size_t)h, sizeof(uint32_t));
+    int rc = (xt && v && o && work) ? 0 : -1;
+    for (size_t c = 0; c < ncols && !rc; c++) {
+        for (int t = 0; t < h; t++)
+            v[t] = get_sym(r, data + (size_t)t * stride, c);
+        if (to_mono)
+            to_mono_tab(r, h, xt, v, o);
+        else
+            from_mono_tab(r, h, xt, v, o, work);
+        for (int t = 0; t < h; t++)
+            put_sym(r, data + (size_t)t * stride, c, o[t]);
+    }
+    free(xt); free(v); free(o); free(work);
+    return rc;
+}

@@ -128,11 +128,44 @@ def run():
                 return False
         return True
 
+    def polymul_is_the_product():
+        # values at 2h points of another coset, by naive evaluation of the basis
+        for r, h, l in ((8, 8, 3), (16, 16, 100)):
+            a, b = _syms(r, h, 1), _syms(r, h, 2)
+            c = oracle.polymul(r, a, b, l)
+            z = np.zeros(h, dtype=np.uint32)
+            shift = (1 << r) - 2 * h
+            va = oracle.eval_naive(r, np.concatenate([a, z]), shift)
+            vb = oracle.eval_naive(r, np.concatenate([b, z]), shift)
+            vc = oracle.eval_naive(r, c, shift)
+            if not all(int(vc[j]) == oracle.mul(r, int(va[j]), int(vb[j])) for j in range(2 * h)):
+                return False
+        return True
+
+    def conversion_and_degree():
+        for r, h in ((8, 32), (16, 16)):
+            d = _syms(r, h, 3)
+            d[h - 3:] = 0
+            m = oracle.to_monomial(r, d)
+            if not (oracle.from_monomial(r, m) == d).all():
+                return False
+            if oracle.degree(d) != int(np.nonzero(m)[0][-1]):
+                return False
+            e = np.zeros(h, dtype=np.uint32)
+            e[h - 1] = 1
+            x = np.zeros(h, dtype=np.uint32)
+            x[:h] = oracle.X_monomial(r, h - 1)
+            if not (oracle.from_monomial(r, x) == e).all():
+                return False
+        return True
+
     for name, fn in (("alpha_order", alpha_order), ("inverse_and_distributive", inverse_and_distributive),
                      ("transform_equals_naive", transform_equals_naive), ("round_trip", round_trip),
                      ("op_counts", op_counts), ("derivative_three_ways", derivative_three_ways),
                      ("encode_equals_lagrange", encode_equals_lagrange),
                      ("decode_every_pattern", decode_every_pattern), ("decode_shortened", decode_shortened),
-                     ("locator_fwht_equals_direct", locator_fwht_equals_direct)):
+                     ("locator_fwht_equals_direct", locator_fwht_equals_direct),
+                     ("polymul_is_the_product", polymul_is_the_product),
+                     ("conversion_and_degree", conversion_and_degree)):
         _check(fails, name, fn)
     return fails

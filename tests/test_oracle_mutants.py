@@ -38,6 +38,12 @@ MUTANTS = [
      "out[j] = orc_mul(r, acc, orc_inv(r, B[j]));", "out[j] = orc_mul(r, acc, B[j]);"),
     ("locator without the 1/N normalisation",
      "uint64_t ninv = ((uint64_t)1 << (r - ilog2(N))) % M;", "uint64_t ninv = 1;"),
+    ("product without the zero padding of b",
+     "memcpy(tb, b, sizeof(uint32_t) * (size_t)h);", "memcpy(tb, b, sizeof(uint32_t) * (size_t)h); tb[h] = b[0];"),
+    ("product transformed back forward", "    ifft_core(r, basis, H, l, f, out, NULL);\n    free(f); free(tb);",
+     "    fft_core(r, basis, H, l, f, out, NULL);\n    free(f); free(tb);"),
+    ("conversion divides by the wrong leading coefficient",
+     "d[j] = orc_mul(r, work[j], orc_inv(r, xj[j]));", "d[j] = orc_mul(r, work[j], orc_inv(r, xj[0] ? xj[0] : 1));"),
     ("decode divides by Pi' squared",
      "cst[p] = orc_inv(r, cst[p]);              /* divisor of step 6 */",
      "cst[p] = orc_inv(r, orc_mul(r, cst[p], cst[p]));"),
