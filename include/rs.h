@@ -97,6 +97,31 @@ int nb_ifft(rs_ctx *ctx, int h, uint32_t l, void *data, size_t row_bytes, void *
  * [D_h](x) by those of [D_h]'(x), in place; h as for nb_fft. */
 int nb_derivative(rs_ctx *ctx, int h, void *data, size_t row_bytes, void *stream);
 
+/* Product in the novel basis (Sec. 5): for each column, out holds the 2h
+ * coefficients of [A_h](x) [B_h](x), computed as the inverse transform
+ * Psi_2h^l of the point-by-point product of the transforms Psi_2h^l of A and
+ * B padded with h zero coefficients (the last output coefficient is zero).
+ * a and b: h rows; out: 2h rows, overlapping neither (RS_EINVAL).  h a power
+ * of two with 2h <= 2^r (RS_ESHAPE); l < 2^r (any l: the 2h points
+ * omega_b + omega_l are distinct, and the product does not depend on l).
+ * Uses the stream's scratch of the context (2h rows). */
+int nb_polymul(rs_ctx *ctx, int h, uint32_t l, const void *a, const void *b, void *out, size_t row_bytes,
+               void *stream);
+
+/* Degree (Sec. 5): deg[c] (device, one int32 per column) = the largest j < h
+ * whose coefficient in column c is nonzero (deg X_j = j), or -1.
+ * 1 <= h <= 2^r (any h). */
+int nb_degree(rs_ctx *ctx, int h, const void *data, size_t row_bytes, int32_t *deg, void *stream);
+
+/* Basis conversion in place, each column a polynomial of degree < h: novel
+ * -> monomial coefficients of x^0 .. x^(h-1), and back.  Computed level by
+ * level from X_{i + 2^(t-1)} = X_i What_{t-1} (Definition 1) and the
+ * monomials of What_{t-1}, which sit at the degrees 2^m (Sec. 2.2):
+ * O(h lg^2 h) operations per column.  h a power of two <= 2^r.
+ * nb_to_monomial uses the stream's scratch of the context (h rows). */
+int nb_to_monomial(rs_ctx *ctx, int h, void *data, size_t row_bytes, void *stream);
+int nb_from_monomial(rs_ctx *ctx, int h, void *data, size_t row_bytes, void *stream);
+
 /* One stripe of a batch.  Encode: in = k message rows, out = n - k parity
  * rows.  Decode: in = n shard rows, out = n rows (may equal in). */
 typedef struct rs_stripe_desc {

@@ -288,6 +288,13 @@ hipError_t init_tables(int r, const uint32_t *d_basis, uint32_t *d_Wv, uint32_t 
     return hipGetLastError();
 }
 
+// Perm tables of `count` field elements (vals, device) into tabs.
+hipError_t perm_tables(int r, const uint32_t *vals, uint32_t count, uint32_t *tabs, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_init_perm, dim3(8), dim3(256), 0, s, r, vals, count, tabs);
+    return hipGetLastError();
+}
+
 hipError_t init_prepare(int r)
 {
     const int lds = (int)((1u << r) * 2);

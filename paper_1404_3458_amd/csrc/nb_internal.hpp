@@ -68,6 +68,21 @@ struct PassArgs {
     int32_t post_B;           // multiply rows by B_p after the levels
 };
 
+// Polynomial operations of Sec. 5 (nb_poly.hip): padding, point-by-point
+// product, degree and basis conversion; each kernel reads the fields it needs.
+struct PolyArgs {
+    const uint8_t *src;       // rows read
+    const uint8_t *src2;      // the second operand (point-by-point product)
+    uint8_t *dst;             // rows written
+    int32_t *deg;             // degree, one entry per column
+    uint64_t row_bytes;
+    int32_t ncols, col0, nct; // columns, first column of the launch, its column tiles
+    int32_t rows;             // rows of the operation
+    int32_t src_rows;         // padding: rows copied, the rest written as zero
+    int32_t t;                // conversion level (blocks of 2^t rows)
+    int32_t e0, e1;           // division: quotient entries [e0, e1) of each block; e1 == 0: the remainder
+};
+
 // Derivative partial pass (Sec. 4.2 split over level ranges): for the rows
 // p of each group, z_p (+)= sum of y_{p + 2^l} over the levels l of the pass
 // with bit l of p clear.  first: z is written instead of accumulated.

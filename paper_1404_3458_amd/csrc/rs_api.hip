@@ -27,6 +27,10 @@ hipError_t loc_pass_launch(const LocPassArgs &a, const KPtrs &k, const uint32_t 
                            int ngroups, hipStream_t s);
 hipError_t fused_prepare_16();
 hipError_t fused_prepare_8();
+hipError_t poly_launch(int r, int ld, int kind, const PolyArgs &a, const uint32_t *t1, const uint32_t *t2,
+                       uint32_t nblocks, hipStream_t s);
+hipError_t perm_tables(int r, const uint32_t *vals, uint32_t count, uint32_t *tabs, hipStream_t s);
+enum { PK_PAD = 0, PK_MUL = 1, PK_DEGREE = 2, PK_UP = 3, PK_DOWN = 4 };
 hipError_t fused_launch_16(int mode, int sh, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
                            hipStream_t s);
 hipError_t fused_launch_8(int mode, int sh, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
@@ -106,6 +110,7 @@ struct rs_ctx {
     void *d_mem = nullptr;
     uint32_t *d_basis, *d_Wv, *d_S, *d_wp, *d_skew, *d_B, *d_Binv, *d_exp, *d_log, *d_FL;
     uint32_t *d_tw_tab, *d_B_tab, *d_Binv_tab;
+    uint32_t *d_wh, *d_wh_tab;  // What_j monomial coefficients (16 j + m) and 1 / leading (256 + j); perm tables
     KPtrs kp;           // method tables (masks / rowtabs filled per call)
     std::mutex mu;
     std::vector<Scratch *> scratch;
@@ -945,37 +950,15 @@ int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, in
     return exec_codec(ctx, cp, dev, stream);
 }
 
-int run_xform(rs_ctx *ctx, int mode, int h, uint32_t l, void *data, size_t rb, hipStream_t stream)
+// The transform (mode MODE_FFT / MODE_IFFT / MODE_DERIV) of h rows of d in
+// place, with the context locked and the stream's scratch at hand.
+int xform_locked(rs_ctx *ctx, Scratch *sc, int mode, int h, uint32_t l, uint8_t *d, size_t rb, hipStream_t stream)
 {
-    if (!ctx)
-        return RS_EINVAL;
-    if (!is_pow2(h) || h > (1 << ctx->r))
-        return RS_ESHAPE;
-    if (l >= (1u << ctx->r))
-        return RS_EINVAL;
-    if (rb % (size_t)sym_bytes(ctx))
-        return RS_EALIGN;
-    if (rb == 0)
-        return RS_OK;
-    if (!data)
-        return RS_EINVAL;
-    if (rb / sym_bytes(ctx) > (size_t)INT32_MAX / 2)
-        return RS_ESHAPE;
-    DeviceGuard guard(ctx->device);
-    if (!guard.ok)
-        return RS_EDEVICE;
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    if (ctx->sticky)
-        return ctx->sticky;
-    Scratch *sc = get_scratch(ctx, stream);
-    if (!sc)
-        return RS_ENOMEM;
     const int L = ilog2(h);
     const int ncols = (int)(rb / sym_bytes(ctx));
-    const bool aligned = vec_aligned(ctx, data, data, rb);
+    const bool aligned = vec_aligned(ctx, d, d, rb);
     // with h | l every factor is a plain table entry; otherwise bit i of l adds 1
     const bool gen_l = mode != MODE_DERIV && (l & (uint32_t)(h - 1)) != 0;
-    uint8_t *d = (uint8_t *)data;
     if (mode == MODE_DERIV && L == 0)
         return fill_zero(ctx, stream, d, rb);
     if (L <= FUSED_MAX_L) {
@@ -1021,6 +1004,34 @@ int run_xform(rs_ctx *ctx, int mode, int h, uint32_t l, void *data, size_t rb, h
     return rc;
 }
 
+int run_xform(rs_ctx *ctx, int mode, int h, uint32_t l, void *data, size_t rb, hipStream_t stream)
+{
+    if (!ctx)
+        return RS_EINVAL;
+    if (!is_pow2(h) || h > (1 << ctx->r))
+        return RS_ESHAPE;
+    if (l >= (1u << ctx->r))
+        return RS_EINVAL;
+    if (rb % (size_t)sym_bytes(ctx))
+        return RS_EALIGN;
+    if (rb == 0)
+        return RS_OK;
+    if (!data)
+        return RS_EINVAL;
+    if (rb / sym_bytes(ctx) > (size_t)INT32_MAX / 2)
+        return RS_ESHAPE;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return RS_EDEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->sticky)
+        return ctx->sticky;
+    Scratch *sc = get_scratch(ctx, stream);
+    if (!sc)
+        return RS_ENOMEM;
+    return xform_locked(ctx, sc, mode, h, l, (uint8_t *)data, rb, stream);
+}
+
 bool basis_independent(int r, const uint32_t *b)
 {
     uint32_t rows[16];
@@ -1046,6 +1057,85 @@ bool basis_independent(int r, const uint32_t *b)
         rank++;
     }
     return rank == r;
+}
+
+// ------------------------------------------------------------------ polynomial operations (Sec. 5)
+
+// Launch one nb_poly kernel over every column part of a call; per_tile:
+// workgroups per column tile (rows of the operation, or 1 for the degree).
+int poly_run(rs_ctx *ctx, hipStream_t s, int kind, PolyArgs a, bool aligned, uint32_t per_tile, const uint32_t *t1,
+             const uint32_t *t2)
+{
+    for (const ColPart &cp : col_parts(aligned, a.ncols)) {
+        a.col0 = cp.col0;
+        a.nct = cp.ntiles;
+        if (dev_err(ctx, poly_launch(ctx->r, cp.ld, kind, a, t1, t2, per_tile * (uint32_t)cp.ntiles, s)))
+            return RS_EDEVICE;
+    }
+    return RS_OK;
+}
+
+PolyArgs poly_args(const void *src, const void *src2, void *dst, size_t rb, int ncols)
+{
+    PolyArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.src = (const uint8_t *)src;
+    a.src2 = (const uint8_t *)src2;
+    a.dst = (uint8_t *)dst;
+    a.row_bytes = rb;
+    a.ncols = ncols;
+    return a;
+}
+
+bool ranges_overlap(const void *p, size_t pn, const void *q, size_t qn)
+{
+    const uintptr_t a = (uintptr_t)p, b = (uintptr_t)q;
+    return a < b + qn && b < a + pn;
+}
+
+// Shared argument checks of the polynomial calls (rows: rows of the
+// operand; pow2: rows must be a power of two).
+int poly_check(const rs_ctx *ctx, long rows, bool pow2, size_t rb)
+{
+    if (!ctx)
+        return RS_EINVAL;
+    if (rows < 1 || rows > (1L << ctx->r) || (pow2 && !is_pow2(rows)))
+        return RS_ESHAPE;
+    if (rb % (size_t)sym_bytes(ctx))
+        return RS_EALIGN;
+    if (rb / sym_bytes(ctx) > (size_t)INT32_MAX / 2)
+        return RS_ESHAPE;
+    return RS_OK;
+}
+
+// Monomial coefficients of the normalized subspace polynomials What_j,
+// j < r, for the basis conversion: W_0(x) = x and W_{j+1}(x) =
+// W_j(x) (W_j(x) + W_j(v_j)) (Sec. 2.2; W_j is F2-linear, so
+// W_j(x + v_j) = W_j(x) + W_j(v_j)), i.e. with W_j(x) = sum_m a_m x^(2^m)
+// in characteristic 2, a'_m = a_{m-1}^2 + W_j(v_j) a_m; What_j = W_j / W_j(v_j).
+// Entry 16 j + m holds the coefficient of x^(2^m) in What_j; entry 256 + j
+// the inverse of its leading coefficient.
+constexpr uint32_t WH_COUNT = 512;
+
+void what_coefficients(int r, const uint32_t *basis, std::vector<uint32_t> &out)
+{
+    out.assign(WH_COUNT, 0u);
+    uint32_t a[17] = {1u};
+    for (int j = 0; j < r; j++) {
+        uint32_t wv = 0, vp = basis[j];                 // W_j(v_j), vp = v_j^(2^m)
+        for (int m = 0; m <= j; m++) {
+            wv ^= gf_mul(a[m], vp, r);
+            vp = gf_mul(vp, vp, r);
+        }
+        const uint32_t iv = gf_inv(wv, r);
+        for (int m = 0; m <= j; m++)
+            out[16 * j + m] = gf_mul(a[m], iv, r);
+        out[256 + j] = gf_inv(out[16 * j + j], r);
+        uint32_t nx[17] = {0u};
+        for (int m = 0; m <= j + 1; m++)
+            nx[m] = (m ? gf_mul(a[m - 1], a[m - 1], r) : 0u) ^ (m <= j ? gf_mul(wv, a[m], r) : 0u);
+        std::memcpy(a, nx, sizeof(a));
+    }
 }
 
 // A pass-pipeline schedule is valid for transforms over 2^N > 256 points
@@ -1137,8 +1227,10 @@ __attribute__((visibility("default"))) int rs_init(int r, const uint32_t *basis,
     const int ts = r == 16 ? TAB16 : TAB8;
     // dword counts of every table, one allocation
     const size_t n_basis = 16, n_Wv = 256, n_S = 256, n_wp = 16, n_skew = q, n_B = q, n_Binv = q, n_exp = q,
-                 n_log = q, n_FL = 2 * q, n_tw = ts * q, n_Bt = ts * q, n_Binvt = ts * q;
-    const size_t sizes[] = {n_basis, n_Wv, n_S, n_wp, n_skew, n_B, n_Binv, n_exp, n_log, n_FL, n_tw, n_Bt, n_Binvt};
+                 n_log = q, n_FL = 2 * q, n_tw = ts * q, n_Bt = ts * q, n_Binvt = ts * q, n_wh = WH_COUNT,
+                 n_wht = ts * WH_COUNT;
+    const size_t sizes[] = {n_basis, n_Wv, n_S,  n_wp,   n_skew, n_B,  n_Binv, n_exp,
+                            n_log,   n_FL, n_tw, n_Bt, n_Binvt, n_wh, n_wht};
     size_t total = 0;
     for (size_t s : sizes)
         total += align_up(s * 4, 256);
@@ -1146,8 +1238,9 @@ __attribute__((visibility("default"))) int rs_init(int r, const uint32_t *basis,
         delete ctx;
         return RS_ENOMEM;
     }
-    uint32_t **dst[] = {&ctx->d_basis, &ctx->d_Wv, &ctx->d_S, &ctx->d_wp, &ctx->d_skew, &ctx->d_B, &ctx->d_Binv,
-                        &ctx->d_exp, &ctx->d_log, &ctx->d_FL, &ctx->d_tw_tab, &ctx->d_B_tab, &ctx->d_Binv_tab};
+    uint32_t **dst[] = {&ctx->d_basis, &ctx->d_Wv,  &ctx->d_S,      &ctx->d_wp,    &ctx->d_skew,
+                        &ctx->d_B,     &ctx->d_Binv, &ctx->d_exp,    &ctx->d_log,   &ctx->d_FL,
+                        &ctx->d_tw_tab, &ctx->d_B_tab, &ctx->d_Binv_tab, &ctx->d_wh, &ctx->d_wh_tab};
     size_t off = 0;
     for (size_t i = 0; i < sizeof(sizes) / sizeof(sizes[0]); i++) {
         *dst[i] = (uint32_t *)((uint8_t *)ctx->d_mem + off);
@@ -1159,6 +1252,12 @@ __attribute__((visibility("default"))) int rs_init(int r, const uint32_t *basis,
     if (e == hipSuccess)
         e = init_tables(r, ctx->d_basis, ctx->d_Wv, ctx->d_S, ctx->d_wp, ctx->d_skew, ctx->d_B, ctx->d_Binv,
                         ctx->d_exp, ctx->d_log, ctx->d_FL, ctx->d_tw_tab, ctx->d_B_tab, ctx->d_Binv_tab, nullptr);
+    std::vector<uint32_t> wh;
+    what_coefficients(r, b, wh);
+    if (e == hipSuccess)
+        e = hipMemcpy(ctx->d_wh, wh.data(), sizeof(uint32_t) * WH_COUNT, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = perm_tables(r, ctx->d_wh, WH_COUNT, ctx->d_wh_tab, nullptr);
     if (e == hipSuccess)
         e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -1275,6 +1374,153 @@ __attribute__((visibility("default"))) int nb_derivative(rs_ctx *ctx, int h, voi
                                                          void *stream)
 {
     return run_xform(ctx, MODE_DERIV, h, 0, data, row_bytes, (hipStream_t)stream);
+}
+
+__attribute__((visibility("default"))) int nb_polymul(rs_ctx *ctx, int h, uint32_t l, const void *a, const void *b,
+                                                      void *out, size_t row_bytes, void *stream_)
+{
+    const hipStream_t stream = (hipStream_t)stream_;
+    int rc = poly_check(ctx, 2L * h, true, row_bytes);
+    if (rc)
+        return rc;
+    if (l >= (1u << ctx->r))
+        return RS_EINVAL;
+    if (row_bytes == 0)
+        return RS_OK;
+    const size_t rb = row_bytes, in_bytes = (size_t)h * rb, out_bytes = 2 * in_bytes;
+    if (!a || !b || !out || ranges_overlap(out, out_bytes, a, in_bytes) || ranges_overlap(out, out_bytes, b, in_bytes))
+        return RS_EINVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return RS_EDEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->sticky)
+        return ctx->sticky;
+    Scratch *sc = get_scratch(ctx, stream);
+    if (!sc)
+        return RS_ENOMEM;
+    uint8_t *Z;
+    if ((rc = big_scratch(sc, out_bytes, &Z)))
+        return rc;
+    const int H = 2 * h, ncols = (int)(rb / sym_bytes(ctx));
+    // A and B padded with zeros to 2h coefficients
+    PolyArgs pa = poly_args(a, nullptr, out, rb, ncols);
+    pa.rows = H;
+    pa.src_rows = h;
+    if ((rc = poly_run(ctx, stream, PK_PAD, pa, vec_aligned(ctx, a, out, rb), (uint32_t)H, nullptr, nullptr)))
+        return rc;
+    pa.src = (const uint8_t *)b;
+    pa.dst = Z;
+    if ((rc = poly_run(ctx, stream, PK_PAD, pa, vec_aligned(ctx, b, Z, rb), (uint32_t)H, nullptr, nullptr)))
+        return rc;
+    // both transformed at 2h points, multiplied point by point, transformed back
+    if ((rc = xform_locked(ctx, sc, MODE_FFT, H, l, (uint8_t *)out, rb, stream)))
+        return rc;
+    if ((rc = xform_locked(ctx, sc, MODE_FFT, H, l, Z, rb, stream)))
+        return rc;
+    PolyArgs pm = poly_args(nullptr, Z, out, rb, ncols);
+    pm.rows = H;
+    if ((rc = poly_run(ctx, stream, PK_MUL, pm, vec_aligned(ctx, out, Z, rb), (uint32_t)H, ctx->d_log, ctx->d_exp)))
+        return rc;
+    return xform_locked(ctx, sc, MODE_IFFT, H, l, (uint8_t *)out, rb, stream);
+}
+
+__attribute__((visibility("default"))) int nb_degree(rs_ctx *ctx, int h, const void *data, size_t row_bytes,
+                                                     int32_t *deg, void *stream_)
+{
+    const hipStream_t stream = (hipStream_t)stream_;
+    int rc = poly_check(ctx, h, false, row_bytes);
+    if (rc)
+        return rc;
+    if (row_bytes == 0)
+        return RS_OK;
+    if (!data || !deg)
+        return RS_EINVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return RS_EDEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->sticky)
+        return ctx->sticky;
+    PolyArgs pa = poly_args(data, nullptr, nullptr, row_bytes, (int)(row_bytes / sym_bytes(ctx)));
+    pa.deg = deg;
+    pa.rows = h;
+    return poly_run(ctx, stream, PK_DEGREE, pa, vec_aligned(ctx, data, data, row_bytes), 1u, nullptr, nullptr);
+}
+
+// Shared body of the two conversions.
+static int convert(rs_ctx *ctx, int h, void *data, size_t rb, hipStream_t stream, bool to_mono)
+{
+    int rc = poly_check(ctx, h, true, rb);
+    if (rc)
+        return rc;
+    if (rb == 0 || h == 1)
+        return RS_OK;                                    // X_0 = 1
+    if (!data)
+        return RS_EINVAL;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return RS_EDEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->sticky)
+        return ctx->sticky;
+    const int L = ilog2(h), ncols = (int)(rb / sym_bytes(ctx));
+    uint8_t *d = (uint8_t *)data;
+    const bool aligned = vec_aligned(ctx, d, d, rb);
+    if (to_mono) {
+        Scratch *sc = get_scratch(ctx, stream);
+        if (!sc)
+            return RS_ENOMEM;
+        uint8_t *Z;
+        if ((rc = big_scratch(sc, (size_t)h * rb, &Z)))
+            return rc;
+        uint8_t *cur = d, *oth = Z;
+        for (int t = 1; t <= L; t++) {
+            PolyArgs pa = poly_args(cur, nullptr, oth, rb, ncols);
+            pa.rows = h;
+            pa.t = t;
+            if ((rc = poly_run(ctx, stream, PK_UP, pa, aligned, (uint32_t)h, ctx->d_wh_tab, nullptr)))
+                return rc;
+            std::swap(cur, oth);
+        }
+        if (cur != d) {                                  // odd level count: copy back
+            PolyArgs pa = poly_args(cur, nullptr, d, rb, ncols);
+            pa.rows = pa.src_rows = h;
+            return poly_run(ctx, stream, PK_PAD, pa, aligned, (uint32_t)h, nullptr, nullptr);
+        }
+        return RS_OK;
+    }
+    for (int t = L; t >= 1; t--) {
+        const int hh = 1 << (t - 1), nblk = h >> t;
+        PolyArgs pa = poly_args(nullptr, nullptr, d, rb, ncols);
+        pa.rows = h;
+        pa.t = t;
+        for (int e1 = hh; e1 > 0; e1 /= 2) {             // quotient ranges, top first
+            pa.e1 = e1;
+            pa.e0 = e1 / 2;
+            if ((rc = poly_run(ctx, stream, PK_DOWN, pa, aligned, (uint32_t)(nblk * (pa.e1 - pa.e0)), ctx->d_wh_tab,
+                               nullptr)))
+                return rc;
+        }
+        if (t > 1) {                                     // remainders (t = 1: the coefficient itself)
+            pa.e0 = pa.e1 = 0;
+            if ((rc = poly_run(ctx, stream, PK_DOWN, pa, aligned, (uint32_t)(nblk * hh), ctx->d_wh_tab, nullptr)))
+                return rc;
+        }
+    }
+    return RS_OK;
+}
+
+__attribute__((visibility("default"))) int nb_to_monomial(rs_ctx *ctx, int h, void *data, size_t row_bytes,
+                                                          void *stream)
+{
+    return convert(ctx, h, data, row_bytes, (hipStream_t)stream, true);
+}
+
+__attribute__((visibility("default"))) int nb_from_monomial(rs_ctx *ctx, int h, void *data, size_t row_bytes,
+                                                            void *stream)
+{
+    return convert(ctx, h, data, row_bytes, (hipStream_t)stream, false);
 }
 
 struct rs_plan {

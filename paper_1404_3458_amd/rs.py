@@ -147,6 +147,10 @@ def load():
             "nb_fft": (i32, [vp, i32, u32, vp, sz, vp]),
             "nb_ifft": (i32, [vp, i32, u32, vp, sz, vp]),
             "nb_derivative": (i32, [vp, i32, vp, sz, vp]),
+            "nb_polymul": (i32, [vp, i32, u32, vp, vp, vp, sz, vp]),
+            "nb_degree": (i32, [vp, i32, vp, sz, vp, vp]),
+            "nb_to_monomial": (i32, [vp, i32, vp, sz, vp]),
+            "nb_from_monomial": (i32, [vp, i32, vp, sz, vp]),
             "rs_encode_batch": (i32, [vp, vp, i32, vp]),
             "rs_decode_batch": (i32, [vp, vp, vp, i32, vp]),
             "rs_plan_encode_batch": (i32, [vp, vp, i32, ctypes.POINTER(vp)]),
@@ -332,6 +336,38 @@ class Codec:
             _, row_bytes = _rows(data, h)
         return _check(load().nb_derivative(self._ctx, h, _ptr(data), row_bytes, _stream(stream)),
                       "nb_derivative")
+
+    # ------------------------------------------------------------ polynomial operations (Sec. 5)
+    def polymul(self, h, l, a, b, out, row_bytes=None, stream=None):
+        """out (2h rows) = product of the novel-basis polynomials in a and b (h rows each)."""
+        if row_bytes is None:
+            _, row_bytes = _rows(a, h)
+            _rows(b, h)
+            _rows(out, 2 * h)
+        return _check(load().nb_polymul(self._ctx, h, l, _ptr(a), _ptr(b), _ptr(out), row_bytes, _stream(stream)),
+                      "nb_polymul")
+
+    def degree(self, h, data, deg=None, row_bytes=None, stream=None):
+        """int32 tensor of the column degrees (-1 for zero columns)."""
+        import torch
+
+        if row_bytes is None:
+            _, row_bytes = _rows(data, h)
+        if deg is None:
+            deg = torch.empty(row_bytes // (self.r // 8), dtype=torch.int32, device=data.device)
+        _check(load().nb_degree(self._ctx, h, _ptr(data), row_bytes, _ptr(deg), _stream(stream)), "nb_degree")
+        return deg
+
+    def to_monomial(self, h, data, row_bytes=None, stream=None):
+        if row_bytes is None:
+            _, row_bytes = _rows(data, h)
+        return _check(load().nb_to_monomial(self._ctx, h, _ptr(data), row_bytes, _stream(stream)), "nb_to_monomial")
+
+    def from_monomial(self, h, data, row_bytes=None, stream=None):
+        if row_bytes is None:
+            _, row_bytes = _rows(data, h)
+        return _check(load().nb_from_monomial(self._ctx, h, _ptr(data), row_bytes, _stream(stream)),
+                      "nb_from_monomial")
 
     # ------------------------------------------------------------ schedules
     def set_schedule(self, op, N, T1):
