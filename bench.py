@@ -44,6 +44,12 @@ CONFIGS = {
                workload="GF(2^16) mod 0x1100B serving: Poisson arrivals, 70% encode / 30% decode requests, "
                         "(n,k) and shards as the mixed workload (5000 resident stripes), 64 GB admission budget; "
                         "saturated rate mu, then lambda = 0.5, 0.7, 0.9 mu with 5000 requests each after 500 warm-up"),
+    "poly": dict(r=16, h=4096, cols=32768, poly="mul",
+                 workload="GF(2^16) mod 0x1100B novel-basis product (Sec. 5): two operands of h = 4096 "
+                          "coefficients x 32768 columns, 8192-point transforms, point-by-point product, inverse"),
+    "conv": dict(r=16, h=4096, cols=32768, poly="conv",
+                 workload="GF(2^16) mod 0x1100B basis conversion novel -> monomial -> novel: h = 4096 "
+                          "coefficients x 32768 columns"),
     "c4": dict(r=16, stripes=8192, mixed=True,
                workload="GF(2^16) mod 0x1100B, 8192 stripes, (n,k) uniform over (16,8) (64,48) (256,224) "
                         "(1024,512) (4096,2048), shards log-uniform 1-64 KiB, erasures uniform in [0,n-k]; "
@@ -182,6 +188,143 @@ def schedule_for(args, codec, shapes):
         src = "autotuned"
     return {"source": src, "setup_s": round(time.perf_counter() - t0, 2), "T1": tune.summary(tab),
             "candidate_ms": {"%s:%d" % (e["op"], e["N"]): e.get("ms") for e in tab["entries"]}}
+
+
+def conv_mults_per_column(h):
+    """Constant multiplications of the two basis conversions of one column,
+    as the kernels do them: level t of the way up, one per (output row, m)
+    with a term; level t of the way down, one per quotient term plus the
+    division, and one per remainder term."""
+    L = h.bit_length() - 1
+    up = down = 0
+    for t in range(1, L + 1):
+        hh, blocks = 1 << (t - 1), h >> t
+        up += blocks * sum(1 for j in range(2 * hh) for m in range(t) if 0 <= j - (1 << m) < hh)
+        q = sum(1 + sum(1 for m in range(t - 1) if (1 << m) > e) for e in range(hh))
+        rem = sum(1 for j in range(hh) for m in range(t - 1) if (1 << m) <= j) if t > 1 else 0
+        down += blocks * (q + rem)
+    return up + down
+
+
+def run_poly(args, cfg):
+    """Polynomial operations of Sec. 5 on a fixed synthetic batch of columns:
+    the product (nb_polymul) or the conversion round trip (nb_to_monomial then
+    nb_from_monomial)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1404_3458_amd import rs, synth
+
+    r, h, nc = cfg["r"], cfg["h"], cfg["cols"]
+    sb = r // 8
+    rb = nc * sb
+    torch.cuda.set_device(0)
+    codec = rs.Codec(r)
+    stream = torch.cuda.current_stream()
+    a = torch.empty((h, rb), dtype=torch.uint8, device="cuda")
+    synth.fill_random_torch(synth.key(cfg["id"], 1, synth.DATA), a)
+    mul = cfg["poly"] == "mul"
+    if mul:
+        b = torch.empty_like(a)
+        synth.fill_random_torch(synth.key(cfg["id"], 2, synth.DATA), b)
+        out = torch.empty((2 * h, rb), dtype=torch.uint8, device="cuda")
+
+        def step():
+            codec.polymul(h, 0, a, b, out)
+    else:
+        x = a.clone()
+
+        def step():
+            codec.to_monomial(h, x)
+            codec.from_monomial(h, x)
+    cols = [0, 1, nc // 3, nc - 1] if mul else [0, nc - 1]
+    if not args.no_check:
+        pick = lambda t: np.ascontiguousarray(
+            t.cpu().numpy().reshape(t.shape[0], nc, sb)[:, cols, :].reshape(t.shape[0], len(cols) * sb))
+        if mul:
+            step()
+            torch.cuda.synchronize()
+            assert (pick(out) == oracle.polymul_rows(r, pick(a), pick(b), 0)).all(), "product differs from the oracle"
+        else:
+            codec.to_monomial(h, x)
+            torch.cuda.synchronize()
+            assert (pick(x) == oracle.convert_rows(r, pick(a), True)).all(), "monomial form differs from the oracle"
+            codec.from_monomial(h, x)
+            torch.cuda.synchronize()
+            assert torch.equal(x, a), "conversion round trip"
+    for _ in range(args.warmup):
+        step()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        step()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    t = float(ms.mean()) * 1e-3
+    H = 2 * h
+    if mul:
+        per_col = 3 * ((H // 2) * (H.bit_length() - 1) - (H - 1)) + H      # Sec. 3.4 counts at shift 0
+        nbytes = 2 * h * rb                                                 # operand coefficients
+        algo_bytes = 2 * h * rb + H * rb
+    else:
+        per_col = conv_mults_per_column(h)
+        nbytes = 2 * h * rb                                                 # two conversions of h rows
+        algo_bytes = 4 * h * rb
+    mults = per_col * nc
+    peak = mult_peak_per_s(r)
+    cpu = None
+    if not args.no_cpu:
+        threads = min(16, len(os.sched_getaffinity(0)))
+        sc = 256 if mul else 4
+        sample = np.ascontiguousarray(a[:, :sc * sb].cpu().numpy())
+        sample2 = np.ascontiguousarray(b[:, :sc * sb].cpu().numpy()) if mul else None
+        t1 = time.perf_counter()
+        if mul:
+            import concurrent.futures as cf
+
+            per = max(1, sc // threads)
+            parts = [(c0, min(sc, c0 + per)) for c0 in range(0, sc, per)]
+            with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+                list(ex.map(lambda p: oracle.polymul_rows(r, np.ascontiguousarray(sample[:, p[0] * sb:p[1] * sb]),
+                                                          np.ascontiguousarray(sample2[:, p[0] * sb:p[1] * sb]), 0),
+                            parts))
+            used = threads
+        else:
+            m = oracle.convert_rows(r, sample.copy(), True)
+            oracle.convert_rows(r, m, False)
+            used = 1
+        dt = time.perf_counter() - t1
+        cpu = {"value": round(2 * h * sc * sb / dt / 1e9, 6), "unit": "GB/s", "cores": used, "kind": "oracle",
+               "sample": "%d columns of the same operands (%s), %.2f s wall" %
+                         (sc, "product by the oracle's transforms" if mul else
+                          "the oracle's O(h^2) conversion both ways", dt)}
+        cpu["ratio_gpu_over_cpu"] = round(nbytes / t / 1e9 / cpu["value"], 1)
+    out = {
+        "metric": "polynomial %s GB/s of operand coefficients" % ("product" if mul else "basis conversion"),
+        "value": round(nbytes / t / 1e9, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(float(ms.mean()), 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u16" if r == 16 else "u8",
+        "data": "synthetic (seeded splitmix64 bytes)",
+        "config": {"workload": cfg["workload"], "field_bits": r, "h": h, "columns": nc,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": round(mults / t / 1e12, 4), "peak": round(peak / 1e12, 4),
+                     "unit": "Tmul/s", "frac": round(mults / t / peak, 4), "traffic": None,
+                     "kernel": "whole call (all launches)", "algorithmic_mults_per_step": mults,
+                     "algorithmic_bytes_per_step": algo_bytes,
+                     "hbm_GBps": round(algo_bytes / t / 1e9, 1), "hbm_peak_GBps": HBM_PEAK_GBS,
+                     "hbm_frac": round(algo_bytes / t / 1e9 / HBM_PEAK_GBS, 4)},
+        "cpu_baseline": cpu,
+        "detail": {"step_ms_p50": round(float(np.percentile(ms, 50)), 4),
+                   "step_ms_p99": round(float(np.percentile(ms, 99)), 4), "wall_ms_per_step": round(wall, 4),
+                   "mults_per_column": per_col},
+    }
+    print(json.dumps(out))
+    codec.close()
 
 
 def run_mixed(args, cfg):
@@ -511,7 +654,9 @@ def main():
         return
 
     cfg = dict(CONFIGS[args.config])
-    cfg["id"] = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c5": 5}[args.config]
+    cfg["id"] = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c5": 5, "poly": 6, "conv": 7}[args.config]
+    if cfg.get("poly"):
+        return run_poly(args, cfg)
     if cfg.get("mixed"):
         return run_mixed(args, cfg)
     if cfg.get("serving"):

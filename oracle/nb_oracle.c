@@ -902,17 +902,40 @@ ORC_EXPORT int orc_poly_mul(int r, int la, const uint32_t *a, int lb, const uint
 }
 
 /* Row i of the table holds the i + 1 monomial coefficients of X_i
- * (Definition 1), i < h; entries above the diagonal are zero. */
+ * (Definition 1: the product of What_j over the set bits j of i), i < h;
+ * entries above the diagonal are zero.  Row i is row i - 2^j times What_j
+ * for the highest set bit j of i; What_j has nonzero monomials only at the
+ * degrees 2^m (Sec. 2.2), and the product skips its zero coefficients. */
 static uint32_t *x_table(int r, const uint32_t *basis, int h)
 {
     uint32_t *t = calloc((size_t)h * (size_t)h, sizeof(uint32_t));
-    if (!t)
+    uint32_t *wh = calloc((size_t)h + 1, sizeof(uint32_t));
+    if (!t || !wh) {
+        free(t); free(wh);
         return NULL;
-    for (int i = 0; i < h; i++)
-        if (orc_X_monomial(r, basis, (uint32_t)i, t + (size_t)i * h)) {
-            free(t);
+    }
+    t[0] = 1;                                       /* X_0 = 1 */
+    for (int j = 0; (1 << j) < h; j++) {
+        const int dj = 1 << j;
+        if (orc_W_monomial(r, basis, j, wh)) {
+            free(t); free(wh);
             return NULL;
         }
+        const uint32_t inv = orc_inv(r, orc_W(r, basis, j, orc_omega(r, basis, (uint32_t)dj)));
+        for (int m = 0; m <= dj; m++)
+            wh[m] = orc_mul(r, wh[m], inv);
+        for (int i = dj; i < 2 * dj && i < h; i++) {
+            const uint32_t *src = t + (size_t)(i - dj) * h;   /* X_{i - 2^j}, degree i - 2^j */
+            uint32_t *dst = t + (size_t)i * h;
+            for (int m = 0; m <= dj; m++) {
+                if (!wh[m])
+                    continue;
+                for (int e = 0; e <= i - dj; e++)
+                    dst[e + m] ^= orc_mul(r, src[e], wh[m]);
+            }
+        }
+    }
+    free(wh);
     return t;
 }
 
