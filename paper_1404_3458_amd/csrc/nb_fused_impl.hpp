@@ -58,7 +58,10 @@ __device__ __forceinline__ void deriv_regs(uint32_t (*x)[Traits<R>::NW], const T
 
 // ------------------------------------------------------------------ L <= 4
 
-template <int R, int L, int MODE, int SH, int LD>
+// PR: the pruned variant, for stripes some of whose forward-transform
+// outputs are never used (encode: parity rows of a shortened code that are
+// not stored; decode: groups of 16 points without an erased stored row).
+template <int R, int L, int MODE, int SH, int LD, bool PR = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_small(NB_FUSED_PARAMS)
 {
     constexpr int NW = Traits<R>::NW, NR = 1 << L;
@@ -96,7 +99,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         reg_levels<R, L, true, SH_ZERO, true>(x, 0, 0, tw0);
         const int nblocks = st.np / st.kp;
         const int npar = st.n - st.k;
-        for (int blk = 1; blk < nblocks; blk++) {
+        // only the stored parity rows are computed (pruned forward transforms)
+        for (int blk = 1; blk < nblocks && (!PR || (blk - 1) * NR < npar); blk++) {
             uint32_t y[NR][NW];
 #pragma unroll
             for (int j = 0; j < NR; j++)
@@ -104,7 +108,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 for (int w = 0; w < NW; w++)
                     y[j][w] = x[j][w];
             const TwGlobal<R> twb = {p_tw, (uint32_t)(blk * NR)};
-            reg_levels<R, L, false, SH_ALIGNED, true>(y, 0, 0, twb);
+            const int nout = npar - (blk - 1) * NR;
+            reg_levels<R, L, false, SH_ALIGNED, true>(y, 0, 0, twb, !PR || nout >= 32 ? ~0u : (1u << nout) - 1u);
 #pragma unroll
             for (int j = 0; j < NR; j++) {
                 const int t = (blk - 1) * NR + j;
@@ -188,7 +193,7 @@ struct DecTile {
         }
     }
 
-    template <int LD, class HOOK>
+    template <int LD, bool PR, class HOOK>
     __device__ __forceinline__ void run(uint32_t (*x)[Traits<R>::NW], const bool *rcv, const DevStripe &st,
                                         const Lane &ln, const uint32_t *__restrict__ bits,
                                         const uint32_t *__restrict__ rowtab, const HOOK &hook) const
@@ -251,6 +256,19 @@ struct DecTile {
             }
         }
         __syncthreads();
+        // Step 5 is pruned to the outputs step 6 uses: bit j of `used` says
+        // that consecutive group j (points 16 j .. 16 j + 15) holds an erased
+        // stored point; the other groups' forward levels are skipped.
+        constexpr uint32_t ALL = NR2 >= 32 ? ~0u : (1u << NR2) - 1u;
+        uint32_t used = ALL;
+        if (PR) {
+            const uint32_t *__restrict__ sbm = bits + bitmap_words(st.np);
+            used = 0;
+#pragma unroll
+            for (int j = 0; j < NR2; j++)
+                used |= ((sbm[(16 * j) >> 5] >> ((16 * j) & 31)) & 0xFFFFu) ? (1u << j) : 0u;
+            used = fresh(used);
+        }
         // coefficients over B_j, step 5's levels L-1..4
 #pragma unroll
         for (int u = 0; u < GPW; u++) {
@@ -260,12 +278,17 @@ struct DecTile {
                                     if (r0 + 16 * j)
                                         scale<R>(z[u][j], t);
                                 });
-            reg_levels<R, L2, false, SH_ZERO, true>(z[u], (uint32_t)r0, 4, twX);
+            reg_levels<R, L2, false, SH_ZERO, true>(z[u], (uint32_t)r0, 4, twX, used);
 #pragma unroll
             for (int j = 0; j < NR2; j++)
-                put(r0 + 16 * j, z[u][j]);
+                if ((used >> j) & 1u)
+                    put(r0 + 16 * j, z[u][j]);
         }
         __syncthreads();
+        if (PR && !((used >> g) & 1u)) {
+            hook();
+            return;
+        }
 #pragma unroll
         for (int j = 0; j < 16; j++)
             get(16 * g + j, x[j]);
@@ -279,7 +302,7 @@ struct DecTile {
     }
 };
 
-template <int R, int L, int MODE, int SH, int LD>
+template <int R, int L, int MODE, int SH, int LD, bool PR = false>
 __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4))) void k_tiled(NB_FUSED_PARAMS)
 {
     typedef TiledLds<R, L, MODE> LY;
@@ -445,7 +468,7 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
     stage_tables();
     if (MODE == M_DEC) {
         const DecTile<R, L> dt = {lds, p_tw, p_B, p_Binv, wave, lane};
-        dt.template run<LD>(x, rcv, st, ln, bits, rowtab, [] {});
+        dt.template run<LD, PR>(x, rcv, st, ln, bits, rowtab, [] {});
         return;
     }
     reg_levels<R, 4, true, (MODE == M_IFFT ? SH : SH_ZERO), false>(x, (uint32_t)(16 * g), 0, twX);
@@ -476,18 +499,26 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
     }
 
     if (MODE == M_ENC2) {
-        // the one parity block at shift 2^L, transformed in place
+        // the one parity block at shift 2^L, transformed in place; of a
+        // shortened code only the first npar rows are stored, so the stride
+        // groups compute only the blocks of rows 16 j with j < ceil(npar/16)
+        // and only the waves holding such rows run the consecutive levels
         const TwLds<R, L> twY = {p_tw, 1u << L, vY};
+        const int npar = st.n - st.k;
+        const int ng = PR ? (npar + 15) >> 4 : NR2;      // consecutive groups with stored rows
+        const uint32_t need = ng >= NR2 ? ~0u : (1u << ng) - 1u;
 #pragma unroll
         for (int u = 0; u < GPW; u++) {
             const int r0 = wave * GPW + u;
-            reg_levels<R, L2, false, SH_ALIGNED, true>(y[u], (uint32_t)r0, 4, twY);
+            reg_levels<R, L2, false, SH_ALIGNED, true>(y[u], (uint32_t)r0, 4, twY, need);
 #pragma unroll
             for (int j = 0; j < NR2; j++)
-                lds_put(my + RS * r0, 16 * j, y[u][j]);
+                if (!PR || j < ng)
+                    lds_put(my + RS * r0, 16 * j, y[u][j]);
         }
         __syncthreads();
-        const int npar = st.n - st.k;
+        if (PR && g >= ng)
+            return;
 #pragma unroll
         for (int j = 0; j < 16; j++)
             lds_get(cb, j, x[j]);
@@ -504,7 +535,10 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
     if (MODE == M_ENC) {
         const int nblocks = st.np >> L;
         const int npar = st.n - st.k;
-        for (int blk = 1; blk < nblocks; blk++) {
+        // parity blocks and rows past the stored ones are not computed
+        for (int blk = 1; blk < nblocks && (!PR || (blk - 1) * H < npar); blk++) {
+            const int ng = PR ? (npar - (blk - 1) * H + 15) >> 4 : NR2;
+            const uint32_t need = ng >= NR2 ? ~0u : (1u << ng) - 1u;
             const uint32_t lsh = (uint32_t)(blk << L);
             const TwLds<R, L> twY = {p_tw, lsh, vY + NV * (H - 1) * (blk & 1)};
             if (blk > 1)
@@ -518,25 +552,28 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
 #pragma unroll
                     for (int w = 0; w < NW; w++)
                         z[j][w] = y[u][j][w];
-                reg_levels<R, L2, false, SH_ALIGNED, true>(z, (uint32_t)r0, 4, twY);
+                reg_levels<R, L2, false, SH_ALIGNED, true>(z, (uint32_t)r0, 4, twY, need);
 #pragma unroll
                 for (int j = 0; j < NR2; j++)
-                    lds_put(my + RS * r0, 16 * j, z[j]);
+                    if (!PR || j < ng)
+                        lds_put(my + RS * r0, 16 * j, z[j]);
             }
             __syncthreads();
             // the next block's factors go to the other buffer, last read by
             // block blk - 1 before the barrier above
-            if (blk + 1 < nblocks)
+            if (blk + 1 < nblocks && (!PR || blk * H < npar))
                 stage_levels<R, L>(vY + NV * (H - 1) * ((blk + 1) & 1), p_tw, (uint32_t)((blk + 1) << L), tid, NT);
+            if (!PR || g < ng) {
 #pragma unroll
-            for (int j = 0; j < 16; j++)
-                lds_get(cb, j, x[j]);
-            reg_levels<R, 4, false, SH_ALIGNED, false>(x, (uint32_t)(16 * g), 0, twY);
+                for (int j = 0; j < 16; j++)
+                    lds_get(cb, j, x[j]);
+                reg_levels<R, 4, false, SH_ALIGNED, false>(x, (uint32_t)(16 * g), 0, twY);
 #pragma unroll
-            for (int j = 0; j < 16; j++) {
-                const int t = (blk - 1) * H + 16 * g + j;
-                if (t < npar)
-                    store_chunk<R, LD>(row_ptr(st.out, fresh(t), rb), ln.off, ln.act, ln.nsym, x[j]);
+                for (int j = 0; j < 16; j++) {
+                    const int t = (blk - 1) * H + 16 * g + j;
+                    if (t < npar)
+                        store_chunk<R, LD>(row_ptr(st.out, fresh(t), rb), ln.off, ln.act, ln.nsym, x[j]);
+                }
             }
         }
         return;
@@ -546,21 +583,33 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
 
 // ------------------------------------------------------------------ launchers
 
-template <int R, int L, int MODE, int SH, int LD>
-static hipError_t launch_one(const FusedArgs &a, const KPtrs &k, int ntiles, hipStream_t stream)
+// Modes with a pruned variant.
+constexpr bool can_prune(int mode) { return mode == M_ENC || mode == M_ENC2 || mode == M_DEC; }
+
+template <int R, int L, int MODE, int SH, int LD, bool PR>
+static hipError_t launch_pr(const FusedArgs &a, const KPtrs &k, int ntiles, hipStream_t stream)
 {
-    if (ntiles <= 0)
-        return hipSuccess;
     if (L <= 4) {
-        hipLaunchKernelGGL((k_small<R, (L <= 4 ? L : 4), MODE, SH, LD>), dim3(ntiles), dim3(64), 0, stream, a,
+        hipLaunchKernelGGL((k_small<R, (L <= 4 ? L : 4), MODE, SH, LD, PR>), dim3(ntiles), dim3(64), 0, stream, a,
                            k.tw, k.B, k.Binv, k.bits, k.rowtabs);
     } else {
         constexpr int LL = L > 4 ? L : 5;
         const size_t lds = TiledLds<R, LL, MODE>::BYTES;
-        hipLaunchKernelGGL((k_tiled<R, LL, MODE, SH, LD>), dim3(ntiles), dim3(64 << (LL - 4)), lds, stream, a, k.tw,
-                           k.B, k.Binv, k.bits, k.rowtabs);
+        hipLaunchKernelGGL((k_tiled<R, LL, MODE, SH, LD, PR>), dim3(ntiles), dim3(64 << (LL - 4)), lds, stream, a,
+                           k.tw, k.B, k.Binv, k.bits, k.rowtabs);
     }
     return hipGetLastError();
+}
+
+template <int R, int L, int MODE, int SH, int LD>
+static hipError_t launch_one(const FusedArgs &a, const KPtrs &k, int ntiles, bool pr, hipStream_t stream)
+{
+    if (ntiles <= 0)
+        return hipSuccess;
+    if constexpr (can_prune(MODE))
+        if (pr)
+            return launch_pr<R, L, MODE, SH, LD, true>(a, k, ntiles, stream);
+    return launch_pr<R, L, MODE, SH, LD, false>(a, k, ntiles, stream);
 }
 
 template <int R, int L, int MODE, int SH, int LD>
@@ -568,25 +617,34 @@ static hipError_t prep_one()
 {
     if (L > 4) {
         constexpr int LL = L > 4 ? L : 5;
-        return hipFuncSetAttribute((const void *)k_tiled<R, LL, MODE, SH, LD>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)TiledLds<R, LL, MODE>::BYTES);
+        hipError_t e = hipFuncSetAttribute((const void *)k_tiled<R, LL, MODE, SH, LD, false>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)TiledLds<R, LL, MODE>::BYTES);
+        if constexpr (can_prune(MODE)) {
+            const hipError_t f = hipFuncSetAttribute((const void *)k_tiled<R, LL, MODE, SH, LD, true>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)TiledLds<R, LL, MODE>::BYTES);
+            if (e == hipSuccess)
+                e = f;
+        }
+        return e;
     }
     return hipSuccess;
 }
 
 template <int R, int MODE, int SH, int LD>
-static hipError_t launch_L(int L, const FusedArgs &a, const KPtrs &k, int ntiles, hipStream_t s)
+static hipError_t launch_L(int L, const FusedArgs &a, const KPtrs &k, int ntiles, bool pr, hipStream_t s)
 {
     switch (L) {
-    case 0: return launch_one<R, 0, MODE, SH, LD>(a, k, ntiles, s);
-    case 1: return launch_one<R, 1, MODE, SH, LD>(a, k, ntiles, s);
-    case 2: return launch_one<R, 2, MODE, SH, LD>(a, k, ntiles, s);
-    case 3: return launch_one<R, 3, MODE, SH, LD>(a, k, ntiles, s);
-    case 4: return launch_one<R, 4, MODE, SH, LD>(a, k, ntiles, s);
-    case 5: return launch_one<R, 5, MODE, SH, LD>(a, k, ntiles, s);
-    case 6: return launch_one<R, 6, MODE, SH, LD>(a, k, ntiles, s);
-    case 7: return launch_one<R, 7, MODE, SH, LD>(a, k, ntiles, s);
-    case 8: return launch_one<R, 8, MODE, SH, LD>(a, k, ntiles, s);
+    case 0: return launch_one<R, 0, MODE, SH, LD>(a, k, ntiles, pr, s);
+    case 1: return launch_one<R, 1, MODE, SH, LD>(a, k, ntiles, pr, s);
+    case 2: return launch_one<R, 2, MODE, SH, LD>(a, k, ntiles, pr, s);
+    case 3: return launch_one<R, 3, MODE, SH, LD>(a, k, ntiles, pr, s);
+    case 4: return launch_one<R, 4, MODE, SH, LD>(a, k, ntiles, pr, s);
+    case 5: return launch_one<R, 5, MODE, SH, LD>(a, k, ntiles, pr, s);
+    case 6: return launch_one<R, 6, MODE, SH, LD>(a, k, ntiles, pr, s);
+    case 7: return launch_one<R, 7, MODE, SH, LD>(a, k, ntiles, pr, s);
+    case 8: return launch_one<R, 8, MODE, SH, LD>(a, k, ntiles, pr, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -603,21 +661,22 @@ static hipError_t prep_L()
 }
 
 template <int R, int LD>
-static hipError_t launch_ld(int mode, int sh, int L, const FusedArgs &a, const KPtrs &k, int ntiles, hipStream_t s)
+static hipError_t launch_ld(int mode, int sh, int L, const FusedArgs &a, const KPtrs &k, int ntiles, bool pr,
+                            hipStream_t s)
 {
     switch (mode) {
     case M_FFT:
-        return sh == SH_ZERO ? launch_L<R, M_FFT, SH_ZERO, LD>(L, a, k, ntiles, s)
-             : sh == SH_ALIGNED ? launch_L<R, M_FFT, SH_ALIGNED, LD>(L, a, k, ntiles, s)
-                                : launch_L<R, M_FFT, SH_GENERAL, LD>(L, a, k, ntiles, s);
+        return sh == SH_ZERO ? launch_L<R, M_FFT, SH_ZERO, LD>(L, a, k, ntiles, pr, s)
+             : sh == SH_ALIGNED ? launch_L<R, M_FFT, SH_ALIGNED, LD>(L, a, k, ntiles, pr, s)
+                                : launch_L<R, M_FFT, SH_GENERAL, LD>(L, a, k, ntiles, pr, s);
     case M_IFFT:
-        return sh == SH_ZERO ? launch_L<R, M_IFFT, SH_ZERO, LD>(L, a, k, ntiles, s)
-             : sh == SH_ALIGNED ? launch_L<R, M_IFFT, SH_ALIGNED, LD>(L, a, k, ntiles, s)
-                                : launch_L<R, M_IFFT, SH_GENERAL, LD>(L, a, k, ntiles, s);
-    case M_DERIV: return launch_L<R, M_DERIV, SH_ZERO, LD>(L, a, k, ntiles, s);
-    case M_ENC: return launch_L<R, M_ENC, SH_ZERO, LD>(L, a, k, ntiles, s);
-    case M_ENC2: return launch_L<R, M_ENC2, SH_ZERO, LD>(L, a, k, ntiles, s);
-    case M_DEC: return launch_L<R, M_DEC, SH_ZERO, LD>(L, a, k, ntiles, s);
+        return sh == SH_ZERO ? launch_L<R, M_IFFT, SH_ZERO, LD>(L, a, k, ntiles, pr, s)
+             : sh == SH_ALIGNED ? launch_L<R, M_IFFT, SH_ALIGNED, LD>(L, a, k, ntiles, pr, s)
+                                : launch_L<R, M_IFFT, SH_GENERAL, LD>(L, a, k, ntiles, pr, s);
+    case M_DERIV: return launch_L<R, M_DERIV, SH_ZERO, LD>(L, a, k, ntiles, pr, s);
+    case M_ENC: return launch_L<R, M_ENC, SH_ZERO, LD>(L, a, k, ntiles, pr, s);
+    case M_ENC2: return launch_L<R, M_ENC2, SH_ZERO, LD>(L, a, k, ntiles, pr, s);
+    case M_DEC: return launch_L<R, M_DEC, SH_ZERO, LD>(L, a, k, ntiles, pr, s);
     }
     return hipErrorInvalidValue;
 }

@@ -107,6 +107,22 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
     const uint32_t *__restrict__ rowtab = p_rowtabs + st.rowtab_off;
     auto grow = [&](int p) -> uint32_t { return gbase + ((uint32_t)p << lo); };
 
+    // Pruning: a consecutive group none of whose rows is written has nothing
+    // to compute in the last pass (decode: no erased stored point, encode:
+    // rows past the stored parity).  The test is workgroup-uniform.
+    if (KIND == W_D5) {
+        const uint32_t *__restrict__ sbm = bits + bitmap_words(st.np);
+        uint32_t any = 0;
+        for (uint32_t w = gbase >> 5; w <= (gbase + H - 1) >> 5; w++)
+            any |= sbm[w];
+        if (H < 32)
+            any = (any >> (gbase & 31)) & ((1u << (H & 31)) - 1u);
+        if (!fresh(any))
+            return;
+    }
+    if (KIND == W_E3 && (int)gbase >= ws.dst_rows)
+        return;
+
     // the inverse part runs at shift 0; the forward part at shift blk * k'
     // (encode) or 0 (decode)
     const uint32_t lf = (KIND == W_E2) ? (uint32_t)st.kp

@@ -199,14 +199,25 @@ constexpr int block_row(int k)
 // zero factor is simply multiplied (its table is all zero), which avoids a
 // data-dependent branch around the butterflies.  TW is the factor source;
 // the factor of the next block is fetched while a block is computed.
+// Pruning (forward only): bit j of `need` (wave-uniform, T <= 5) says that
+// output row j is used; a block none of whose rows is used is skipped, its
+// rows left undefined.  The default keeps every block at no cost.
 template <int R, int T, bool INV, int SH, bool CT_BASE, class TW>
-__device__ __forceinline__ void reg_levels(uint32_t (*x)[Traits<R>::NW], uint32_t base, int LO, const TW &tw)
+__device__ __forceinline__ void reg_levels(uint32_t (*x)[Traits<R>::NW], uint32_t base, int LO, const TW &tw,
+                                           uint32_t need = ~0u)
 {
     typedef typename Ops<R>::Tab Tab;
     constexpr int NW = Traits<R>::NW, NB = (1 << T) - 1;
+    static_assert(T <= 5, "a 32-bit row mask");
+    auto used = [&](int t, int blk) {
+        const uint32_t span = (2u << t) >= 32u ? ~0u : ((1u << (2u << t)) - 1u);
+        return ((need >> blk) & span) != 0u;
+    };
     auto fetch = [&](int k) -> Tab {
         const int t = block_level<T, INV>(k), blk = block_row<T, INV>(k);
         if (SH == SH_ZERO && CT_BASE && blk == 0)
+            return Tab{};
+        if (!used(t, blk))
             return Tab{};
         const int i = LO + t;
         const uint32_t c = (base & ~((2u << i) - 1u)) | ((uint32_t)blk << LO);
@@ -214,6 +225,8 @@ __device__ __forceinline__ void reg_levels(uint32_t (*x)[Traits<R>::NW], uint32_
     };
     auto work = [&](int k, const Tab &tab) {
         const int t = block_level<T, INV>(k), blk = block_row<T, INV>(k);
+        if (!used(t, blk))
+            return;
         const bool zero = SH == SH_ZERO && CT_BASE && blk == 0;
         const uint32_t m1 = SH == SH_GENERAL ? tw.plus1(t + LO) : 0u;
 #pragma unroll

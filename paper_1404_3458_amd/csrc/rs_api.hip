@@ -32,9 +32,9 @@ hipError_t poly_launch(int r, int ld, int kind, const PolyArgs &a, const uint32_
 hipError_t perm_tables(int r, const uint32_t *vals, uint32_t count, uint32_t *tabs, hipStream_t s);
 enum { PK_PAD = 0, PK_MUL = 1, PK_DEGREE = 2, PK_UP = 3, PK_DOWN = 4 };
 hipError_t fused_launch_16(int mode, int sh, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
-                           hipStream_t s);
+                           bool pr, hipStream_t s);
 hipError_t fused_launch_8(int mode, int sh, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
-                          hipStream_t s);
+                          bool pr, hipStream_t s);
 hipError_t pass_launch(int r, int ld, int T, bool inv, bool gen_l, const PassArgs &a, const KPtrs &k,
                        uint32_t nblocks, hipStream_t s);
 hipError_t dpart_launch(int r, int ld, int T, const DerivPassArgs &a, const KPtrs &k, uint32_t nblocks,
@@ -271,6 +271,7 @@ struct Plan {
     int erasures;
     bool decoding;
     bool aligned;       // rows and bases allow LD_VEC accesses
+    bool prune;         // fused kernels: some outputs of a forward transform are unused (set by validate_stripe)
     size_t mask_src;    // offset of the stripe's mask in the caller's mask array
 };
 
@@ -329,6 +330,7 @@ int validate_stripe(rs_ctx *ctx, const rs_stripe_desc &d, bool decode, const uin
     pl.L = ilog2(decode ? np : kp);
     pl.erasures = 0;
     pl.decoding = decode;
+    pl.prune = false;
     if (decode) {
         if (!mask)
             return RS_EINVAL;
@@ -338,6 +340,20 @@ int validate_stripe(rs_ctx *ctx, const rs_stripe_desc &d, bool decode, const uin
         if (e > d.n - d.k)
             return RS_ETOOMANY;
         pl.erasures = e;
+        // a group of 16 points without an erased stored row leaves its
+        // outputs of decode step 5 unused
+        if (np >= 32)
+            for (int g = 0; g < np / 16 && !pl.prune; g++) {
+                bool any = false;
+                for (int p = 16 * g; p < 16 * g + 16 && !any; p++) {
+                    const int row = p < d.k ? p : (p >= kp && p - kp < d.n - d.k ? d.k + (p - kp) : -1);
+                    any = row >= 0 && mask[row];
+                }
+                pl.prune = !any;
+            }
+    } else {
+        // parity rows that are not stored (shortened codes)
+        pl.prune = d.n - d.k < np - kp;
     }
     return RS_OK;
 }
@@ -480,11 +496,12 @@ int big_scratch(Scratch *sc, size_t need, uint8_t **p)
     return rc;
 }
 
+// pr: the kernel variant that skips unused outputs (encode and decode only).
 hipError_t fused_launch(int r, int mode, int sh, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
-                        hipStream_t s)
+                        bool pr, hipStream_t s)
 {
-    return r == 16 ? fused_launch_16(mode, sh, ld, L, a, k, ntiles, s)
-                   : fused_launch_8(mode, sh, ld, L, a, k, ntiles, s);
+    return r == 16 ? fused_launch_16(mode, sh, ld, L, a, k, ntiles, pr, s)
+                   : fused_launch_8(mode, sh, ld, L, a, k, ntiles, pr, s);
 }
 
 // An encode whose mother code has a single parity block (n' = 2 k') runs a
@@ -493,7 +510,10 @@ bool one_parity_block(const Plan &p) { return !p.decoding && p.ds.np == 2 * p.ds
 
 // Stripes of one fused launch share the transform size, the row access
 // variant and the kernel variant.
-int launch_key(const Plan &p, int ld) { return (p.L * 2 + ld) * 2 + (one_parity_block(p) ? 1 : 0); }
+int launch_key(const Plan &p, int ld)
+{
+    return ((p.L * 2 + ld) * 2 + (one_parity_block(p) ? 1 : 0)) * 2 + (p.prune ? 1 : 0);
+}
 
 // One launch unit: a column part of one stripe.
 struct Entry {
@@ -676,6 +696,7 @@ void plan_wide(const std::vector<Plan> &plans, const std::vector<int> &idx, bool
 // exec_codec on any stream, with the arena at any device address.
 struct FusedLaunch {
     int mode, ld, L;
+    bool prune;                // the pruned kernel variant
     size_t first, count;       // entries of the descriptor array
     int ntiles;
 };
@@ -783,6 +804,7 @@ int build_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, 
         fl.mode = decode ? MODE_DEC : (one_parity_block(pj) ? MODE_ENC2 : MODE_ENC);
         fl.ld = ents[j].cp.ld;
         fl.L = pj.L;
+        fl.prune = pj.prune;
         fl.first = (size_t)j;
         fl.count = (size_t)(e - j);
         fl.ntiles = tiles;
@@ -894,7 +916,7 @@ int exec_codec(rs_ctx *ctx, const CodecPlan &cp, uint8_t *dev, hipStream_t strea
         fa.stripes = d_ents + fl.first;
         fa.nstripes = (int)fl.count;
         fa.l = 0;
-        if (dev_err(ctx, fused_launch(ctx->r, fl.mode, 0, fl.ld, fl.L, fa, kp, fl.ntiles, stream)))
+        if (dev_err(ctx, fused_launch(ctx->r, fl.mode, 0, fl.ld, fl.L, fa, kp, fl.ntiles, fl.prune, stream)))
             return RS_EDEVICE;
     }
     const WideStripe *d_wide = (const WideStripe *)(dev + cp.off_wide);
@@ -986,7 +1008,7 @@ int xform_locked(rs_ctx *ctx, Scratch *sc, int mode, int h, uint32_t l, uint8_t 
             fa.nstripes = 1;
             fa.l = l;
             const int sh = gen_l ? 2 : (l == 0 ? 0 : 1);
-            if (dev_err(ctx, fused_launch(ctx->r, mode, sh, parts[i].ld, L, fa, ctx->kp, parts[i].ntiles, stream)))
+            if (dev_err(ctx, fused_launch(ctx->r, mode, sh, parts[i].ld, L, fa, ctx->kp, parts[i].ntiles, false, stream)))
                 return RS_EDEVICE;
         }
         return RS_OK;

@@ -11,7 +11,8 @@ from gpu_util import first_diff, rand_rows, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
-SHAPES16 = [(4, 2), (16, 8), (64, 48), (256, 128), (256, 224), (40, 7), (1024, 512), (4096, 2048)]
+SHAPES16 = [(4, 2), (16, 8), (64, 48), (256, 128), (256, 224), (40, 7), (1024, 512), (4096, 2048), (100, 32),
+            (96, 32), (150, 40)]
 # more than 256 points: 8-level pass pipelines (low / high level split 5+4 .. 7+6),
 # shortened mother codes, and codes with several parity blocks
 SHAPES16_WIDE = [(512, 256), (2048, 1024), (8192, 4096), (600, 500), (1000, 300), (2048, 512), (300, 200)]
