@@ -305,24 +305,42 @@ __device__ __forceinline__ void pin(const uint32_t *v)
 // Runs work(k, table_k) for k < N with table k + 1 fetched before work k, so
 // that one table fetch is in flight while a block is computed; work ends
 // with pin() on what it produced.
+// Step k of the loop is instantiated once per k (template recursion rather
+// than an unroll pragma, which the compiler may decline for long loops; a
+// loop left rolled would index the register arrays at run time and move them
+// to scratch memory).
+template <class Tab, int K, int N>
+struct PipeStep {
+    template <class F, class W>
+    __device__ static __forceinline__ void run(const F &fetch, const W &work, Tab &cur)
+    {
+        // wait for table K (fetched a block ago) before issuing table K + 1,
+        // so that the wait, which covers every outstanding scalar and LDS
+        // load, never includes the fetch that should overlap block K
+        touch(cur);
+        asm volatile("" ::: "memory");
+        Tab nxt = cur;
+        if (K + 1 < N)
+            nxt = fetch(K + 1);
+        asm volatile("" ::: "memory");
+        work(K, cur);
+        cur = nxt;
+        PipeStep<Tab, K + 1, N>::run(fetch, work, cur);
+    }
+};
+template <class Tab, int N>
+struct PipeStep<Tab, N, N> {
+    template <class F, class W>
+    __device__ static __forceinline__ void run(const F &, const W &, Tab &)
+    {
+    }
+};
+
 template <class Tab, int N, class F, class W>
 __device__ __forceinline__ void pipelined(const F &fetch, const W &work)
 {
     Tab cur = fetch(0);
-#pragma unroll
-    for (int k = 0; k < N; k++) {
-        // wait for table k (fetched a block ago) before issuing table k + 1,
-        // so that the wait, which covers every outstanding scalar and LDS
-        // load, never includes the fetch that should overlap block k
-        touch(cur);
-        asm volatile("" ::: "memory");
-        Tab nxt = cur;
-        if (k + 1 < N)
-            nxt = fetch(k + 1);
-        asm volatile("" ::: "memory");
-        work(k, cur);
-        cur = nxt;
-    }
+    PipeStep<Tab, 0, N>::run(fetch, work, cur);
 }
 
 // Load this lane's chunk (byte offset `off` in the row) into byte-sliced

@@ -48,12 +48,19 @@ __device__ __forceinline__ int find_wide(const WideStripe *__restrict__ st, int 
 __device__ __forceinline__ const uint8_t *wrow(const uint8_t *b, uint32_t t, uint64_t rb) { return b + (uint64_t)t * rb; }
 __device__ __forceinline__ uint8_t *wrow(uint8_t *b, uint32_t t, uint64_t rb) { return b + (uint64_t)t * rb; }
 
+// Groups of up to 2^WREG rows are held whole in the registers of one wave
+// (no LDS exchange, no barrier); larger ones are exchanged through an LDS
+// tile between 16-row register groups and stride-16 groups.  (One-wave
+// groups of 32 rows were measured slower than the tiled ones: they need up
+// to 190 registers, leaving two or three waves per SIMD.)
+constexpr int WREG = 4;
+
 // LDS of a pass: the group tile, then the staged V words of the factor
 // tables (a second set for W_E2's forward part) and of the per-point tables.
 template <int T, int KIND>
 struct WideLds {
     static constexpr int R = 16, H = 1 << T, NV = Ops<R>::NV, NW = Traits<R>::NW;
-    static constexpr int TILE = T > 4 ? H * 64 * NW : 0;
+    static constexpr int TILE = T > WREG ? H * 64 * NW : 0;
     static constexpr int EX = KIND == W_D3 ? 0 : H - 1;
     static constexpr int EX2 = KIND == W_E2 ? H - 1 : 0;
     static constexpr int EB = (KIND == W_D2 || KIND == W_D3) ? H : 0;
@@ -62,7 +69,7 @@ struct WideLds {
     static_assert(BYTES <= 160 * 1024, "pass tile and tables exceed the LDS of a workgroup");
 };
 
-#define NB_WIDE_THREADS(T) ((T) > 4 ? (64 << ((T) - 4)) : 64)
+#define NB_WIDE_THREADS(T) ((T) > WREG ? (64 << ((T) - 4)) : 64)
 
 template <int T, int KIND, int LD>
 __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per_eu(4))) void k_wide(
@@ -73,10 +80,11 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
     typedef WideLds<T, KIND> LY;
     typedef typename Ops<R>::Tab Tab;
     constexpr int NW = Traits<R>::NW, NV = Ops<R>::NV, H = 1 << T;
-    constexpr int TA = T < 4 ? T : 4;              // levels of the consecutive (register) phase
-    constexpr int L2 = T > 4 ? T - 4 : 0;          // levels of the stride phase
+    constexpr bool TILED = T > WREG;               // LDS exchange between two register groupings
+    constexpr int TA = TILED ? 4 : T;              // levels of the consecutive (register) phase
+    constexpr int L2 = TILED ? T - 4 : 0;          // levels of the stride phase
     constexpr int NR2 = 1 << L2;
-    constexpr int GPW = T > 4 ? 16 >> L2 : 1;
+    constexpr int GPW = TILED ? 16 >> L2 : 1;
     constexpr int NT = NB_WIDE_THREADS(T);
     constexpr int NX = 1 << TA;                    // rows of a consecutive register group
     constexpr bool INV_FIRST = KIND == W_E1 || KIND == W_E2 || KIND == W_D1 || KIND == W_D2;
@@ -161,9 +169,9 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
     uint32_t y[GPW][NR2][NW];                       // stride-phase registers (local rows r0 + 16 j)
     auto xrow = [&](int j) { return NX * g + j; };
 
-    // Rows of the data once it sits in stride registers (T > 4) or in x.
+    // Rows of the data once it sits in stride registers (TILED) or in x.
     auto store_data = [&](uint8_t *d) {
-        if constexpr (T > 4) {
+        if constexpr (TILED) {
 #pragma unroll
             for (int u = 0; u < GPW; u++)
 #pragma unroll
@@ -179,7 +187,7 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
 
     // ------------------------------------------------ input
     bool rcv[NX];
-    if (INV_FIRST || KIND == W_D3 || T <= 4) {
+    if (INV_FIRST || KIND == W_D3 || !TILED) {
 #pragma unroll
         for (int j = 0; j < NX; j++) {
             const uint32_t p = grow(xrow(j));
@@ -189,7 +197,7 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
                 load_chunk<R, LD>(wrow(ws.src, p, rb), ln.off, ln.act && (int)p < ws.src_rows, ln.nsym, x[j]);
         }
     } else {
-        if constexpr (T > 4) {
+        if constexpr (TILED) {
 #pragma unroll
             for (int u = 0; u < GPW; u++)
 #pragma unroll
@@ -201,9 +209,39 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
     }
     stage_tables();
 
-    if (KIND == W_D3) {
+    if (KIND == W_D3 && !TILED) {
         // z_p = partial sums of W_D2 + sum over clear local bits l of p of
-        // y_{p + 2^l}; the coefficient is z_p / B_p (Sec. 4.2).
+        // y_{p + 2^l}; the coefficient is z_p / B_p (Sec. 4.2).  Rows in
+        // chunks of 16, so that the partial sums need no second copy of the
+        // group in registers.
+#pragma unroll
+        for (int c = 0; c < NX; c += 16) {
+            constexpr int NC = NX < 16 ? NX : 16;
+            uint32_t z[NC][NW];
+#pragma unroll
+            for (int j = 0; j < NC; j++)
+                load_chunk<R, LD>(wrow(ws.src2, grow(c + j), rb), ln.off, ln.act, ln.nsym, z[j]);
+#pragma unroll
+            for (int j = 0; j < NC; j++)
+#pragma unroll
+                for (int lv = 0; lv < TA; lv++)
+                    if (!(((c + j) >> lv) & 1))
+#pragma unroll
+                        for (int w = 0; w < NW; w++)
+                            z[j][w] ^= x[c + j + (1 << lv)][w];
+            pipelined<Tab, NC>([&](int j) { return row_tab<R>(p_Binv, vB, c + j, grow(c + j)); },
+                               [&](int j, const Tab &t) {
+                                   const uint32_t p = grow(c + j);
+                                   if (p)
+                                       scale<R>(z[j], t);
+                                   store_chunk<R, LD>(wrow(ws.dst, fresh(p), rb), ln.off, ln.act, ln.nsym, z[j]);
+                               });
+        }
+        return;
+    }
+    if (KIND == W_D3) {
+        // as above, for a tiled group: the partners 2^l away with l < 4 are
+        // in this wave's registers, the others in the LDS tile
         uint32_t z[NX][NW];
 #pragma unroll
         for (int j = 0; j < NX; j++)
@@ -216,7 +254,7 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
 #pragma unroll
                     for (int w = 0; w < NW; w++)
                         z[j][w] ^= x[j + (1 << lv)][w];
-        if constexpr (T > 4) {
+        if constexpr (TILED) {
 #pragma unroll
             for (int j = 0; j < 16; j++)
                 lds_put(cb, j, x[j]);
@@ -250,7 +288,7 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
             pipelined<Tab, NX>([&](int j) { return row_tab<R>(rowtab, vRT, xrow(j), grow(xrow(j))); },
                                [&](int j, const Tab &t) { dec_weigh<R>(x[j], rcv[j], t); });
         reg_levels<R, TA, true, SH_ZERO, false>(x, (uint32_t)(NX * g), 0, twI);
-        if constexpr (T > 4) {
+        if constexpr (TILED) {
 #pragma unroll
             for (int j = 0; j < 16; j++)
                 lds_put(cb, j, x[j]);
@@ -275,7 +313,7 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
             // over the clear local bits (the transform's high bits).  Each
             // wave rewrites only the tile rows it read itself, so no barrier
             // is needed before the exchange.
-            if constexpr (T > 4) {
+            if constexpr (TILED) {
 #pragma unroll
                 for (int u = 0; u < GPW; u++) {
                     const int r0 = wave * GPW + u;
@@ -343,7 +381,7 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
     }
 
     if (FWD) {
-        if constexpr (T > 4) {
+        if constexpr (TILED) {
 #pragma unroll
             for (int u = 0; u < GPW; u++) {
                 const int r0 = wave * GPW + u;

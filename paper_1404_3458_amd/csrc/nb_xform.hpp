@@ -199,19 +199,19 @@ constexpr int block_row(int k)
 // zero factor is simply multiplied (its table is all zero), which avoids a
 // data-dependent branch around the butterflies.  TW is the factor source;
 // the factor of the next block is fetched while a block is computed.
-// Pruning (forward only): bit j of `need` (wave-uniform, T <= 5) says that
-// output row j is used; a block none of whose rows is used is skipped, its
-// rows left undefined.  The default keeps every block at no cost.
+// Pruning (forward only): bit j of `need` (wave-uniform) says that output
+// row j is used; a block none of whose rows is used is skipped, its rows
+// left undefined.  The default keeps every block at no cost.
 template <int R, int T, bool INV, int SH, bool CT_BASE, class TW>
 __device__ __forceinline__ void reg_levels(uint32_t (*x)[Traits<R>::NW], uint32_t base, int LO, const TW &tw,
-                                           uint32_t need = ~0u)
+                                           uint64_t need = ~0ull)
 {
     typedef typename Ops<R>::Tab Tab;
     constexpr int NW = Traits<R>::NW, NB = (1 << T) - 1;
-    static_assert(T <= 5, "a 32-bit row mask");
+    static_assert(T <= 6, "a 64-bit row mask");
     auto used = [&](int t, int blk) {
-        const uint32_t span = (2u << t) >= 32u ? ~0u : ((1u << (2u << t)) - 1u);
-        return ((need >> blk) & span) != 0u;
+        const uint64_t span = (2u << t) >= 64u ? ~0ull : ((1ull << (2u << t)) - 1ull);
+        return ((need >> blk) & span) != 0ull;
     };
     auto fetch = [&](int k) -> Tab {
         const int t = block_level<T, INV>(k), blk = block_row<T, INV>(k);
