@@ -169,11 +169,12 @@ def cpu_baseline(cfg, sample_stripes, sample_cols, threads):
                       "%.2f s wall" % (sample_stripes, cols, nbytes, dt)}
 
 
-def schedule_for(args, codec, shapes):
-    """Pass-pipeline schedules for a mixed workload, set in `codec`: a saved
-    table (--schedule), the defaults (--no-tune), or the autotuner run on
-    seeded batches of the workload's (n, k) classes with row lengths at the
-    deciles of its shard lengths (setup, outside every timed region)."""
+def schedule_for(args, codec, shapes, target_bytes=256 << 20):
+    """Pass-pipeline schedules for a workload, set in `codec`: a saved table
+    (--schedule), the defaults (--no-tune), or the autotuner run on seeded
+    batches of the workload's (n, k) classes with row lengths at the deciles
+    of its shard lengths and about target_bytes of codeword per class (setup,
+    outside every timed region)."""
     from paper_1404_3458_amd import tune
 
     t0 = time.perf_counter()
@@ -184,7 +185,7 @@ def schedule_for(args, codec, shapes):
     else:
         sbs = sorted(sb for n, k, sb, e in shapes)
         rbs = tuple(sorted({sbs[int(q * (len(sbs) - 1))] for q in (0.1, 0.3, 0.5, 0.7, 0.9)}))
-        tab = tune.tune(codec, sorted({(n, k) for n, k, sb, e in shapes}), row_bytes=rbs)
+        tab = tune.tune(codec, sorted({(n, k) for n, k, sb, e in shapes}), row_bytes=rbs, target_bytes=target_bytes)
         src = "autotuned"
     return {"source": src, "setup_s": round(time.perf_counter() - t0, 2), "T1": tune.summary(tab),
             "candidate_ms": {"%s:%d" % (e["op"], e["N"]): e.get("ms") for e in tab["entries"]}}
@@ -666,6 +667,10 @@ def main():
     dev = torch.device("cuda", 0)
     codec = rs.Codec(r)
     stream = torch.cuda.current_stream()
+    # codes over more than 256 points run pass pipelines: tune their splits
+    kp_ = pow2ceil(k)
+    sched = schedule_for(args, codec, [(n, k, S, e)], target_bytes=ns * n * S) \
+        if r == 16 and pow2ceil(kp_ + n - k) > 256 else None
 
     # Codeword buffer: stripe s rows 0..k-1 are its message, k..n-1 its parity.
     cw = torch.empty((ns, n, S), dtype=torch.uint8, device=dev)
@@ -764,6 +769,8 @@ def main():
         "host_call_ms_p50": [round(float(np.median(host_ms[:, 0])), 3), round(float(np.median(host_ms[:, 1])), 3)],
         "msg_over_hbm_peak": round(value / HBM_PEAK_GBS, 4),
     }
+    if sched is not None:
+        extra["schedule"] = sched
 
     if not args.no_per_stripe and ns > 1:
         # the same work as per-stripe launches (one call per stripe and direction)

@@ -196,23 +196,29 @@ int rs_server_pending(rs_server *srv);
 void rs_server_free(rs_server *srv);
 
 /* Schedules of the pass pipelines used by codes whose transforms exceed
- * 256 points (GF(2^16) only).  Such a transform over 2^N points runs as
- * passes over groups of 2^T1 consecutive rows, which apply its low T1
- * levels, and passes over groups of 2^(N - T1) rows at stride 2^T1, which
- * apply the others: level i only pairs rows j and j + 2^i (Sec. 3.2), so a
- * group holding every row that differs in a range of index bits can apply
- * those levels alone.  Both parts need 4 to 8 levels; the default is
- * T1 = ceil(N / 2).  op selects the encoder (N = lg k', the size of its
- * transforms) or the decoder (N = lg n').  T1 = 0 restores the default.  A
- * schedule changes only the speed, never an output; calls and plans built
- * after the change use it.  rs_init applies the environment variable
- * RS_NB_SCHEDULE, a comma-separated list of "enc:N:T1" and "dec:N:T1"
- * entries, and returns RS_EINVAL when it is malformed.
+ * 256 points (GF(2^16) only).  Such a transform over 2^N points is split
+ * into 2 to 4 parts of consecutive levels, each applied by passes over
+ * groups of rows that differ only in that part's index bits: level i only
+ * pairs rows j and j + 2^i (Sec. 3.2), so such a group can apply those
+ * levels alone.  parts[0] is the low part (groups of consecutive rows); each
+ * part has 4 to 8 levels and they sum to N.  The default is two parts,
+ * ceil(N / 2) low.  op selects the encoder (N = lg k', the size of its
+ * transforms) or the decoder (N = lg n').  A schedule changes only the
+ * speed, never an output; calls and plans built after the change use it.
+ * rs_schedule_set is the two-part form (T1 low levels; T1 = 0 restores the
+ * default); rs_schedule_set_parts takes the list (nparts = 0 restores the
+ * default).  rs_init applies the environment variable RS_NB_SCHEDULE, a
+ * comma-separated list of "enc:N:P" and "dec:N:P" entries where P is the low
+ * part's count or the counts joined by '/', low part first, and returns
+ * RS_EINVAL when it is malformed.
  * Errors: RS_ESHAPE for r = 8 or N outside 9..16; RS_EINVAL for a bad op or
- * T1. */
+ * split. */
 int rs_schedule_set(rs_ctx *ctx, int op, int N, int T1);
-/* The T1 in effect for (op, N) (the default when none was set). */
+int rs_schedule_set_parts(rs_ctx *ctx, int op, int N, const int *parts, int nparts);
+/* The schedule in effect for (op, N): the low part's count, or the parts
+ * (parts: room for 4). */
 int rs_schedule_get(rs_ctx *ctx, int op, int N, int *T1);
+int rs_schedule_get_parts(rs_ctx *ctx, int op, int N, int *parts, int *nparts);
 
 /* Wait for all work of this context on `stream`; reports deferred device
  * errors. */

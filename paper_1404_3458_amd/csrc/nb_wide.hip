@@ -23,14 +23,20 @@
 //     W_D1   step 2 (received rows times Pi) and low inverse levels
 //     W_D2   high inverse levels, d^d = B (.) coefficients (Sec. 4.2), and the
 //            derivative's partial sums over the high bits
-//     W_D3   the partial sums over the low bits, plus those of W_D2, over B_j
+//     W_D3   the partial sums over the low bits, plus those of the other
+//            passes, over B_j
+//     W_DPM  (pipelines of three or four parts) the partial sums over the bits
+//            of a middle part, added to those of W_D2
+// Pipelines of more than two parts run the middle parts' inverse levels as
+// W_E1 passes and their forward levels as W_E2F (encode) or W_D4 (decode)
+// passes, in place on the same buffers.
 //     W_D4   high forward levels
 //     W_D5   low forward levels and step 6 (erased rows over Pi')
 #include "nb_xform.hpp"
 
 namespace nb {
 
-enum WideKind { W_E1 = 0, W_E2 = 1, W_E2F = 2, W_E3 = 3, W_D1 = 4, W_D2 = 5, W_D3 = 6, W_D4 = 7, W_D5 = 8 };
+enum WideKind { W_E1 = 0, W_E2 = 1, W_E2F = 2, W_E3 = 3, W_D1 = 4, W_D2 = 5, W_D3 = 6, W_D4 = 7, W_D5 = 8, W_DPM = 9 };
 
 __device__ __forceinline__ int find_wide(const WideStripe *__restrict__ st, int n, int tile)
 {
@@ -61,7 +67,7 @@ template <int T, int KIND>
 struct WideLds {
     static constexpr int R = 16, H = 1 << T, NV = Ops<R>::NV, NW = Traits<R>::NW;
     static constexpr int TILE = T > WREG ? H * 64 * NW : 0;
-    static constexpr int EX = KIND == W_D3 ? 0 : H - 1;
+    static constexpr int EX = (KIND == W_D3 || KIND == W_DPM) ? 0 : H - 1;
     static constexpr int EX2 = KIND == W_E2 ? H - 1 : 0;
     static constexpr int EB = (KIND == W_D2 || KIND == W_D3) ? H : 0;
     static constexpr int ERT = (KIND == W_D1 || KIND == W_D5) ? H : 0;
@@ -88,6 +94,7 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
     constexpr int NT = NB_WIDE_THREADS(T);
     constexpr int NX = 1 << TA;                    // rows of a consecutive register group
     constexpr bool INV_FIRST = KIND == W_E1 || KIND == W_E2 || KIND == W_D1 || KIND == W_D2;
+    constexpr bool PSUM = KIND == W_D3 || KIND == W_DPM;     // partial sums of the derivative
     constexpr bool FWD = KIND == W_E2 || KIND == W_E2F || KIND == W_E3 || KIND == W_D4 || KIND == W_D5;
     constexpr int SHF = (KIND == W_D4 || KIND == W_D5) ? SH_ZERO : SH_ALIGNED;   // forward-part shift
 
@@ -187,7 +194,7 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
 
     // ------------------------------------------------ input
     bool rcv[NX];
-    if (INV_FIRST || KIND == W_D3 || !TILED) {
+    if (INV_FIRST || PSUM || !TILED) {
 #pragma unroll
         for (int j = 0; j < NX; j++) {
             const uint32_t p = grow(xrow(j));
@@ -209,7 +216,7 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
     }
     stage_tables();
 
-    if (KIND == W_D3 && !TILED) {
+    if (PSUM && !TILED) {
         // z_p = partial sums of W_D2 + sum over clear local bits l of p of
         // y_{p + 2^l}; the coefficient is z_p / B_p (Sec. 4.2).  Rows in
         // chunks of 16, so that the partial sums need no second copy of the
@@ -229,17 +236,23 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
 #pragma unroll
                         for (int w = 0; w < NW; w++)
                             z[j][w] ^= x[c + j + (1 << lv)][w];
-            pipelined<Tab, NC>([&](int j) { return row_tab<R>(p_Binv, vB, c + j, grow(c + j)); },
-                               [&](int j, const Tab &t) {
-                                   const uint32_t p = grow(c + j);
-                                   if (p)
-                                       scale<R>(z[j], t);
-                                   store_chunk<R, LD>(wrow(ws.dst, fresh(p), rb), ln.off, ln.act, ln.nsym, z[j]);
-                               });
+            if (KIND == W_DPM) {
+#pragma unroll
+                for (int j = 0; j < NC; j++)
+                    store_chunk<R, LD>(wrow(ws.dst, fresh(grow(c + j)), rb), ln.off, ln.act, ln.nsym, z[j]);
+            } else {
+                pipelined<Tab, NC>([&](int j) { return row_tab<R>(p_Binv, vB, c + j, grow(c + j)); },
+                                   [&](int j, const Tab &t) {
+                                       const uint32_t p = grow(c + j);
+                                       if (p)
+                                           scale<R>(z[j], t);
+                                       store_chunk<R, LD>(wrow(ws.dst, fresh(p), rb), ln.off, ln.act, ln.nsym, z[j]);
+                                   });
+            }
         }
         return;
     }
-    if (KIND == W_D3) {
+    if (PSUM) {
         // as above, for a tiled group: the partners 2^l away with l < 4 are
         // in this wave's registers, the others in the LDS tile
         uint32_t z[NX][NW];
@@ -273,13 +286,19 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
                 }
             }
         }
-        pipelined<Tab, NX>([&](int j) { return row_tab<R>(p_Binv, vB, xrow(j), grow(xrow(j))); },
-                           [&](int j, const Tab &t) {
-                               const uint32_t p = grow(xrow(j));
-                               if (p)
-                                   scale<R>(z[j], t);
-                               store_chunk<R, LD>(wrow(ws.dst, fresh(p), rb), ln.off, ln.act, ln.nsym, z[j]);
-                           });
+        if (KIND == W_DPM) {
+#pragma unroll
+            for (int j = 0; j < NX; j++)
+                store_chunk<R, LD>(wrow(ws.dst, fresh(grow(xrow(j))), rb), ln.off, ln.act, ln.nsym, z[j]);
+        } else {
+            pipelined<Tab, NX>([&](int j) { return row_tab<R>(p_Binv, vB, xrow(j), grow(xrow(j))); },
+                               [&](int j, const Tab &t) {
+                                   const uint32_t p = grow(xrow(j));
+                                   if (p)
+                                       scale<R>(z[j], t);
+                                   store_chunk<R, LD>(wrow(ws.dst, fresh(p), rb), ln.off, ln.act, ln.nsym, z[j]);
+                               });
+        }
         return;
     }
 
@@ -464,6 +483,7 @@ static hipError_t wide_launch_ld(int kind, int T, const WideArgs &a, const KPtrs
     case W_D1: return wide_launch_T<W_D1, LD>(T, a, k, ntiles, s);
     case W_D2: return wide_launch_T<W_D2, LD>(T, a, k, ntiles, s);
     case W_D3: return wide_launch_T<W_D3, LD>(T, a, k, ntiles, s);
+    case W_DPM: return wide_launch_T<W_DPM, LD>(T, a, k, ntiles, s);
     case W_D4: return wide_launch_T<W_D4, LD>(T, a, k, ntiles, s);
     case W_D5: return wide_launch_T<W_D5, LD>(T, a, k, ntiles, s);
     }
@@ -485,6 +505,7 @@ hipError_t wide_prepare()
     if ((f = wide_prep_T<K, LD_VEC>()) != hipSuccess) e = f;                                                       \
     if ((f = wide_prep_T<K, LD_SYM>()) != hipSuccess) e = f;
     NB_WPREP(W_E1) NB_WPREP(W_E2) NB_WPREP(W_E2F) NB_WPREP(W_E3) NB_WPREP(W_D1) NB_WPREP(W_D2) NB_WPREP(W_D3)
+    NB_WPREP(W_DPM)
     NB_WPREP(W_D4) NB_WPREP(W_D5)
 #undef NB_WPREP
     return e;

@@ -52,7 +52,7 @@ enum { MODE_FFT = 0, MODE_IFFT = 1, MODE_DERIV = 2, MODE_ENC = 3, MODE_DEC = 4, 
 constexpr int FUSED_MAX_L = 8;      // fused single-launch kernels cover h <= 256
 constexpr int LOC_ONE_WG_MAX = 4096; // larger mother codes use the multi-workgroup locator
 // pass kinds of nb_wide.hip
-enum { W_E1 = 0, W_E2 = 1, W_E2F = 2, W_E3 = 3, W_D1 = 4, W_D2 = 5, W_D3 = 6, W_D4 = 7, W_D5 = 8 };
+enum { W_E1 = 0, W_E2 = 1, W_E2F = 2, W_E3 = 3, W_D1 = 4, W_D2 = 5, W_D3 = 6, W_D4 = 7, W_D5 = 8, W_DPM = 9 };
 // scratch of the 8-level pass pipelines: stripes are processed in chunks
 // whose scratch fits this budget (a stripe larger than it runs alone)
 constexpr size_t WIDE_SCRATCH_BUDGET = (size_t)2 << 30;
@@ -115,8 +115,9 @@ struct rs_ctx {
     std::mutex mu;
     std::vector<Scratch *> scratch;
     int sticky = RS_OK;
-    // schedules of the pass pipelines: T1 per (op, N); 0 = ceil(N / 2)
-    std::atomic<int> sched_T1[2][17] = {};
+    // schedules of the pass pipelines per (op, N): the level counts of the
+    // parts, low part first, one per 4-bit field; 0 = two parts, ceil(N / 2) low
+    std::atomic<int> sched[2][17] = {};
 };
 
 namespace {
@@ -552,12 +553,14 @@ size_t wide_scratch_rows(const Plan &p)
     return 2 * (size_t)d.kp;
 }
 
+void unpack_parts(int v, int N, int *parts, int *nparts);
+
 // Split the wide stripes (plan indices, all with L > FUSED_MAX_L) into
 // chunks, lay out their scratch from `scratch_base` (null while sizing) and
 // list the launches: per chunk and transform size, every pass kind in order,
 // one launch per row-access variant.
 void plan_wide(const std::vector<Plan> &plans, const std::vector<int> &idx, bool decode, uint8_t *scratch_base,
-               const int *sched_T1, WidePlan &wp)
+               const int *sched, WidePlan &wp)
 {
     wp.descs.clear();
     wp.launches.clear();
@@ -598,21 +601,41 @@ void plan_wide(const std::vector<Plan> &plans, const std::vector<int> &idx, bool
                 Ns.push_back(plans[idx[q]].L);
         std::sort(Ns.begin(), Ns.end());
         for (int N : Ns) {
-            const int T1 = sched_T1[N] ? sched_T1[N] : (N + 1) / 2, T2 = N - T1;
+            int parts[4], m = 0;
+            unpack_parts(sched[N], N, parts, &m);
+            int los[4] = {0, 0, 0, 0};
+            for (int i = 1; i < m; i++)
+                los[i] = los[i - 1] + parts[i - 1];
+            const int T1 = parts[0], TH = parts[m - 1], LH = los[m - 1];
             int max_blocks = 2;
             for (size_t q = ch.first; q < ch.second; q++)
                 if (plans[idx[q]].L == N)
                     max_blocks = std::max(max_blocks, plans[idx[q]].ds.np / plans[idx[q]].ds.kp);
-            // (kind, lo, T, blk) sequence
-            struct Step { int kind, lo, T, blk; };
+            // (kind, lo, T, blk, middle part) sequence: the low part, the
+            // middle parts (pipelines of three or four parts), the high part
+            struct Step { int kind, lo, T, blk; bool mid; };
             std::vector<Step> steps;
             if (decode) {
-                steps = {{W_D1, 0, T1, 0}, {W_D2, T1, T2, 0}, {W_D3, 0, T1, 0}, {W_D4, T1, T2, 0}, {W_D5, 0, T1, 0}};
+                steps.push_back({W_D1, 0, T1, 0, false});
+                for (int i = 1; i + 1 < m; i++)
+                    steps.push_back({W_E1, los[i], parts[i], 0, true});
+                steps.push_back({W_D2, LH, TH, 0, false});
+                for (int i = m - 2; i >= 1; i--)
+                    steps.push_back({W_DPM, los[i], parts[i], 0, true});
+                steps.push_back({W_D3, 0, T1, 0, false});
+                steps.push_back({W_D4, LH, TH, 0, false});
+                for (int i = m - 2; i >= 1; i--)
+                    steps.push_back({W_D4, los[i], parts[i], 0, true});
+                steps.push_back({W_D5, 0, T1, 0, false});
             } else {
-                steps = {{W_E1, 0, T1, 0}, {W_E2, T1, T2, 1}, {W_E3, 0, T1, 1}};
-                for (int b = 2; b < max_blocks; b++) {
-                    steps.push_back({W_E2F, T1, T2, b});
-                    steps.push_back({W_E3, 0, T1, b});
+                steps.push_back({W_E1, 0, T1, 0, false});
+                for (int i = 1; i + 1 < m; i++)
+                    steps.push_back({W_E1, los[i], parts[i], 0, true});
+                for (int b = 1; b < max_blocks; b++) {
+                    steps.push_back({b == 1 ? W_E2 : W_E2F, LH, TH, b, false});
+                    for (int i = m - 2; i >= 1; i--)
+                        steps.push_back({W_E2F, los[i], parts[i], b, true});
+                    steps.push_back({W_E3, 0, T1, b, false});
                 }
             }
             for (const Step &stp : steps) {
@@ -650,13 +673,25 @@ void plan_wide(const std::vector<Plan> &plans, const std::vector<int> &idx, bool
                         w.src_rows = decode ? d.np : d.kp;
                         w.dst_rows = decode ? d.np : d.kp;
                         switch (stp.kind) {
-                        case W_E1: w.src = d.in; w.src_rows = d.k; w.dst = coef; break;
+                        case W_E1:
+                            if (decode) {                       // a middle part's inverse levels
+                                w.src = A;
+                                w.dst = A;
+                            } else {
+                                w.src = stp.mid ? coef : d.in;
+                                w.src_rows = stp.mid ? d.kp : d.k;
+                                w.dst = coef;
+                            }
+                            break;
                         case W_E2:
                             w.src = coef;
                             w.dst2 = nblocks > 2 ? coef : nullptr;
                             w.dst = block_buf(1);
                             break;
-                        case W_E2F: w.src = coef; w.dst = block_buf(stp.blk); break;
+                        case W_E2F:
+                            w.src = stp.mid ? block_buf(stp.blk) : coef;
+                            w.dst = block_buf(stp.blk);
+                            break;
                         case W_E3:
                             w.src = block_buf(stp.blk);
                             w.dst = d.out + (size_t)(stp.blk - 1) * d.kp * rb;
@@ -665,6 +700,7 @@ void plan_wide(const std::vector<Plan> &plans, const std::vector<int> &idx, bool
                         case W_D1: w.dst = A; break;
                         case W_D2: w.src = A; w.dst = A; w.dst2 = Z; break;
                         case W_D3: w.src = A; w.src2 = Z; w.dst = A; break;
+                        case W_DPM: w.src = A; w.src2 = Z; w.dst = Z; break;
                         case W_D4: w.src = A; w.dst = A; break;
                         case W_D5: w.src = A; break;
                         }
@@ -835,10 +871,10 @@ int build_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, 
         if (plans[act[q]].L > FUSED_MAX_L)
             widx.push_back(act[q]);
     if (!widx.empty()) {
-        int t1[17];
+        int sc[17];
         for (int N = 0; N < 17; N++)
-            t1[N] = ctx->sched_T1[decode ? 1 : 0][N].load(std::memory_order_relaxed);
-        plan_wide(plans, widx, decode, scratch, t1, cp.wp);
+            sc[N] = ctx->sched[decode ? 1 : 0][N].load(std::memory_order_relaxed);
+        plan_wide(plans, widx, decode, scratch, sc, cp.wp);
         if (scratch_need)
             *scratch_need = cp.wp.scratch;
     } else if (scratch_need) {
@@ -1160,16 +1196,50 @@ void what_coefficients(int r, const uint32_t *basis, std::vector<uint32_t> &out)
     }
 }
 
-// A pass-pipeline schedule is valid for transforms over 2^N > 256 points
-// (GF(2^16)) when both pass kinds get 4..8 levels; T1 = 0 is the default.
-bool schedule_ok(int r, int op, int N, int T1)
+// A pass-pipeline schedule: the level counts of 2..4 parts (low part first),
+// each 4..8, summing to N, for transforms over 2^N > 256 points (GF(2^16)).
+bool schedule_ok(int r, int op, int N, const int *parts, int nparts)
 {
     if (r != 16 || (op != RS_OP_ENCODE && op != RS_OP_DECODE) || N <= FUSED_MAX_L || N > 16)
         return false;
-    return T1 == 0 || (T1 >= 4 && T1 <= 8 && N - T1 >= 4 && N - T1 <= 8);
+    if (nparts < 2 || nparts > 4 || !parts)
+        return false;
+    int sum = 0;
+    for (int i = 0; i < nparts; i++) {
+        if (parts[i] < 4 || parts[i] > 8)
+            return false;
+        sum += parts[i];
+    }
+    return sum == N;
 }
 
-// RS_NB_SCHEDULE: comma-separated "enc:N:T1" / "dec:N:T1" entries.
+int pack_parts(const int *parts, int nparts)
+{
+    int v = 0;
+    for (int i = nparts - 1; i >= 0; i--)
+        v = (v << 4) | parts[i];
+    return v;
+}
+
+// The parts of a packed schedule; 0 is the default two-part split.
+void unpack_parts(int v, int N, int *parts, int *nparts)
+{
+    if (!v) {
+        parts[0] = (N + 1) / 2;
+        parts[1] = N - parts[0];
+        *nparts = 2;
+        return;
+    }
+    int m = 0;
+    while (v && m < 4) {
+        parts[m++] = v & 15;
+        v >>= 4;
+    }
+    *nparts = m;
+}
+
+// RS_NB_SCHEDULE: comma-separated "enc:N:P" / "dec:N:P" entries, P the low
+// part's level count or the parts' counts joined by '/', low part first.
 bool apply_schedule_env(rs_ctx *ctx)
 {
     const char *env = std::getenv("RS_NB_SCHEDULE");
@@ -1187,16 +1257,31 @@ bool apply_schedule_env(rs_ctx *ctx)
         p += 4;
         char *end;
         const long N = std::strtol(p, &end, 10);
-        if (end == p || *end != ':')
+        if (end == p || *end != ':' || N < 0 || N > 16)
             return false;
         p = end + 1;
-        const long T1 = std::strtol(p, &end, 10);
-        if (end == p || (*end && *end != ','))
+        int parts[4], m = 0;
+        while (true) {
+            const long v = std::strtol(p, &end, 10);
+            if (end == p || m == 4)
+                return false;
+            parts[m++] = (int)v;
+            p = end;
+            if (*p != '/')
+                break;
+            p++;
+        }
+        if (*p && *p != ',')
             return false;
-        p = *end ? end + 1 : end;
-        if (N < 0 || N > 16 || !schedule_ok(ctx->r, op, (int)N, (int)T1))
+        if (*p)
+            p++;
+        if (m == 1) {                                   // the low part only
+            parts[1] = (int)N - parts[0];
+            m = 2;
+        }
+        if (!schedule_ok(ctx->r, op, (int)N, parts, m))
             return false;
-        ctx->sched_T1[op][N].store((int)T1);
+        ctx->sched[op][N].store(pack_parts(parts, m));
     }
     return true;
 }
@@ -1296,27 +1381,51 @@ __attribute__((visibility("default"))) int rs_init(int r, const uint32_t *basis,
     return RS_OK;
 }
 
-__attribute__((visibility("default"))) int rs_schedule_set(rs_ctx *ctx, int op, int N, int T1)
+__attribute__((visibility("default"))) int rs_schedule_set_parts(rs_ctx *ctx, int op, int N, const int *parts,
+                                                                 int nparts)
 {
     if (!ctx)
         return RS_EINVAL;
     if (ctx->r != 16 || N <= FUSED_MAX_L || N > 16)
         return RS_ESHAPE;
-    if (!schedule_ok(ctx->r, op, N, T1))
+    if (op != RS_OP_ENCODE && op != RS_OP_DECODE)
         return RS_EINVAL;
-    ctx->sched_T1[op][N].store(T1);
+    if (nparts == 0) {
+        ctx->sched[op][N].store(0);
+        return RS_OK;
+    }
+    if (!schedule_ok(ctx->r, op, N, parts, nparts))
+        return RS_EINVAL;
+    ctx->sched[op][N].store(pack_parts(parts, nparts));
+    return RS_OK;
+}
+
+__attribute__((visibility("default"))) int rs_schedule_set(rs_ctx *ctx, int op, int N, int T1)
+{
+    const int parts[2] = {T1, N - T1};
+    return rs_schedule_set_parts(ctx, op, N, parts, T1 ? 2 : 0);
+}
+
+__attribute__((visibility("default"))) int rs_schedule_get_parts(rs_ctx *ctx, int op, int N, int *parts,
+                                                                 int *nparts)
+{
+    if (!ctx || !parts || !nparts || (op != RS_OP_ENCODE && op != RS_OP_DECODE))
+        return RS_EINVAL;
+    if (ctx->r != 16 || N <= FUSED_MAX_L || N > 16)
+        return RS_ESHAPE;
+    unpack_parts(ctx->sched[op][N].load(), N, parts, nparts);
     return RS_OK;
 }
 
 __attribute__((visibility("default"))) int rs_schedule_get(rs_ctx *ctx, int op, int N, int *T1)
 {
-    if (!ctx || !T1 || (op != RS_OP_ENCODE && op != RS_OP_DECODE))
+    if (!T1)
         return RS_EINVAL;
-    if (ctx->r != 16 || N <= FUSED_MAX_L || N > 16)
-        return RS_ESHAPE;
-    const int t = ctx->sched_T1[op][N].load();
-    *T1 = t ? t : (N + 1) / 2;
-    return RS_OK;
+    int parts[4], m = 0;
+    const int rc = rs_schedule_get_parts(ctx, op, N, parts, &m);
+    if (!rc)
+        *T1 = parts[0];
+    return rc;
 }
 
 __attribute__((visibility("default"))) void rs_free(rs_ctx *ctx)

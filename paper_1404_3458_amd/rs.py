@@ -164,6 +164,8 @@ def load():
             "rs_server_free": (None, [vp]),
             "rs_schedule_set": (i32, [vp, i32, i32, i32]),
             "rs_schedule_get": (i32, [vp, i32, i32, ctypes.POINTER(i32)]),
+            "rs_schedule_set_parts": (i32, [vp, i32, i32, vp, i32]),
+            "rs_schedule_get_parts": (i32, [vp, i32, i32, vp, ctypes.POINTER(i32)]),
             "rs_sync": (i32, [vp, vp]),
             "rs_get_table": (i32, [vp, i32, vp, sz]),
             "rs_strerror": (ctypes.c_char_p, [i32]),
@@ -370,15 +372,25 @@ class Codec:
                       "nb_from_monomial")
 
     # ------------------------------------------------------------ schedules
-    def set_schedule(self, op, N, T1):
-        """Low-level count T1 of the pass pipelines for transforms over 2^N
-        points (op RS_OP_ENCODE: N = lg k'; RS_OP_DECODE: N = lg n'); 0 = default."""
-        return _check(load().rs_schedule_set(self._ctx, op, N, T1), "rs_schedule_set")
+    def set_schedule(self, op, N, split):
+        """Pass-pipeline schedule for transforms over 2^N points (op
+        RS_OP_ENCODE: N = lg k'; RS_OP_DECODE: N = lg n'): an int is the low
+        part's level count (0 = default), a sequence the parts' counts, low first."""
+        if isinstance(split, int):
+            return _check(load().rs_schedule_set(self._ctx, op, N, split), "rs_schedule_set")
+        arr = (ctypes.c_int * max(1, len(split)))(*split)
+        return _check(load().rs_schedule_set_parts(self._ctx, op, N, arr, len(split)), "rs_schedule_set_parts")
 
     def get_schedule(self, op, N):
+        """The low part's level count in effect."""
         t = ctypes.c_int()
         _check(load().rs_schedule_get(self._ctx, op, N, ctypes.byref(t)), "rs_schedule_get")
         return t.value
+
+    def get_schedule_parts(self, op, N):
+        arr, m = (ctypes.c_int * 4)(), ctypes.c_int()
+        _check(load().rs_schedule_get_parts(self._ctx, op, N, arr, ctypes.byref(m)), "rs_schedule_get_parts")
+        return tuple(arr[:m.value])
 
     # ------------------------------------------------------------ misc
     def sync(self, stream=None):

@@ -1,15 +1,17 @@
 """Autotuner of the pass-pipeline schedules (rs_schedule_set in include/rs.h).
 
 A code whose transforms exceed 256 points runs each transform over 2^N
-points as passes over groups of 2^T1 consecutive rows (the low T1 levels)
-and passes over groups of 2^(N - T1) strided rows (the other levels); every
-split with 4..8 levels per part computes the same result (level i only pairs
-rows j and j + 2^i, Sec. 3.2), but the kernels of different group sizes use
-the device differently (workgroup size, LDS per workgroup, resident
-workgroups per CU, arithmetic per byte moved).  For every (operation, N)
-class of a workload the tuner times each split on a seeded synthetic batch
-of that class through a reusable plan and keeps the fastest.  The result is
-a versioned JSON table that apply() or load() puts into a context.
+points as 2 to 4 parts of consecutive levels, each applied by passes over
+groups of rows that differ only in that part's index bits (the low part:
+groups of consecutive rows); every split into parts of 4..8 levels computes
+the same result (level i only pairs rows j and j + 2^i, Sec. 3.2), but the
+kernels of different group sizes use the device differently (workgroup
+size, LDS per workgroup, resident workgroups per CU, arithmetic per byte
+moved), and more parts mean more passes over the rows.  For every
+(operation, N) class of a workload the tuner times each candidate split on
+a seeded synthetic batch of that class through a reusable plan and keeps
+the fastest.  The result is a versioned JSON table that apply() or load()
+puts into a context.
 """
 from __future__ import annotations
 
@@ -19,7 +21,7 @@ import time
 
 from . import rs, synth
 
-VERSION = 1
+VERSION = 2
 FUSED_MAX_L = 8
 _OPS = {"enc": rs.RS_OP_ENCODE, "dec": rs.RS_OP_DECODE}
 
@@ -35,8 +37,22 @@ def mother(n: int, k: int):
 
 
 def candidates(N: int):
-    """Valid low-level counts T1 for a transform over 2^N points."""
-    return [t for t in range(4, 9) if 4 <= N - t <= 8]
+    """Candidate splits (level counts, low part first) of a transform over
+    2^N points: every two-part split, the three-part splits with at most 6
+    levels per part, and four parts of 4 levels."""
+    out = [(t, N - t) for t in range(4, 9) if 4 <= N - t <= 8]
+    out += [(a, b, N - a - b) for a in range(4, 7) for b in range(4, 7) if 4 <= N - a - b <= 6]
+    if N == 16:
+        out.append((4, 4, 4, 4))
+    return out
+
+
+def default_split(N: int):
+    return ((N + 1) // 2, N // 2)
+
+
+def split_name(parts):
+    return "/".join(str(p) for p in parts)
 
 
 def classes(shapes):
@@ -103,16 +119,16 @@ def tune(codec, shapes, row_bytes=(1024, 4096, 16384, 65536), target_bytes=256 <
             batch = enc
         torch.cuda.synchronize()
         ms = {}
-        for T1 in candidates(N):
-            codec.set_schedule(_OPS[op], N, T1)
+        for parts in candidates(N):
+            codec.set_schedule(_OPS[op], N, parts)
             plan = codec.plan_decode_batch(batch) if op == "dec" else codec.plan_encode_batch(batch)
-            ms[T1] = _time_plan(plan, stream, warmup, reps)
+            ms[parts] = _time_plan(plan, stream, warmup, reps)
             plan.close()
-        best = min(ms, key=lambda t: (ms[t], t))
+        best = min(ms, key=lambda t: (ms[t], len(t), t))
         codec.set_schedule(_OPS[op], N, best)
-        entry = {"op": op, "N": N, "T1": best, "default_T1": (N + 1) // 2, "shapes": [list(x) for x in shp],
-                 "stripes": len(stripes), "codeword_bytes": total,
-                 "ms": {str(t): round(v, 4) for t, v in sorted(ms.items())}}
+        entry = {"op": op, "N": N, "parts": list(best), "default": list(default_split(N)),
+                 "shapes": [list(x) for x in shp], "stripes": len(stripes), "codeword_bytes": total,
+                 "ms": {split_name(t): round(v, 4) for t, v in sorted(ms.items())}}
         table["entries"].append(entry)
         if log:
             log(entry)
@@ -125,7 +141,7 @@ def apply(codec, table):
     if table.get("version") != VERSION:
         raise ValueError("schedule table version %r, expected %d" % (table.get("version"), VERSION))
     for e in table["entries"]:
-        codec.set_schedule(_OPS[e["op"]], int(e["N"]), int(e["T1"]))
+        codec.set_schedule(_OPS[e["op"]], int(e["N"]), tuple(int(p) for p in e["parts"]))
 
 
 def save(table, path):
@@ -142,8 +158,8 @@ def load(path, codec=None):
 
 
 def summary(table):
-    """{"dec:12": T1, ...} of a table, for reports."""
-    return {"%s:%d" % (e["op"], e["N"]): e["T1"] for e in table["entries"]}
+    """{"dec:12": "4/4/4", ...} of a table, for reports."""
+    return {"%s:%d" % (e["op"], e["N"]): split_name(e["parts"]) for e in table["entries"]}
 
 
 if __name__ == "__main__":

@@ -1,8 +1,9 @@
-"""GPU parity of every schedule of the pass pipelines (rs_schedule_set):
-each split of a transform over 2^N > 256 points into low and high levels
-gives the oracle's parity and restores every erasure, for aligned and
-unaligned rows; plus the error paths of the schedule calls, the environment
-variable that sets schedules at rs_init, and the autotuner's table."""
+"""GPU parity of every candidate schedule of the pass pipelines
+(rs_schedule_set_parts): each split of a transform over 2^N > 256 points
+into two, three or four parts of levels gives the oracle's parity and
+restores every erasure, for aligned and unaligned rows; plus the error paths
+of the schedule calls, the environment variable that sets schedules at
+rs_init, and the autotuner's table."""
 import math
 import os
 
@@ -16,8 +17,9 @@ from gpu_util import first_diff, rand_rows, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
-ENC_SHAPES = [(1024, 512), (2048, 1024), (4096, 2048), (8192, 4096)]          # N = lg k' = 9 .. 12
-DEC_SHAPES = [(512, 256), (300, 200), (1024, 512), (2048, 1024), (4096, 2048), (8192, 4096)]  # lg n' = 9 .. 13
+ENC_SHAPES = [(1024, 512), (2048, 1024), (4096, 2048), (8192, 4096), (16384, 8192)]   # N = lg k' = 9 .. 13
+DEC_SHAPES = [(512, 256), (300, 200), (1024, 512), (2048, 1024), (4096, 2048), (8192, 4096),
+              (5000, 4000)]                                                            # lg n' = 9 .. 13
 NCOLS = (260, 37)     # a whole and a ragged tile with 8-byte-aligned rows; unaligned rows (74-byte rows)
 
 
@@ -37,6 +39,8 @@ def cs():
 
 
 def _stripes(n, k, key):
+    if isinstance(key, tuple):
+        key = sum(v << (4 * q) for q, v in enumerate(key))
     return [rand_rows(k, 2 * nc, 60, n, k, nc, key) for nc in NCOLS]
 
 
@@ -44,7 +48,7 @@ def _stripes(n, k, key):
 def test_encode_every_split(cs, n, k, N, T1):
     cs.set_schedule(rs.RS_OP_ENCODE, N, T1)
     try:
-        assert cs.get_schedule(rs.RS_OP_ENCODE, N) == T1
+        assert cs.get_schedule_parts(rs.RS_OP_ENCODE, N) == T1
         msgs = _stripes(n, k, T1)
         dm = [to_dev(m) for m in msgs]
         dp = [torch.zeros((n - k, m.shape[1]), dtype=torch.uint8, device="cuda") for m in msgs]
@@ -60,11 +64,11 @@ def test_encode_every_split(cs, n, k, N, T1):
 def test_decode_every_split(cs, n, k, N, T1):
     cs.set_schedule(rs.RS_OP_DECODE, N, T1)
     try:
-        assert cs.get_schedule(rs.RS_OP_DECODE, N) == T1
+        assert cs.get_schedule_parts(rs.RS_OP_DECODE, N) == T1
         cws, masks, ds = [], [], []
-        for i, m in enumerate(_stripes(n, k, 100 + T1)):
+        for i, m in enumerate(_stripes(n, k, 100 + sum(v << (4 * q) for q, v in enumerate(T1)))):
             cw = np.concatenate([m, oracle.encode(16, n, k, m)])
-            mask = synth.erasure_mask(synth.key(61, n, k, T1, i), n, [n - k, (n - k) // 2][i])
+            mask = synth.erasure_mask(synth.key(61, n, k, len(T1), T1[0], i), n, [n - k, (n - k) // 2][i])
             rx = cw.copy()
             rx[mask == 1] = 0x5A
             cws.append(cw)
@@ -96,18 +100,28 @@ def test_schedule_errors(cs, codec8):
     assert ei.value.code == rs.RS_ESHAPE
     for N in range(9, 17):
         assert cs.get_schedule(rs.RS_OP_DECODE, N) == (N + 1) // 2
+        assert cs.get_schedule_parts(rs.RS_OP_DECODE, N) == tune.default_split(N)
+    for bad in ((4, 4, 3), (4, 4, 4, 4), (4, 4, 4, 1), (9, 3), (4, 4, 4, 4, 0)):
+        with pytest.raises(rs.RSError) as ei:
+            cs.set_schedule(rs.RS_OP_DECODE, 12, bad)
+        assert ei.value.code == rs.RS_EINVAL, bad
+    cs.set_schedule(rs.RS_OP_DECODE, 12, (4, 4, 4))
+    assert cs.get_schedule_parts(rs.RS_OP_DECODE, 12) == (4, 4, 4) and cs.get_schedule(rs.RS_OP_DECODE, 12) == 4
+    cs.set_schedule(rs.RS_OP_DECODE, 12, ())
+    assert cs.get_schedule_parts(rs.RS_OP_DECODE, 12) == (6, 6)
 
 
 def test_schedule_environment():
     old = os.environ.get("RS_NB_SCHEDULE")
     try:
-        os.environ["RS_NB_SCHEDULE"] = "dec:12:8,enc:11:4"
+        os.environ["RS_NB_SCHEDULE"] = "dec:12:8,enc:11:4,dec:16:4/4/4/4"
         c = rs.Codec(16)
         assert c.get_schedule(rs.RS_OP_DECODE, 12) == 8
         assert c.get_schedule(rs.RS_OP_ENCODE, 11) == 4
         assert c.get_schedule(rs.RS_OP_DECODE, 11) == 6
+        assert c.get_schedule_parts(rs.RS_OP_DECODE, 16) == (4, 4, 4, 4)
         c.close()
-        for bad in ("dec:12:3", "dec:12", "xyz:10:5", "enc:11:4;dec:12:6"):
+        for bad in ("dec:12:3", "dec:12", "xyz:10:5", "enc:11:4;dec:12:6", "dec:12:4/4/3", "dec:12:4/"):
             os.environ["RS_NB_SCHEDULE"] = bad
             with pytest.raises(rs.RSError) as ei:
                 rs.Codec(16)
@@ -126,14 +140,43 @@ def test_autotuner_table(tmp_path):
         got = {(e["op"], e["N"]): e for e in tab["entries"]}
         assert set(got) == {("enc", 9), ("dec", 10)}
         for (op, N), e in got.items():
-            assert e["T1"] in tune.candidates(N) and set(e["ms"]) == {str(t) for t in tune.candidates(N)}
-            assert c.get_schedule(tune._OPS[op], N) == e["T1"]
+            assert tuple(e["parts"]) in tune.candidates(N)
+            assert set(e["ms"]) == {tune.split_name(t) for t in tune.candidates(N)}
+            assert c.get_schedule_parts(tune._OPS[op], N) == tuple(e["parts"])
         path = str(tmp_path / "sched.json")
         tune.save(tab, path)
         c2 = rs.Codec(16)
         assert tune.load(path, c2) == tab
         for (op, N), e in got.items():
-            assert c2.get_schedule(tune._OPS[op], N) == e["T1"]
+            assert c2.get_schedule_parts(tune._OPS[op], N) == tuple(e["parts"])
         c2.close()
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("parts,enc_parts", [((8, 8), (7, 8)), ((4, 4, 4, 4), (4, 4, 7)), ((4, 6, 6), (4, 5, 6)),
+                                             ((6, 5, 5), (5, 5, 5))])
+def test_largest_code_splits(cs, parts, enc_parts):
+    # the (65536, 32768) code: decode over 2^16 points and encode over 2^15
+    n, k, nc = 65536, 32768, 5
+    N = 16
+    cs.set_schedule(rs.RS_OP_DECODE, N, parts)
+    cs.set_schedule(rs.RS_OP_ENCODE, 15, enc_parts)
+    try:
+        msg = rand_rows(k, 2 * nc, 62, len(parts))
+        dm = to_dev(msg)
+        dp = torch.zeros((n - k, 2 * nc), dtype=torch.uint8, device="cuda")
+        cs.encode(n, k, dm, dp)
+        par = to_host(dp)
+        assert (par == oracle.encode(16, n, k, msg)).all(), enc_parts
+        cw = np.concatenate([msg, par])
+        mask = synth.erasure_mask(synth.key(63, len(parts), parts[0]), n, n - k)
+        rx = cw.copy()
+        rx[mask == 1] = 0
+        d = to_dev(rx)
+        cs.decode(n, k, mask, d)
+        got = to_host(d)
+        assert (got == cw).all(), (parts, first_diff(got, cw))
+    finally:
+        cs.set_schedule(rs.RS_OP_DECODE, N, 0)
+        cs.set_schedule(rs.RS_OP_ENCODE, 15, 0)

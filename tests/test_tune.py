@@ -6,11 +6,14 @@ from paper_1404_3458_amd import rs, tune
 
 
 def test_candidates():
-    assert tune.candidates(9) == [4, 5]
-    assert tune.candidates(12) == [4, 5, 6, 7, 8]
-    assert tune.candidates(16) == [8]
+    assert tune.candidates(9) == [(4, 5), (5, 4)]
+    assert tune.candidates(12) == [(4, 8), (5, 7), (6, 6), (7, 5), (8, 4), (4, 4, 4)]
+    assert (8, 8) in tune.candidates(16) and (4, 4, 4, 4) in tune.candidates(16)
     for N in range(9, 17):
-        assert (N + 1) // 2 in tune.candidates(N)          # the default is always valid
+        c = tune.candidates(N)
+        assert tune.default_split(N) in c                  # the default is always a candidate
+        assert all(sum(p) == N and all(4 <= v <= 8 for v in p) and 2 <= len(p) <= 4 for p in c)
+        assert len(set(c)) == len(c)
 
 
 def test_classes():
@@ -29,12 +32,13 @@ class FakeCodec:
 
 
 def test_table_roundtrip(tmp_path):
-    tab = {"version": tune.VERSION, "entries": [{"op": "dec", "N": 12, "T1": 7}, {"op": "enc", "N": 11, "T1": 5}]}
+    tab = {"version": tune.VERSION, "entries": [{"op": "dec", "N": 12, "parts": [4, 4, 4]},
+                                                 {"op": "enc", "N": 11, "parts": [5, 6]}]}
     p = str(tmp_path / "t.json")
     tune.save(tab, p)
     c = FakeCodec()
     assert tune.load(p, c) == tab
-    assert c.calls == [(rs.RS_OP_DECODE, 12, 7), (rs.RS_OP_ENCODE, 11, 5)]
-    assert tune.summary(tab) == {"dec:12": 7, "enc:11": 5}
+    assert c.calls == [(rs.RS_OP_DECODE, 12, (4, 4, 4)), (rs.RS_OP_ENCODE, 11, (5, 6))]
+    assert tune.summary(tab) == {"dec:12": "4/4/4", "enc:11": "5/6"}
     with pytest.raises(ValueError):
         tune.apply(FakeCodec(), {"version": tune.VERSION + 1, "entries": []})
