@@ -62,7 +62,8 @@ __device__ __forceinline__ void deriv_regs(uint32_t (*x)[Traits<R>::NW], const T
 // outputs are never used (encode: parity rows of a shortened code that are
 // not stored; decode: groups of 16 points without an erased stored row).
 template <int R, int L, int MODE, int SH, int LD, bool PR = false>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_small(NB_FUSED_PARAMS)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == M_ENC || MODE == M_ENC2 ? 3 : 4))) void k_small(
+    NB_FUSED_PARAMS)
 {
     constexpr int NW = Traits<R>::NW, NR = 1 << L;
     const int tile = blockIdx.x;
@@ -153,9 +154,7 @@ struct TiledLds {
 // in x (zeros for the other points) and whose tables are staged: the
 // weighting by Pi, the inverse transform (16-row register groups, LDS
 // transpose, stride-16 groups), the derivative across both groupings, the
-// forward transform and the division of erased rows by Pi'.  `hook` runs
-// right after the last read of the tile region (each wave then owns its 16
-// consecutive rows of it until the function returns).
+// forward transform and the division of erased rows by Pi'.
 template <int R, int L>
 struct DecTile {
     typedef TiledLds<R, L, M_DEC> LY;
@@ -193,10 +192,10 @@ struct DecTile {
         }
     }
 
-    template <int LD, bool PR, class HOOK>
+    template <int LD, bool PR>
     __device__ __forceinline__ void run(uint32_t (*x)[Traits<R>::NW], const bool *rcv, const DevStripe &st,
                                         const Lane &ln, const uint32_t *__restrict__ bits,
-                                        const uint32_t *__restrict__ rowtab, const HOOK &hook) const
+                                        const uint32_t *__restrict__ rowtab) const
     {
         const int g = wave;
         const TwLds<R, L> twX = {p_tw, 0u, vX()};
@@ -285,14 +284,11 @@ struct DecTile {
                     put(r0 + 16 * j, z[u][j]);
         }
         __syncthreads();
-        if (PR && !((used >> g) & 1u)) {
-            hook();
+        if (PR && !((used >> g) & 1u))
             return;
-        }
 #pragma unroll
         for (int j = 0; j < 16; j++)
             get(16 * g + j, x[j]);
-        hook();
         // levels 3..0 and step 6
         reg_levels<R, 4, false, SH_ZERO, false>(x, (uint32_t)(16 * g), 0, twX);
         pipelined<Tab, 16>([&](int j) { return row_tab<R>(rowtab, vrt, 16 * g + j); },
@@ -302,8 +298,11 @@ struct DecTile {
     }
 };
 
+// M_ENC keeps the coefficients in registers across the parity blocks: below
+// 2^8 points its workgroup has at most 8 waves, so it may use the registers
+// of two waves per SIMD instead of spilling.
 template <int R, int L, int MODE, int SH, int LD, bool PR = false>
-__global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4))) void k_tiled(NB_FUSED_PARAMS)
+__global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(MODE == M_ENC && L < 8 ? 2 : 4))) void k_tiled(NB_FUSED_PARAMS)
 {
     typedef TiledLds<R, L, MODE> LY;
     typedef typename Ops<R>::Tab Tab;
@@ -468,7 +467,7 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
     stage_tables();
     if (MODE == M_DEC) {
         const DecTile<R, L> dt = {lds, p_tw, p_B, p_Binv, wave, lane};
-        dt.template run<LD, PR>(x, rcv, st, ln, bits, rowtab, [] {});
+        dt.template run<LD, PR>(x, rcv, st, ln, bits, rowtab);
         return;
     }
     reg_levels<R, 4, true, (MODE == M_IFFT ? SH : SH_ZERO), false>(x, (uint32_t)(16 * g), 0, twX);

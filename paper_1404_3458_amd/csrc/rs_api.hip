@@ -509,6 +509,12 @@ hipError_t fused_launch(int r, int mode, int sh, int ld, int L, const FusedArgs 
 // kernel variant without the loop over parity blocks.
 bool one_parity_block(const Plan &p) { return !p.decoding && p.ds.np == 2 * p.ds.kp; }
 
+// Stripes whose transforms run as pass pipelines: more than 256 points, and
+// encodes over 256 points with several parity blocks (the fused kernel
+// would keep the coefficients of a 1024-thread workgroup in registers across
+// the blocks, which does not fit).
+bool runs_wide(const Plan &p) { return p.L > FUSED_MAX_L || (p.L == FUSED_MAX_L && !p.decoding && !one_parity_block(p)); }
+
 // Stripes of one fused launch share the transform size, the row access
 // variant and the kernel variant.
 int launch_key(const Plan &p, int ld)
@@ -555,7 +561,7 @@ size_t wide_scratch_rows(const Plan &p)
 
 void unpack_parts(int v, int N, int *parts, int *nparts);
 
-// Split the wide stripes (plan indices, all with L > FUSED_MAX_L) into
+// Split the wide stripes (plan indices, all runs_wide) into
 // chunks, lay out their scratch from `scratch_base` (null while sizing) and
 // list the launches: per chunk and transform size, every pass kind in order,
 // one launch per row-access variant.
@@ -815,7 +821,7 @@ int build_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, 
     std::vector<Entry> ents;
     for (int q = 0; q < m; q++) {
         const Plan &p = plans[act[q]];
-        if (p.L > FUSED_MAX_L)
+        if (runs_wide(p))
             continue;
         for (const ColPart &c : col_parts(p.aligned, p.ds.ncols))
             ents.push_back({act[q], c});
@@ -868,7 +874,7 @@ int build_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, 
     // Stripes over more than 256 points: 8-level pass pipelines.
     std::vector<int> widx;
     for (int q = 0; q < m; q++)
-        if (plans[act[q]].L > FUSED_MAX_L)
+        if (runs_wide(plans[act[q]]))
             widx.push_back(act[q]);
     if (!widx.empty()) {
         int sc[17];

@@ -53,8 +53,9 @@ struct Batch {
 };
 
 // Device bytes a request keeps in flight: its codeword rows, the scratch of
-// the 8-level pass pipelines (mother codes over 256 points) and, for a
-// decode, the per-point locator tables (20 dwords each at r = 16).
+// the pass pipelines (mother codes over 256 points, and encodes over 256
+// points with several parity blocks) and, for a decode, the per-point
+// locator tables (20 dwords each at r = 16).
 size_t request_bytes(const rs_request &q)
 {
     const rs_stripe_desc &d = q.desc;
@@ -65,7 +66,7 @@ size_t request_bytes(const rs_request &q)
         b += (size_t)np * 80;
         if (np > 256)
             b += 2 * (size_t)np * rb;
-    } else if (kp > 256) {
+    } else if (kp > 256 || (kp == 256 && np > 512)) {
         b += 2 * (size_t)kp * rb;
     }
     return b;
