@@ -585,10 +585,17 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(M
 // Modes with a pruned variant.
 constexpr bool can_prune(int mode) { return mode == M_ENC || mode == M_ENC2 || mode == M_DEC; }
 
+// Encodes over 2^8 points with several parity blocks run as pass pipelines
+// (the host never sends them here), so that variant is not built.
+template <int R, int L, int MODE>
+constexpr bool fused_built() { return !(MODE == M_ENC && L >= 8); }
+
 template <int R, int L, int MODE, int SH, int LD, bool PR>
 static hipError_t launch_pr(const FusedArgs &a, const KPtrs &k, int ntiles, hipStream_t stream)
 {
-    if (L <= 4) {
+    if constexpr (!fused_built<R, L, MODE>())
+        return hipErrorInvalidValue;
+    else if (L <= 4) {
         hipLaunchKernelGGL((k_small<R, (L <= 4 ? L : 4), MODE, SH, LD, PR>), dim3(ntiles), dim3(64), 0, stream, a,
                            k.tw, k.B, k.Binv, k.bits, k.rowtabs);
     } else {
@@ -614,7 +621,9 @@ static hipError_t launch_one(const FusedArgs &a, const KPtrs &k, int ntiles, boo
 template <int R, int L, int MODE, int SH, int LD>
 static hipError_t prep_one()
 {
-    if (L > 4) {
+    if constexpr (!fused_built<R, L, MODE>())
+        return hipSuccess;
+    else if (L > 4) {
         constexpr int LL = L > 4 ? L : 5;
         hipError_t e = hipFuncSetAttribute((const void *)k_tiled<R, LL, MODE, SH, LD, false>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
