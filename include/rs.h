@@ -156,6 +156,20 @@ int rs_plan_encode_batch(rs_ctx *ctx, const rs_stripe_desc *descs, int count, rs
 int rs_plan_decode_batch(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, int count,
                          rs_plan **out);
 int rs_plan_launch(rs_plan *plan, void *stream);
+/* Completion timestamps of the stripes of a plan (the per-stripe timing of a
+ * batch): each later launch first sets ts[0] to the device's real-time
+ * counter; every workgroup of every kernel of the launch then raises a slot
+ * of its own to the counter as its waves finish (a vector atomic maximum),
+ * and a last kernel of the launch sets ts[1 + i] to the latest slot of the
+ * workgroups that worked on stripe i, so ts[1 + i] - ts[0] is when stripe i
+ * was done.  ts[1 + i] is 0 when no kernel works on the stripe (no columns;
+ * a decode without erasures, which is nothing in place and a copy
+ * otherwise).  dev_ts: count + 1 device uint64 (NULL stops the stamps);
+ * clock_khz (may be NULL) receives the counter's rate.  The first call with
+ * a non-NULL dev_ts allocates the plan's slots (8 bytes per workgroup of its
+ * launches, freed with the plan): RS_ENOMEM if they cannot be allocated.  A
+ * graph captured from the plan keeps the setting it was captured with. */
+int rs_plan_set_timestamps(rs_plan *plan, uint64_t *dev_ts, int *clock_khz);
 /* Waits for the device, then frees the plan (NULL is a no-op). */
 void rs_plan_free(rs_plan *plan);
 

@@ -302,9 +302,20 @@ __device__ __forceinline__ void pin(const uint32_t *v)
         asm volatile("" ::"v"(v[0]));
 }
 
-// Runs work(k, table_k) for k < N with table k + 1 fetched before work k, so
-// that one table fetch is in flight while a block is computed; work ends
-// with pin() on what it produced.
+// Completion stamp of a workgroup: when an object of this type goes out of
+// scope (every return of a kernel), the first lane of each wave raises
+// slots[blockIdx.x] to the device's real-time counter with a vector atomic,
+// so that the slot ends as the time its last wave finished.  Every
+// workgroup has a slot of its own (atomics on one address serialize).
+struct DoneStamp {
+    uint64_t *slots;
+    __device__ __forceinline__ ~DoneStamp()
+    {
+        if (slots && (threadIdx.x & 63u) == 0u)
+            atomicMax((unsigned long long *)(slots + blockIdx.x), (unsigned long long)__builtin_amdgcn_s_memrealtime());
+    }
+};
+
 // Step k of the loop is instantiated once per k (template recursion rather
 // than an unroll pragma, which the compiler may decline for long loops; a
 // loop left rolled would index the register arrays at run time and move them
@@ -336,6 +347,9 @@ struct PipeStep<Tab, N, N> {
     }
 };
 
+// Runs work(k, table_k) for k < N with table k + 1 fetched before work k, so
+// that one table fetch is in flight while a block is computed; work ends
+// with pin() on what it produced.
 template <class Tab, int N, class F, class W>
 __device__ __forceinline__ void pipelined(const F &fetch, const W &work)
 {

@@ -70,6 +70,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == M_EN
     const int s = find_stripe(a.stripes, a.nstripes, tile);
     const DevStripe st = a.stripes[s];
     const Lane ln = lane_of<R, LD>(tile - st.tile0, (int)threadIdx.x, st.col0, st.ncols);
+    const DoneStamp done = {a.ts};
     const uint64_t rb = st.row_bytes;
     const Tabs tb = {p_tw, p_B, p_Binv};
     const uint32_t *__restrict__ bits = p_bits + st.bits_off;
@@ -325,6 +326,7 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(M
     const int s = find_stripe(a.stripes, a.nstripes, tile);
     const DevStripe st = a.stripes[s];
     const Lane ln = lane_of<R, LD>(tile - st.tile0, lane, st.col0, st.ncols);
+    const DoneStamp done = {a.ts};
     const uint64_t rb = st.row_bytes;
     const uint32_t *__restrict__ bits = p_bits + st.bits_off;
     const uint32_t *__restrict__ rowtab = p_rowtabs + st.rowtab_off;

@@ -288,6 +288,60 @@ hipError_t init_tables(int r, const uint32_t *d_basis, uint32_t *d_Wv, uint32_t 
     return hipGetLastError();
 }
 
+// Start of a timed plan launch: ts[0] = the device's real-time counter, and
+// the per-workgroup slots the kernels stamp are cleared.  A kernel rather
+// than a memset, so that the launch can be captured in a graph.
+__global__ void k_stamp_start(uint64_t *__restrict__ ts, uint64_t *__restrict__ slots, size_t nslots)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0)
+        ts[0] = __builtin_amdgcn_s_memrealtime();
+    for (; i < nslots; i += (size_t)gridDim.x * blockDim.x)
+        slots[i] = 0ull;
+}
+
+hipError_t stamp_start(uint64_t *ts, uint64_t *slots, size_t nslots, hipStream_t s)
+{
+    const size_t blocks = (nslots + 255) / 256;
+    hipLaunchKernelGGL(k_stamp_start, dim3(blocks < 1 ? 1 : blocks > 1024 ? 1024 : (unsigned)blocks), dim3(256), 0, s,
+                       ts, slots, nslots);
+    return hipGetLastError();
+}
+
+// End of a timed plan launch: ts[1 + i] = the latest stamp among the slots
+// of the workgroups that worked on stripe i (slot ranges segs[2 j] ..
+// segs[2 j + 1] - 1 for j in seg_ptr[i] .. seg_ptr[i + 1] - 1), 0 when there
+// are none.  One workgroup per stripe.
+__global__ __launch_bounds__(256) void k_stamp_reduce(uint64_t *__restrict__ ts, const uint64_t *__restrict__ slots,
+                                                      const uint32_t *__restrict__ seg_ptr,
+                                                      const uint32_t *__restrict__ segs)
+{
+    __shared__ uint64_t red[256];
+    const int i = blockIdx.x, t = threadIdx.x;
+    uint64_t m = 0;
+    for (uint32_t j = seg_ptr[i]; j < seg_ptr[i + 1]; j++)
+        for (uint32_t k = segs[2 * j] + t; k < segs[2 * j + 1]; k += 256)
+            m = slots[k] > m ? slots[k] : m;
+    red[t] = m;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h && red[t + h] > red[t])
+            red[t] = red[t + h];
+        __syncthreads();
+    }
+    if (t == 0)
+        ts[1 + i] = red[0];
+}
+
+hipError_t stamp_reduce(uint64_t *ts, const uint64_t *slots, const uint32_t *seg_ptr, const uint32_t *segs,
+                        int nstripes, hipStream_t s)
+{
+    if (nstripes <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_stamp_reduce, dim3(nstripes), dim3(256), 0, s, ts, slots, seg_ptr, segs);
+    return hipGetLastError();
+}
+
 // Perm tables of `count` field elements (vals, device) into tabs.
 hipError_t perm_tables(int r, const uint32_t *vals, uint32_t count, uint32_t *tabs, hipStream_t s)
 {

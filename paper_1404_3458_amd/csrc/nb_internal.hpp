@@ -43,12 +43,14 @@ struct DevStripe {
     int32_t tile0;            // index of this stripe's first tile in the launch
     int32_t col0;             // first column covered by this launch
     int32_t copy_survivors;   // decode with out != in
+    int32_t sid;              // index of the stripe in the call (completion timestamps)
 };
 
 struct FusedArgs {
     const DevStripe *stripes;
     int32_t nstripes;
     uint32_t l;               // shift of the plain transforms
+    uint64_t *ts;             // completion stamp slots of this launch (one per workgroup), or null
 };
 
 // Multi-pass (h > 256) kernels: one launch applies up to 4 levels.  The
@@ -115,6 +117,7 @@ struct WideArgs {
     int32_t nstripes;
     int32_t lo;               // groups are rows gbase + (j << lo)
     int32_t blk;              // encode: parity block, transformed at shift blk * k'
+    uint64_t *ts;             // completion stamp slots of this launch (one per workgroup), or null
 };
 
 // One pass of the multi-workgroup locator of one stripe (k_loc_pass).

@@ -111,6 +111,7 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
     const int s = find_wide(a.stripes, a.nstripes, tile);
     const WideStripe ws = a.stripes[s];
     const DevStripe &st = ws.st;
+    const DoneStamp done = {a.ts};
     const int rel = tile - ws.tile0;
     const uint32_t gi = (uint32_t)(rel / ws.nct);
     const int ct = rel % ws.nct;

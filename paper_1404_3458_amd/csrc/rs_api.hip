@@ -30,6 +30,9 @@ hipError_t fused_prepare_8();
 hipError_t poly_launch(int r, int ld, int kind, const PolyArgs &a, const uint32_t *t1, const uint32_t *t2,
                        uint32_t nblocks, hipStream_t s);
 hipError_t perm_tables(int r, const uint32_t *vals, uint32_t count, uint32_t *tabs, hipStream_t s);
+hipError_t stamp_start(uint64_t *ts, uint64_t *slots, size_t nslots, hipStream_t s);
+hipError_t stamp_reduce(uint64_t *ts, const uint64_t *slots, const uint32_t *seg_ptr, const uint32_t *segs,
+                        int nstripes, hipStream_t s);
 enum { PK_PAD = 0, PK_MUL = 1, PK_DEGREE = 2, PK_UP = 3, PK_DOWN = 4 };
 hipError_t fused_launch_16(int mode, int sh, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
                            bool pr, hipStream_t s);
@@ -327,6 +330,7 @@ int validate_stripe(rs_ctx *ctx, const rs_stripe_desc &d, bool decode, const uin
     pl.ds.np = np;
     pl.ds.ncols = (int32_t)(d.row_bytes / sym);
     pl.ds.copy_survivors = decode && d.in != d.out ? 1 : 0;
+    pl.ds.sid = 0;                                    // set by build_codec
     pl.aligned = vec_aligned(ctx, d.in, d.out, d.row_bytes);
     pl.L = ilog2(decode ? np : kp);
     pl.erasures = 0;
@@ -755,6 +759,7 @@ struct CodecPlan {
     size_t dev_bytes = 0;
     size_t off_loc = 0, off_bits = 0, off_wide = 0, off_rt = 0, off_locv = 0;
     std::vector<FusedLaunch> fused;
+    std::vector<std::pair<int32_t, int32_t>> ent_tiles;  // (stripe, first tile) of each fused entry
     int m_small = 0, max_np = 1;
     std::vector<LocLarge> loc_large;
     WidePlan wp;
@@ -783,6 +788,7 @@ int build_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, 
         int rc = validate_stripe(ctx, descs[i], decode, m, plans[i]);
         if (rc)
             return rc;
+        plans[i].ds.sid = i;
         plans[i].mask_src = mask_total;
         if (decode)
             mask_total += (size_t)descs[i].n;
@@ -839,6 +845,7 @@ int build_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, 
             eds[e] = plans[ents[e].plan].ds;
             eds[e].col0 = ents[e].cp.col0;
             eds[e].tile0 = tiles;
+            cp.ent_tiles.push_back({eds[e].sid, tiles});
             tiles += ents[e].cp.ntiles;
             e++;
         }
@@ -920,10 +927,75 @@ int build_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, 
     return RS_OK;
 }
 
+// Completion stamps of a plan: one slot per workgroup of every fused and
+// pass-pipeline launch (the kernels raise their workgroup's slot as its
+// waves finish) and, per stripe, the slot ranges of the workgroups that work
+// on it, which a last kernel reduces into the caller's timestamps.
+struct StampMap {
+    uint8_t *dev = nullptr;             // slots | seg_ptr | segs
+    uint64_t *slots = nullptr;
+    const uint32_t *seg_ptr = nullptr;  // count + 1 offsets into segs (pairs)
+    const uint32_t *segs = nullptr;     // [begin, end) slot ranges
+    size_t nslots = 0;
+    std::vector<size_t> fused_off, wide_off;  // first slot of each launch
+};
+
+// The slot ranges of a built plan of `count` stripes (host side of StampMap;
+// reads the plan's entry lists, not its arena image, which a reusable plan
+// drops once uploaded).  Within a launch, entry e covers workgroups
+// tile0_e .. tile0_{e+1} - 1 (the last entry: up to the launch's workgroup
+// count).
+int stamp_ranges(const CodecPlan &cp, int count, StampMap &sm, std::vector<uint32_t> &seg_ptr,
+                 std::vector<uint32_t> &segs)
+{
+    std::vector<std::vector<std::pair<size_t, size_t>>> per((size_t)count);
+    size_t off = 0;
+    auto add = [&](int sid, size_t b, size_t e) {
+        if (e > b)
+            per[(size_t)sid].push_back({off + b, off + e});
+    };
+    for (const FusedLaunch &fl : cp.fused) {
+        sm.fused_off.push_back(off);
+        for (size_t q = 0; q < fl.count; q++) {
+            const std::pair<int32_t, int32_t> &t = cp.ent_tiles[fl.first + q];
+            const size_t end = q + 1 < fl.count ? (size_t)cp.ent_tiles[fl.first + q + 1].second : (size_t)fl.ntiles;
+            add(t.first, (size_t)t.second, end);
+        }
+        off += (size_t)fl.ntiles;
+    }
+    for (const WideLaunch &wl : cp.wp.launches) {
+        sm.wide_off.push_back(off);
+        for (size_t q = 0; q < wl.count; q++) {
+            const WideStripe &w = cp.wp.descs[wl.first + q];
+            const size_t end = q + 1 < wl.count ? (size_t)cp.wp.descs[wl.first + q + 1].tile0 : (size_t)wl.ntiles;
+            add(w.st.sid, (size_t)w.tile0, end);
+        }
+        off += (size_t)wl.ntiles;
+    }
+    if (off > UINT32_MAX)
+        return RS_EINVAL;
+    sm.nslots = off;
+    seg_ptr.assign(1, 0);
+    segs.clear();
+    for (const auto &v : per) {
+        for (const auto &r : v) {
+            segs.push_back((uint32_t)r.first);
+            segs.push_back((uint32_t)r.second);
+        }
+        seg_ptr.push_back((uint32_t)(segs.size() / 2));
+    }
+    return RS_OK;
+}
+
 // Queue a built plan on `stream` with its arena at `dev` (the uploaded part
 // already in place).  Launches kernels and device-to-device copies only.
-int exec_codec(rs_ctx *ctx, const CodecPlan &cp, uint8_t *dev, hipStream_t stream)
+// sm, ts: completion stamps (ts[0] the launch start, ts[1 + i] stripe i's
+// last workgroup), or null.
+int exec_codec(rs_ctx *ctx, const CodecPlan &cp, uint8_t *dev, hipStream_t stream, const StampMap *sm = nullptr,
+               uint64_t *ts = nullptr, int nstripes = 0)
 {
+    if (sm && dev_err(ctx, stamp_start(ts, sm->slots, sm->nslots, stream)))
+        return RS_EDEVICE;
     for (size_t i = 0; i < cp.copies.size(); i++)
         if (dev_err(ctx, hipMemcpyAsync(cp.copies[i].first, cp.copies[i].second, cp.copy_bytes[i],
                                         hipMemcpyDeviceToDevice, stream)))
@@ -953,24 +1025,30 @@ int exec_codec(rs_ctx *ctx, const CodecPlan &cp, uint8_t *dev, hipStream_t strea
         }
     }
     const DevStripe *d_ents = (const DevStripe *)dev;
-    for (const FusedLaunch &fl : cp.fused) {
+    for (size_t i = 0; i < cp.fused.size(); i++) {
+        const FusedLaunch &fl = cp.fused[i];
         FusedArgs fa;
         fa.stripes = d_ents + fl.first;
         fa.nstripes = (int)fl.count;
         fa.l = 0;
+        fa.ts = sm ? sm->slots + sm->fused_off[i] : nullptr;
         if (dev_err(ctx, fused_launch(ctx->r, fl.mode, 0, fl.ld, fl.L, fa, kp, fl.ntiles, fl.prune, stream)))
             return RS_EDEVICE;
     }
     const WideStripe *d_wide = (const WideStripe *)(dev + cp.off_wide);
-    for (const WideLaunch &wl : cp.wp.launches) {
+    for (size_t i = 0; i < cp.wp.launches.size(); i++) {
+        const WideLaunch &wl = cp.wp.launches[i];
         WideArgs wa;
         wa.stripes = d_wide + wl.first;
         wa.nstripes = (int)wl.count;
         wa.lo = wl.lo;
         wa.blk = wl.blk;
+        wa.ts = sm ? sm->slots + sm->wide_off[i] : nullptr;
         if (dev_err(ctx, wide_launch(wl.kind, wl.ld, wl.T, wa, kp, wl.ntiles, stream)))
             return RS_EDEVICE;
     }
+    if (sm && dev_err(ctx, stamp_reduce(ts, sm->slots, sm->seg_ptr, sm->segs, nstripes, stream)))
+        return RS_EDEVICE;
     return RS_OK;
 }
 
@@ -1049,6 +1127,7 @@ int xform_locked(rs_ctx *ctx, Scratch *sc, int mode, int h, uint32_t l, uint8_t 
             fa.stripes = (const DevStripe *)sc->dev + i;
             fa.nstripes = 1;
             fa.l = l;
+            fa.ts = nullptr;
             const int sh = gen_l ? 2 : (l == 0 ? 0 : 1);
             if (dev_err(ctx, fused_launch(ctx->r, mode, sh, parts[i].ld, L, fa, ctx->kp, parts[i].ntiles, false, stream)))
                 return RS_EDEVICE;
@@ -1665,6 +1744,9 @@ struct rs_plan {
     CodecPlan cp;
     uint8_t *arena = nullptr;
     uint8_t *scratch = nullptr;
+    int count = 0;                // stripes of the batch
+    uint64_t *ts = nullptr;       // completion timestamps (rs_plan_set_timestamps)
+    StampMap *sm = nullptr;       // their slots, built on the first rs_plan_set_timestamps
 };
 
 static int plan_batch(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, int count, bool decode,
@@ -1677,6 +1759,7 @@ static int plan_batch(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *m
     if (!pl)
         return RS_ENOMEM;
     pl->ctx = ctx;
+    pl->count = count;
     size_t need = 0;
     int rc = build_codec(ctx, descs, masks, count, decode, nullptr, &need, pl->cp);
     DeviceGuard guard(ctx->device);
@@ -1739,9 +1822,56 @@ __attribute__((visibility("default"))) int rs_plan_launch(rs_plan *plan, void *s
         if (ctx->sticky)
             return ctx->sticky;
     }
-    if (plan->cp.empty())
+    const StampMap *sm = plan->ts ? plan->sm : nullptr;
+    if (plan->cp.empty()) {
+        if (sm && (dev_err(ctx, stamp_start(plan->ts, sm->slots, sm->nslots, (hipStream_t)stream)) ||
+                   dev_err(ctx, stamp_reduce(plan->ts, sm->slots, sm->seg_ptr, sm->segs, plan->count,
+                                             (hipStream_t)stream))))
+            return RS_EDEVICE;
         return RS_OK;
-    return exec_codec(ctx, plan->cp, plan->arena, (hipStream_t)stream);
+    }
+    return exec_codec(ctx, plan->cp, plan->arena, (hipStream_t)stream, sm, plan->ts, plan->count);
+}
+
+__attribute__((visibility("default"))) int rs_plan_set_timestamps(rs_plan *plan, uint64_t *dev_ts, int *clock_khz)
+{
+    if (!plan)
+        return RS_EINVAL;
+    DeviceGuard guard(plan->ctx->device);
+    if (!guard.ok)
+        return RS_EDEVICE;
+    if (clock_khz && hipDeviceGetAttribute(clock_khz, hipDeviceAttributeWallClockRate, plan->ctx->device) != hipSuccess)
+        return RS_EDEVICE;
+    if (dev_ts && !plan->sm) {
+        StampMap *sm = new (std::nothrow) StampMap();
+        if (!sm)
+            return RS_ENOMEM;
+        std::vector<uint32_t> seg_ptr, segs;
+        int rc = stamp_ranges(plan->cp, plan->count, *sm, seg_ptr, segs);
+        if (rc) {
+            delete sm;
+            return rc;
+        }
+        const size_t b_slots = sm->nslots * sizeof(uint64_t), b_ptr = seg_ptr.size() * sizeof(uint32_t),
+                     b_segs = segs.size() * sizeof(uint32_t);
+        if (hipMalloc((void **)&sm->dev, b_slots + b_ptr + b_segs + 8) != hipSuccess) {
+            (void)hipGetLastError();
+            delete sm;
+            return RS_ENOMEM;
+        }
+        sm->slots = (uint64_t *)sm->dev;
+        sm->seg_ptr = (const uint32_t *)(sm->dev + b_slots);
+        sm->segs = (const uint32_t *)(sm->dev + b_slots + b_ptr);
+        if (hipMemcpy(sm->dev + b_slots, seg_ptr.data(), b_ptr, hipMemcpyHostToDevice) != hipSuccess ||
+            (b_segs && hipMemcpy(sm->dev + b_slots + b_ptr, segs.data(), b_segs, hipMemcpyHostToDevice) != hipSuccess)) {
+            (void)hipFree(sm->dev);
+            delete sm;
+            return RS_EDEVICE;
+        }
+        plan->sm = sm;
+    }
+    plan->ts = dev_ts;
+    return RS_OK;
 }
 
 __attribute__((visibility("default"))) void rs_plan_free(rs_plan *plan)
@@ -1754,6 +1884,10 @@ __attribute__((visibility("default"))) void rs_plan_free(rs_plan *plan)
         (void)hipFree(plan->arena);
     if (plan->scratch)
         (void)hipFree(plan->scratch);
+    if (plan->sm) {
+        (void)hipFree(plan->sm->dev);
+        delete plan->sm;
+    }
     delete plan;
 }
 

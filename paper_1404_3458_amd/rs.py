@@ -60,6 +60,14 @@ class Plan:
     def launch(self, stream=None):
         return _check(load().rs_plan_launch(self._h, _stream(stream)), "rs_plan_launch")
 
+    def set_timestamps(self, ts=None):
+        """Stamp completion times into ts (int64 device tensor of count + 1,
+        None stops); returns the counter's rate in kHz."""
+        khz = ctypes.c_int()
+        _check(load().rs_plan_set_timestamps(self._h, _ptr(ts), ctypes.byref(khz)), "rs_plan_set_timestamps")
+        self._ts = ts
+        return khz.value
+
     def close(self):
         if self._h:
             load().rs_plan_free(self._h)
@@ -156,6 +164,7 @@ def load():
             "rs_plan_encode_batch": (i32, [vp, vp, i32, ctypes.POINTER(vp)]),
             "rs_plan_decode_batch": (i32, [vp, vp, vp, i32, ctypes.POINTER(vp)]),
             "rs_plan_launch": (i32, [vp, vp]),
+            "rs_plan_set_timestamps": (i32, [vp, vp, ctypes.POINTER(i32)]),
             "rs_plan_free": (None, [vp]),
             "rs_server_create": (i32, [vp, sz, i32, i32, ctypes.POINTER(vp)]),
             "rs_server_submit": (i32, [vp, vp]),

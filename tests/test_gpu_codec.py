@@ -312,3 +312,64 @@ def test_decode_many_tiles(request, r, n, k, ns, ncols, inplace):
         assert torch.equal(out[s], ref[s]), s
         if not inplace:
             assert torch.equal(cw[s], rx[s]), s          # input untouched
+
+
+def test_plan_timestamps(codec16):
+    # per-stripe completion stamps: every stripe a kernel works on is stamped
+    # after the launch's start stamp and before the start of a later launch
+    # on the same stream; stripes without kernel work keep 0; None stops them
+    specs = PLAN_SPECS + [(64, 32, 0)]
+    msgs, pars = _plan_buffers(specs, 3)
+    enc = codec16.plan_encode_batch([(n, k, msgs[i], pars[i]) for i, (n, k, _) in enumerate(specs)])
+    ts1 = torch.full((len(specs) + 1,), -1, dtype=torch.int64, device="cuda")
+    ts2 = torch.full_like(ts1, -1)
+    khz = enc.set_timestamps(ts1)
+    assert khz > 0
+    enc.launch()
+    enc.set_timestamps(ts2)
+    enc.launch()
+    torch.cuda.synchronize()
+    _check_parity(specs, msgs, pars)
+    a, b = ts1.cpu().numpy(), ts2.cpu().numpy()
+    for t in (a, b):
+        assert t[0] > 0
+        for i, (n, k, rb) in enumerate(specs):
+            if rb:
+                assert t[1 + i] >= t[0], (specs[i], t)
+            else:
+                assert t[1 + i] == 0, (specs[i], t)
+    assert b[0] >= a[1:].max()
+    assert (b[1:] - b[0]).max() < 10 * khz * 1000      # under 10 s
+    enc.set_timestamps(None)
+    ts2.fill_(-1)
+    enc.launch()
+    torch.cuda.synchronize()
+    assert (ts2.cpu().numpy() == -1).all()
+    enc.close()
+
+    items, cws, worked = [], [], []
+    for i, (n, k, rb) in enumerate(specs):
+        msg = rand_rows(k, rb, 64, i)
+        cws.append(np.concatenate([msg, oracle.encode(16, n, k, msg)]))
+        e = [n - k, 0, 1, 0][i % 4]
+        mask = synth.erasure_mask(synth.key(65, i), n, e)
+        rx = cws[i].copy()
+        rx[mask == 1] = 0x33
+        ds = to_dev(rx)
+        do = ds if i % 4 != 3 else torch.zeros_like(ds)   # i % 4 == 3: no erasures, out of place
+        items.append((n, k, mask, ds, do))
+        worked.append(rb > 0 and e > 0)
+    dec = codec16.plan_decode_batch(items)
+    ts = torch.full((len(specs) + 1,), -1, dtype=torch.int64, device="cuda")
+    dec.set_timestamps(ts)
+    dec.launch()
+    torch.cuda.synchronize()
+    t = ts.cpu().numpy()
+    for i, it in enumerate(items):
+        got = to_host(it[4])
+        assert (got == cws[i]).all(), (specs[i], first_diff(got, cws[i]))
+        if worked[i]:
+            assert t[1 + i] >= t[0] > 0, (specs[i], t)
+        else:
+            assert t[1 + i] == 0, (specs[i], t)
+    dec.close()
