@@ -37,9 +37,10 @@ CONFIGS = {
     "c1": dict(r=8, n=16, k=8, stripes=4096, shard_bytes=1, erasures=8,
                workload="GF(2^8) mod 0x11D, (n,k)=(16,8), 4096 stripes x 1 B shards, "
                         "encode + 8 erasures per stripe + decode"),
-    "c3": dict(r=16, n=65536, k=32768, stripes=1, shard_bytes=256, erasures=32768,
+    "c3": dict(r=16, n=65536, k=32768, stripes=1, shard_bytes=256, erasures=32768, sets=64,
                workload="GF(2^16) mod 0x1100B, (n,k)=(65536,32768), 1 stripe x 256 B shards, "
-                        "encode + 32768 erasures + decode"),
+                        "encode + 32768 erasures + decode; 64 codeword buffers (1 GiB) used in turn, "
+                        "so that no step finds its data in the 256 MB last-level cache"),
     "c5": dict(r=16, stripes=5000, serving=True, budget=64 << 30, requests=5000, warm=500, encode_share=0.7,
                workload="GF(2^16) mod 0x1100B serving: Poisson arrivals, 70% encode / 30% decode requests, "
                         "(n,k) and shards as the mixed workload (5000 resident stripes), 64 GB admission budget; "
@@ -694,6 +695,7 @@ def main():
     if cfg.get("serving"):
         return run_serving(args, cfg)
     r, n, k, S, ns, e = cfg["r"], cfg["n"], cfg["k"], cfg["shard_bytes"], cfg["stripes"], cfg["erasures"]
+    sets = cfg.get("sets", 1)
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     codec = rs.Codec(r)
@@ -703,17 +705,23 @@ def main():
     sched = schedule_for(args, codec, [(n, k, S, e)], target_bytes=ns * n * S) \
         if r == 16 and pow2ceil(kp_ + n - k) > 256 else None
 
-    # Codeword buffer: stripe s rows 0..k-1 are its message, k..n-1 its parity.
-    cw = torch.empty((ns, n, S), dtype=torch.uint8, device=dev)
-    for s in range(ns):
-        synth.fill_random_torch(synth.key(cfg["id"], s, synth.DATA), cw[s, :k])
+    # Codeword buffers: stripe s rows 0..k-1 are its message, k..n-1 its
+    # parity.  A workload smaller than the last-level cache keeps `sets`
+    # copies (same erasure patterns, distinct data) and step i uses copy
+    # i mod sets, so every step reads data that has left the cache.
+    cws = torch.empty((sets, ns, n, S), dtype=torch.uint8, device=dev)
+    for j in range(sets):
+        for s in range(ns):
+            synth.fill_random_torch(synth.key(cfg["id"], s, synth.DATA, *((j,) if j else ())), cws[j, s, :k])
+    cw = cws[0]
     masks = [synth.erasure_mask(synth.key(cfg["id"], s, synth.ERASURE), n, e) for s in range(ns)]
-    enc_items = codec.prepare_encode_batch([(n, k, cw[s, :k], cw[s, k:]) for s in range(ns)])
-    dec_items = codec.prepare_decode_batch([(n, k, masks[s], cw[s], cw[s]) for s in range(ns)])
-
-    def step():
-        codec.encode_batch(enc_items)
-        codec.decode_batch(dec_items)
+    enc_sets = [codec.prepare_encode_batch([(n, k, cws[j, s, :k], cws[j, s, k:]) for s in range(ns)])
+                for j in range(sets)]
+    dec_sets = [codec.prepare_decode_batch([(n, k, masks[s], cws[j, s], cws[j, s]) for s in range(ns)])
+                for j in range(sets)]
+    enc_items, dec_items = enc_sets[0], dec_sets[0]
+    for j in range(1, sets):
+        codec.encode_batch(enc_sets[j])
 
     # Parity check on a column sample before timing (the oracle, one column
     # block of two stripes), and recovery of explicitly zeroed erasures.
@@ -738,8 +746,9 @@ def main():
             assert (par == host[k:]).all(), "parity differs from the oracle on sampled columns"
         del ref
 
-    for _ in range(args.warmup):
-        step()
+    for i in range(args.warmup):
+        codec.encode_batch(enc_sets[i % sets])
+        codec.decode_batch(dec_sets[i % sets])
     torch.cuda.synchronize()
 
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
@@ -747,12 +756,13 @@ def main():
     host_ms = np.zeros((args.steps, 2))
     t0 = time.perf_counter()
     for i in range(args.steps):
+        j = (args.warmup + i) % sets
         ev[i][0].record(stream)
         h0 = time.perf_counter()
-        codec.encode_batch(enc_items)
+        codec.encode_batch(enc_sets[j])
         h1 = time.perf_counter()
         ev[i][1].record(stream)
-        codec.decode_batch(dec_items)
+        codec.decode_batch(dec_sets[j])
         h2 = time.perf_counter()
         ev[i][2].record(stream)
         host_ms[i] = ((h1 - h0) * 1e3, (h2 - h1) * 1e3)
@@ -804,28 +814,32 @@ def main():
         extra["schedule"] = sched
 
     # The same step as two reusable plans replayed in a HIP graph: what a
-    # caller that repeats a batch pays once its host planning is done.
-    pe, pd = codec.plan_encode_batch(enc_items), codec.plan_decode_batch(dec_items)
+    # caller that repeats a batch pays once its host planning is done (with
+    # several buffer sets, one graph runs the step on every set in turn).
+    plans = [(codec.plan_encode_batch(enc_sets[j]), codec.plan_decode_batch(dec_sets[j])) for j in range(sets)]
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        pe.launch()
-        pd.launch()
-    for _ in range(args.warmup):
+        for pe, pd in plans:
+            pe.launch()
+            pd.launch()
+    for _ in range(max(1, args.warmup // sets)):
         g.replay()
-    gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    greps = max(2, args.steps // sets)
+    gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(greps)]
     torch.cuda.synchronize()
     for e0, e1 in gev:
         e0.record(stream)
         g.replay()
         e1.record(stream)
     torch.cuda.synchronize()
-    gms = np.array([e0.elapsed_time(e1) for e0, e1 in gev])
+    gms = np.array([e0.elapsed_time(e1) for e0, e1 in gev]) / sets
     extra["graph_ms_per_step_p50"] = round(float(np.percentile(gms, 50)), 4)
     extra["graph_ms_per_step_p99"] = round(float(np.percentile(gms, 99)), 4)
     extra["graph_msg_GBps"] = round(msg_bytes / (float(gms.mean()) * 1e-3) / 1e9, 2)
     del g
-    pe.close()
-    pd.close()
+    for pe, pd in plans:
+        pe.close()
+        pd.close()
 
     if not args.no_per_stripe and ns > 1:
         # the same work as per-stripe launches (one call per stripe and direction)
@@ -865,7 +879,7 @@ def main():
         "dtype": "u16" if r == 16 else "u8",
         "data": "synthetic (seeded splitmix64 bytes, uniform erasure subsets)",
         "config": {"workload": cfg["workload"], "field_bits": r, "n": n, "k": k, "stripes": ns,
-                   "shard_bytes": S, "erasures_per_stripe": e, "parallelism": "single GPU"},
+                   "shard_bytes": S, "erasures_per_stripe": e, "buffer_sets": sets, "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "detail": extra,
