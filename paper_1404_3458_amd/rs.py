@@ -53,9 +53,10 @@ class Plan:
     """An rs_plan: launch() queues the planned batch on a stream (capturable
     in a HIP graph); close() frees it."""
 
-    def __init__(self, codec, handle):
+    def __init__(self, codec, handle, count):
         self._codec = codec          # keeps the context alive
         self._h = handle
+        self.count = count           # stripes of the batch
 
     def launch(self, stream=None):
         return _check(load().rs_plan_launch(self._h, _stream(stream)), "rs_plan_launch")
@@ -63,6 +64,13 @@ class Plan:
     def set_timestamps(self, ts=None):
         """Stamp completion times into ts (int64 device tensor of count + 1,
         None stops); returns the counter's rate in kHz."""
+        if ts is not None:
+            import torch
+
+            if not isinstance(ts, torch.Tensor) or not ts.is_cuda or ts.dtype not in (torch.int64, torch.uint64) \
+                    or not ts.is_contiguous() or ts.numel() < self.count + 1:
+                raise ValueError("timestamps: a contiguous int64 device tensor of at least %d elements"
+                                 % (self.count + 1))
         khz = ctypes.c_int()
         _check(load().rs_plan_set_timestamps(self._h, _ptr(ts), ctypes.byref(khz)), "rs_plan_set_timestamps")
         self._ts = ts
@@ -317,7 +325,7 @@ class Codec:
         b = stripes if isinstance(stripes, PreparedBatch) else self.prepare_encode_batch(stripes)
         h = ctypes.c_void_p()
         _check(load().rs_plan_encode_batch(self._ctx, b.desc_ptr, b.count, ctypes.byref(h)), "rs_plan_encode_batch")
-        pl = Plan(self, h)
+        pl = Plan(self, h, b.count)
         self._plans.add(pl)
         return pl
 
@@ -327,7 +335,7 @@ class Codec:
         h = ctypes.c_void_p()
         _check(load().rs_plan_decode_batch(self._ctx, b.desc_ptr, b.mask_ptr, b.count, ctypes.byref(h)),
                "rs_plan_decode_batch")
-        pl = Plan(self, h)
+        pl = Plan(self, h, b.count)
         self._plans.add(pl)
         return pl
 

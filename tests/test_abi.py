@@ -36,3 +36,15 @@ def test_library_does_not_link_the_oracle():
 
     out = subprocess.run(["nm", "-D", _lib_path()], capture_output=True, text=True).stdout
     assert "orc_" not in out
+
+
+def test_plan_timestamps_argument_checks():
+    # the binding refuses a timestamp array the device could write past
+    # (host memory, too short, wrong type) before any library call
+    import pytest
+    import torch
+
+    pl = rs.Plan(None, ctypes.c_void_p(), 3)
+    for bad in (torch.zeros(4, dtype=torch.int64), torch.zeros(4, dtype=torch.int32), [0, 0, 0, 0]):
+        with pytest.raises(ValueError):
+            pl.set_timestamps(bad)

@@ -323,6 +323,8 @@ def test_plan_timestamps(codec16):
     enc = codec16.plan_encode_batch([(n, k, msgs[i], pars[i]) for i, (n, k, _) in enumerate(specs)])
     ts1 = torch.full((len(specs) + 1,), -1, dtype=torch.int64, device="cuda")
     ts2 = torch.full_like(ts1, -1)
+    with pytest.raises(ValueError):                  # one entry short
+        enc.set_timestamps(ts1[1:])
     khz = enc.set_timestamps(ts1)
     assert khz > 0
     enc.launch()
