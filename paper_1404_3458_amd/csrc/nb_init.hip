@@ -208,12 +208,15 @@ __global__ void k_locator(LocatorArgs a, const uint32_t *__restrict__ p_bits, ui
 }
 
 // Locator for large n' (one stripe, many workgroups): the same two
-// Walsh-Hadamard transforms as k_locator, each split into a pass over
-// groups of 2^T1 consecutive points and a pass over groups of 2^T2 points at
-// stride 2^T1 (the transform's levels commute), on a global array v of n'
-// residues.  Kinds: 0 = indicator of erased points, then levels; 1 = levels,
-// then times FWHT(L_N); 2 = levels; 3 = levels, then the normalisation,
-// exponentials and per-point perm tables as k_locator writes them.
+// Walsh-Hadamard transforms as k_locator on a global array v of n' residues,
+// in three passes over groups of 2^T1 consecutive points (the low levels)
+// or of 2^T2 points at stride 2^T1 (the high levels).  The levels of a
+// Walsh-Hadamard transform commute, so the second transform can take its
+// high levels first, right after the pointwise product.  Kinds: 0 =
+// indicator of erased points, then the first transform's low levels; 1 =
+// its high levels, times FWHT(L_N), the second transform's high levels; 2 =
+// the second transform's low levels, then the normalisation, exponentials
+// and per-point perm tables as k_locator writes them.
 __global__ __launch_bounds__(256) void k_loc_pass(LocPassArgs a, const uint32_t *__restrict__ p_bits,
                                                   uint32_t *__restrict__ p_rowtabs,
                                                   const uint32_t *__restrict__ fwht_L,
@@ -234,28 +237,35 @@ __global__ __launch_bounds__(256) void k_loc_pass(LocPassArgs a, const uint32_t 
         v[j] = a.kind == 0 ? (erased(p) ? 1u : 0u) : a.v[p];
     }
     __syncthreads();
-    for (int len = 1; len < H; len <<= 1) {
-        for (int idx = threadIdx.x; idx < H / 2; idx += blockDim.x) {
-            const int i = ((idx & ~(len - 1)) << 1) | (idx & (len - 1));
-            const uint32_t u = v[i], w = v[i + len];
-            v[i] = addm(u, w, M);
-            v[i + len] = subm(u, w, M);
+    auto levels = [&]() {
+        for (int len = 1; len < H; len <<= 1) {
+            for (int idx = threadIdx.x; idx < H / 2; idx += blockDim.x) {
+                const int i = ((idx & ~(len - 1)) << 1) | (idx & (len - 1));
+                const uint32_t u = v[i], w = v[i + len];
+                v[i] = addm(u, w, M);
+                v[i + len] = subm(u, w, M);
+            }
+            __syncthreads();
         }
+    };
+    levels();
+    if (a.kind == 1) {
+        const uint32_t *FLN = fwht_L + (st.np - 1);
+        for (int j = threadIdx.x; j < H; j += blockDim.x)
+            v[j] = mulm(v[j], FLN[gbase + ((uint32_t)j << lo)], r);
         __syncthreads();
+        levels();
     }
     int lgN = 0;
     while ((1 << lgN) < st.np)
         lgN++;
     const int sh = (r - lgN) % r;
     const int ts = r == 16 ? TAB16 : TAB8;
-    const uint32_t *FLN = fwht_L + (st.np - 1);
     uint32_t *out = p_rowtabs + st.rowtab_off;
     for (int j = threadIdx.x; j < H; j += blockDim.x) {
         const uint32_t p = gbase + ((uint32_t)j << lo);
         uint32_t x = v[j];
-        if (a.kind == 1)
-            x = mulm(x, FLN[p], r);
-        if (a.kind != 3) {
+        if (a.kind != 2) {
             a.v[p] = x;
             continue;
         }

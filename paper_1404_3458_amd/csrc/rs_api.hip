@@ -1015,10 +1015,10 @@ int exec_codec(rs_ctx *ctx, const CodecPlan &cp, uint8_t *dev, hipStream_t strea
             pa.stripe = la.stripes + ll.q;
             pa.v = (uint32_t *)(dev + cp.off_locv) + ll.v_off;
             pa.r = ctx->r;
-            for (int kind = 0; kind < 4; kind++) {
+            for (int kind = 0; kind < 3; kind++) {     // low, high, low (see k_loc_pass)
                 pa.kind = kind;
-                pa.lo = (kind & 1) ? T1 : 0;
-                pa.T = (kind & 1) ? T2 : T1;
+                pa.lo = kind == 1 ? T1 : 0;
+                pa.T = kind == 1 ? T2 : T1;
                 if (dev_err(ctx, loc_pass_launch(pa, kp, ctx->d_FL, ctx->d_exp, 1 << (ll.N - pa.T), stream)))
                     return RS_EDEVICE;
             }

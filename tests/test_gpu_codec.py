@@ -16,7 +16,7 @@ SHAPES16 = [(4, 2), (16, 8), (64, 48), (256, 128), (256, 224), (40, 7), (1024, 5
 # more than 256 points: 8-level pass pipelines (low / high level split 5+4 .. 7+6),
 # shortened mother codes, and codes with several parity blocks
 SHAPES16_WIDE = [(512, 256), (2048, 1024), (8192, 4096), (600, 500), (1000, 300), (2048, 512), (300, 200), (1024, 256),
-                 (700, 200)]
+                 (700, 200), (10000, 6000)]
 SHAPES8 = [(2, 1), (16, 8), (12, 8), (10, 3), (64, 48), (256, 128), (200, 100)]
 
 
