@@ -375,3 +375,35 @@ def test_plan_timestamps(codec16):
         else:
             assert t[1 + i] == 0, (specs[i], t)
     dec.close()
+
+
+@pytest.mark.parametrize("r,n,k", [(16, 16, 1), (16, 256, 1), (16, 300, 1), (16, 1024, 1), (16, 4096, 1),
+                                   (16, 16, 15), (16, 256, 255), (16, 1000, 999), (8, 255, 1), (8, 2, 1),
+                                   (8, 16, 15), (8, 128, 127)])
+def test_degenerate_codes(request, r, n, k):
+    # k = 1: the message polynomial is a constant, so every codeword row
+    # repeats the message row; k = n - 1: one parity row.  Both recover from
+    # every n - k erasures.
+    c = request.getfixturevalue("codec%d" % r)
+    msg, par = _encode_check(c, r, n, k, 131, 7)
+    cw = np.concatenate([msg, par])
+    if k == 1:
+        assert (cw == msg[0][None, :]).all()
+    for e in sorted({1, n - k}):
+        mask = synth.erasure_mask(synth.key(71, r, n, k, e), n, e)
+        rx = cw.copy()
+        rx[mask == 1] = 0x3C
+        d = to_dev(rx)
+        c.decode(n, k, mask, d)
+        got = to_host(d)
+        assert (got == cw).all(), (r, n, k, e, first_diff(got, cw))
+
+
+def test_mother_code_longer_than_the_field(codec8):
+    # (256, 255) over GF(2^8) would need a 512-point mother code (k' = 256,
+    # n' = pow2ceil(k' + 1)): refused before any work, like the oracle does
+    msg = torch.zeros((255, 4), dtype=torch.uint8, device="cuda")
+    par = torch.zeros((1, 4), dtype=torch.uint8, device="cuda")
+    with pytest.raises(rs.RSError) as ei:
+        codec8.encode(256, 255, msg, par)
+    assert ei.value.code == rs.RS_ESHAPE
