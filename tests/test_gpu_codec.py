@@ -407,3 +407,28 @@ def test_mother_code_longer_than_the_field(codec8):
     with pytest.raises(rs.RSError) as ei:
         codec8.encode(256, 255, msg, par)
     assert ei.value.code == rs.RS_ESHAPE
+
+
+def test_empty_batches(codec16):
+    # zero stripes, and stripes that all have empty rows, are no-ops through
+    # the batched calls and the plans (whose stamps then only mark the start)
+    assert codec16.encode_batch([]) == rs.RS_OK
+    assert codec16.decode_batch([]) == rs.RS_OK
+    assert codec16.raw_call("rs_encode_batch", None, 0, None) == rs.RS_OK
+    assert codec16.raw_call("rs_encode_batch", None, -1, None) == rs.RS_EINVAL
+    assert codec16.raw_call("rs_decode_batch", None, None, 1, None) == rs.RS_EINVAL
+    e = torch.zeros((0,), dtype=torch.uint8, device="cuda")
+    empties = [(16, 8, e, e, 0), (1024, 512, e, e, 0)]
+    assert codec16.encode_batch(empties) == rs.RS_OK
+    masks = [np.ones(16, np.uint8) * (np.arange(16) < 8), np.zeros(1024, np.uint8)]
+    assert codec16.decode_batch([(n, k, masks[i], e, e, 0) for i, (n, k, _, _, _) in enumerate(empties)]) == rs.RS_OK
+    for stripes in ([], empties):
+        for pl in (codec16.plan_encode_batch(stripes), codec16.plan_decode_batch(
+                [(n, k, masks[i], e, e, 0) for i, (n, k, _, _, _) in enumerate(stripes)])):
+            ts = torch.full((len(stripes) + 1,), -1, dtype=torch.int64, device="cuda")
+            pl.set_timestamps(ts)
+            pl.launch()
+            torch.cuda.synchronize()
+            t = ts.cpu().numpy()
+            assert t[0] > 0 and (t[1:] == 0).all(), t
+            pl.close()
