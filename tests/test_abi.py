@@ -48,3 +48,32 @@ def test_plan_timestamps_argument_checks():
     for bad in (torch.zeros(4, dtype=torch.int64), torch.zeros(4, dtype=torch.int32), [0, 0, 0, 0]):
         with pytest.raises(ValueError):
             pl.set_timestamps(bad)
+
+
+def _run(code):
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    return subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=120)
+
+
+def test_missing_library_fails_loudly():
+    # no fallback: without the HIP library every codec entry point raises
+    out = _run("from paper_1404_3458_amd import rs\n"
+               "rs.LIB_PATH = '/nonexistent/librs_nb.so'\n"
+               "try:\n"
+               "    rs.Codec(16)\n"
+               "except RuntimeError as e:\n"
+               "    print('raised:', e)\n")
+    assert out.returncode == 0, out.stderr
+    assert "raised: librs_nb.so is not built" in out.stdout
+
+
+def test_package_does_not_import_the_oracle():
+    out = _run("import sys\n"
+               "import paper_1404_3458_amd\n"
+               "from paper_1404_3458_amd import rs, synth, tune, build\n"
+               "print(sorted(m for m in sys.modules if m == 'oracle' or m.startswith('oracle.')))\n")
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "[]"
