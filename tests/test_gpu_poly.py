@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import oracle
-from paper_1404_3458_amd import rs
+from paper_1404_3458_amd import rs, synth
 from gpu_util import first_diff, rand_rows, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
@@ -128,3 +128,33 @@ def test_conversion_round_trip_large(codec16, h):
         pm = oracle.poly_mul(16, oracle.to_monomial(16, col(a, cc)), oracle.to_monomial(16, col(b, cc)))
         assert (col(om, cc)[:2 * hs - 1] == pm).all() and col(om, cc)[-1] == 0
     assert mono.shape == d.shape
+
+
+
+@pytest.mark.parametrize("r", [16, 8])
+def test_product_of_constants_every_element(request, r):
+    # h = 1: the product of two constant polynomials is the field product of
+    # the constants, so a row holding every field element times a row of one
+    # constant checks the point-by-point multiply against the oracle on all
+    # of GF(2^r): for r = 16 the edge factors 0, 1, x, x^15, all ones, the
+    # reduction word and one more, plus a row of random factors; for r = 8
+    # every constant
+    c = request.getfixturevalue("codec%d" % r)
+    q = 1 << r
+    dt = np.uint16 if r == 16 else np.uint8
+    elems = np.arange(q, dtype=dt)
+    if r == 16:
+        rows_b = [np.full(q, v, dtype=dt) for v in (0, 1, 2, 0x8000, 0xFFFF, 0x100B, 0x1234)]
+        rows_b.append(synth.uniform_int(synth.key(95, r), q, 0, q - 1).astype(dt))
+    else:
+        rows_b = [np.full(q, v, dtype=dt) for v in range(q)]
+    a = torch.from_numpy(elems.view(np.uint8).reshape(1, -1).copy()).cuda()
+    out = torch.empty((2, a.shape[1]), dtype=torch.uint8, device="cuda")
+    for brow in rows_b:
+        b = torch.from_numpy(brow.view(np.uint8).reshape(1, -1).copy()).cuda()
+        c.polymul(1, 0, a, b, out)
+        res = out.cpu().numpy()
+        assert (res[1] == 0).all()
+        got = res[0].view(dt)
+        exp = np.array([oracle.mul(r, int(x), int(y)) for x, y in zip(elems, brow)], dtype=dt)
+        assert (got == exp).all(), (r, int(brow[0]), int(np.argmax(got != exp)))
