@@ -1,8 +1,9 @@
 // nb_pass.hip -- multi-pass kernels for transform sizes h > 256 (up to 2^16).
 //
-// A pass applies up to four consecutive levels lo .. lo+T-1 of the transform
-// (Sec. 3.2 / 3.3) to every group of 2^T rows base + j 2^lo (base has no set
-// bit in lo .. lo+T-1), reading the rows from global memory into registers
+// A pass applies up to five (forward) or four (inverse) consecutive levels
+// lo .. lo+T-1 of the transform (Sec. 3.2 / 3.3) to every group of 2^T rows
+// base + j 2^lo (base has no set bit in lo .. lo+T-1), reading the rows from
+// global memory into registers
 // and writing them back.  The group and the 256-column tile are uniform per
 // workgroup, so the skew factors are wave-uniform as in the fused kernels.
 // Rows may be multiplied by B_p before or after the levels (Sec. 4.2).
@@ -104,6 +105,12 @@ static hipError_t pass_T(int T, const PassArgs &a, const KPtrs &k, uint32_t nblo
     case 2: hipLaunchKernelGGL((k_pass<R, 2, INV, GEN_L, LD>), dim3(nblocks), dim3(64), 0, s, a, k.tw, k.B); break;
     case 3: hipLaunchKernelGGL((k_pass<R, 3, INV, GEN_L, LD>), dim3(nblocks), dim3(64), 0, s, a, k.tw, k.B); break;
     case 4: hipLaunchKernelGGL((k_pass<R, 4, INV, GEN_L, LD>), dim3(nblocks), dim3(64), 0, s, a, k.tw, k.B); break;
+    case 5:                     // forward passes only (an inverse one needs too many registers)
+        if constexpr (!INV)
+            hipLaunchKernelGGL((k_pass<R, 5, INV, GEN_L, LD>), dim3(nblocks), dim3(64), 0, s, a, k.tw, k.B);
+        else
+            return hipErrorInvalidValue;
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -53,6 +53,11 @@ namespace {
 // MODE_ENC2: encode of a code with one parity block (n' = 2 k')
 enum { MODE_FFT = 0, MODE_IFFT = 1, MODE_DERIV = 2, MODE_ENC = 3, MODE_DEC = 4, MODE_ENC2 = 5 };
 constexpr int FUSED_MAX_L = 8;      // fused single-launch kernels cover h <= 256
+// Levels per plain transform pass (k_pass): a forward pass of 5 levels (32
+// rows of a lane in registers, about 100 VGPRs) beats a 4-level and a
+// 1-level pass; an inverse one needs about 175 VGPRs (two waves per SIMD)
+// and loses to them.
+constexpr int PASS_MAX_T_FWD = 5, PASS_MAX_T_INV = 4;
 constexpr int LOC_ONE_WG_MAX = 4096; // larger mother codes use the multi-workgroup locator
 // pass kinds of nb_wide.hip
 enum { W_E1 = 0, W_E2 = 1, W_E2F = 2, W_E3 = 3, W_D1 = 4, W_D2 = 5, W_D3 = 6, W_D4 = 7, W_D5 = 8, W_DPM = 9 };
@@ -373,14 +378,24 @@ int run_passes(rs_ctx *ctx, hipStream_t s, bool inv, bool gen_l, int L, uint32_t
                int src_rows, uint8_t *work, uint8_t *final_dst, int dst_lo, int dst_hi, uint64_t rb,
                int ncols, bool aligned, bool pre_B_first, bool post_B_last)
 {
+    // the L levels in as few passes as possible, as even as possible (e.g.
+    // forward 13 = 5 + 4 + 4): every pass reads and writes all h rows, so the
+    // pass count sets the traffic
     std::vector<std::pair<int, int>> chunks;   // (lo, T)
+    const int maxT = inv ? PASS_MAX_T_INV : PASS_MAX_T_FWD;
+    const int np_ = (L + maxT - 1) / maxT;
+    std::vector<int> Ts;
+    for (int i = 0; i < np_; i++)
+        Ts.push_back(L / np_ + (i < L % np_ ? 1 : 0));
     if (inv) {
-        for (int lo = 0; lo < L; lo += 4)
-            chunks.push_back({lo, std::min(4, L - lo)});
+        int lo = 0;
+        for (int T : Ts) {
+            chunks.push_back({lo, T});
+            lo += T;
+        }
     } else {
         int top = L;
-        while (top > 0) {
-            const int T = std::min(4, top);
+        for (int T : Ts) {
             chunks.push_back({top - T, T});
             top -= T;
         }
