@@ -1633,22 +1633,34 @@ __attribute__((visibility("default"))) int nb_polymul(rs_ctx *ctx, int h, uint32
     uint8_t *Z;
     if ((rc = big_scratch(sc, out_bytes, &Z)))
         return rc;
-    const int H = 2 * h, ncols = (int)(rb / sym_bytes(ctx));
-    // A and B padded with zeros to 2h coefficients
-    PolyArgs pa = poly_args(a, nullptr, out, rb, ncols);
-    pa.rows = H;
-    pa.src_rows = h;
-    if ((rc = poly_run(ctx, stream, PK_PAD, pa, vec_aligned(ctx, a, out, rb), (uint32_t)H, nullptr, nullptr)))
-        return rc;
-    pa.src = (const uint8_t *)b;
-    pa.dst = Z;
-    if ((rc = poly_run(ctx, stream, PK_PAD, pa, vec_aligned(ctx, b, Z, rb), (uint32_t)H, nullptr, nullptr)))
-        return rc;
-    // both transformed at 2h points, multiplied point by point, transformed back
-    if ((rc = xform_locked(ctx, sc, MODE_FFT, H, l, (uint8_t *)out, rb, stream)))
-        return rc;
-    if ((rc = xform_locked(ctx, sc, MODE_FFT, H, l, Z, rb, stream)))
-        return rc;
+    const int H = 2 * h, LH = ilog2(H), ncols = (int)(rb / sym_bytes(ctx));
+    // A and B padded with zeros to 2h coefficients and transformed at 2h
+    // points (into out and Z), multiplied point by point, transformed back
+    if (LH > FUSED_MAX_L) {
+        // pass pipelines: the first forward pass reads the h rows of the
+        // operand and zeros above them, so no padding copy is needed
+        const bool gen_l = (l & (uint32_t)(H - 1)) != 0;
+        if ((rc = run_passes(ctx, stream, false, gen_l, LH, l, (const uint8_t *)a, h, (uint8_t *)out, nullptr, 0, 0,
+                             rb, ncols, vec_aligned(ctx, a, out, rb), false, false)))
+            return rc;
+        if ((rc = run_passes(ctx, stream, false, gen_l, LH, l, (const uint8_t *)b, h, Z, nullptr, 0, 0, rb, ncols,
+                             vec_aligned(ctx, b, Z, rb), false, false)))
+            return rc;
+    } else {
+        PolyArgs pa = poly_args(a, nullptr, out, rb, ncols);
+        pa.rows = H;
+        pa.src_rows = h;
+        if ((rc = poly_run(ctx, stream, PK_PAD, pa, vec_aligned(ctx, a, out, rb), (uint32_t)H, nullptr, nullptr)))
+            return rc;
+        pa.src = (const uint8_t *)b;
+        pa.dst = Z;
+        if ((rc = poly_run(ctx, stream, PK_PAD, pa, vec_aligned(ctx, b, Z, rb), (uint32_t)H, nullptr, nullptr)))
+            return rc;
+        if ((rc = xform_locked(ctx, sc, MODE_FFT, H, l, (uint8_t *)out, rb, stream)))
+            return rc;
+        if ((rc = xform_locked(ctx, sc, MODE_FFT, H, l, Z, rb, stream)))
+            return rc;
+    }
     PolyArgs pm = poly_args(nullptr, Z, out, rb, ncols);
     pm.rows = H;
     if ((rc = poly_run(ctx, stream, PK_MUL, pm, vec_aligned(ctx, out, Z, rb), (uint32_t)H, ctx->d_log, ctx->d_exp)))
