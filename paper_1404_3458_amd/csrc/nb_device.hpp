@@ -302,6 +302,51 @@ __device__ __forceinline__ void pin(const uint32_t *v)
         asm volatile("" ::"v"(v[0]));
 }
 
+// Each 16-bit half of v replaced by all ones if its top bit is set, else 0
+// (a packed arithmetic shift by 15; op_sel_hi:[0,1] makes the high half also
+// take its shift count from the low half of the inline constant.  Written
+// out so that the compiler keeps the masks as data rather than turning the
+// ANDs below into selects).
+__device__ __forceinline__ uint32_t top_mask16x2(uint32_t v)
+{
+    uint32_t r;
+    asm("v_pk_ashrrev_i16 %0, 15, %1 op_sel_hi:[0,1]" : "=v"(r) : "v"(v));
+    return r;
+}
+
+// Products of the GF(2^16) symbols in the two 16-bit halves of a and b:
+// shift and add over the bits of b, highest first, reducing by
+// x^16 = x^12 + x^3 + x + 1 after every shift (about 6 lane-ops per bit for
+// both halves, no memory traffic; both factors vary, so the per-constant
+// lookup tables of the transforms do not apply).
+// U: unroll factor of the 16 steps (a caller that multiplies many rows
+// inside an unrolled loop keeps the steps rolled, or that loop would be left
+// rolled and its register arrays moved to scratch memory).
+template <int U = 16>
+__device__ __forceinline__ uint32_t gf16_mul2(uint32_t a, uint32_t b)
+{
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    uint32_t acc = 0u, bv = b;
+#pragma unroll U
+    for (int i = 0; i < 16; i++) {
+        const uint32_t carry = top_mask16x2(acc);
+        acc = __builtin_bit_cast(uint32_t, (u16x2)(__builtin_bit_cast(u16x2, acc) << 1)) ^ (carry & 0x100B100Bu);
+        acc ^= a & top_mask16x2(bv);
+        bv = __builtin_bit_cast(uint32_t, (u16x2)(__builtin_bit_cast(u16x2, bv) << 1));
+    }
+    return acc;
+}
+
+// x (4 GF(2^16) symbols, byte-sliced) <- x times y symbol by symbol.
+template <int U = 16>
+__device__ __forceinline__ void mul_symbols16(uint32_t *x, const uint32_t *y)
+{
+    uint32_t xw0, xw1, yw0, yw1;
+    Ops<16>::pack(x, xw0, xw1);
+    Ops<16>::pack(y, yw0, yw1);
+    Ops<16>::unpack(gf16_mul2<U>(xw0, yw0), gf16_mul2<U>(xw1, yw1), x);
+}
+
 // Completion stamp of a workgroup: when an object of this type goes out of
 // scope (every return of a kernel), the first lane of each wave raises
 // slots[blockIdx.x] to the device's real-time counter with a vector atomic,

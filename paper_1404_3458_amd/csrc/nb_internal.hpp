@@ -68,6 +68,7 @@ struct PassArgs {
     int32_t nct;              // column tiles (of 256 columns) per group
     int32_t pre_B;            // multiply rows by B_p before the levels
     int32_t post_B;           // multiply rows by B_p after the levels
+    const uint8_t *mul;       // GF(2^16): output row p times row p of mul, symbol by symbol (null: none)
 };
 
 // Polynomial operations of Sec. 5 (nb_poly.hip): padding, point-by-point

@@ -6,7 +6,9 @@
 // global memory into registers
 // and writing them back.  The group and the 256-column tile are uniform per
 // workgroup, so the skew factors are wave-uniform as in the fused kernels.
-// Rows may be multiplied by B_p before or after the levels (Sec. 4.2).
+// Rows may be multiplied by B_p before or after the levels (Sec. 4.2), and
+// (GF(2^16)) by the rows of another array after them, symbol by symbol (the
+// point-by-point product of Sec. 5).
 #include "nb_xform.hpp"
 
 namespace nb {
@@ -53,6 +55,13 @@ __global__ __launch_bounds__(64) void k_pass(PassArgs a, const uint32_t *__restr
         const uint32_t p = fresh(base + ((uint32_t)j << a.lo));
         if (a.post_B)
             scale<R>(x[j], row_tab<R>(p_B, (int)p));
+        if constexpr (R == 16) {
+            if (a.mul) {
+                uint32_t m[NW];
+                load_chunk<R, LD>(prow(a.mul, p, rb), ln.off, ln.act, ln.nsym, m);
+                mul_symbols16<4>(x[j], m);
+            }
+        }
         if ((int)p >= a.dst_lo && (int)p < a.dst_hi)
             store_chunk<R, LD>(prow(a.dst, p - (uint32_t)a.dst_lo, rb), ln.off, ln.act, ln.nsym, x[j]);
     }

@@ -54,37 +54,6 @@ __device__ __forceinline__ uint32_t mul_log(uint32_t x, uint32_t y, const uint32
     return ex[e];
 }
 
-// Each 16-bit half of v replaced by all ones if its top bit is set, else 0
-// (a packed arithmetic shift by 15; op_sel_hi:[0,1] makes the high half also
-// take its shift count from the low half of the inline constant.  Written
-// out so that the compiler keeps the masks as data rather than turning the
-// ANDs below into selects).
-__device__ __forceinline__ uint32_t top_mask16x2(uint32_t v)
-{
-    uint32_t r;
-    asm("v_pk_ashrrev_i16 %0, 15, %1 op_sel_hi:[0,1]" : "=v"(r) : "v"(v));
-    return r;
-}
-
-// Products of the GF(2^16) symbols in the two 16-bit halves of a and b:
-// shift and add over the bits of b, highest first, reducing by
-// x^16 = x^12 + x^3 + x + 1 after every shift (about 6 lane-ops per bit for
-// both halves, no memory traffic; both factors vary, so the per-constant
-// lookup tables of the transforms do not apply).
-__device__ __forceinline__ uint32_t gf16_mul2(uint32_t a, uint32_t b)
-{
-    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-    uint32_t acc = 0u, bv = b;
-#pragma unroll
-    for (int i = 0; i < 16; i++) {
-        const uint32_t carry = top_mask16x2(acc);
-        acc = __builtin_bit_cast(uint32_t, (u16x2)(__builtin_bit_cast(u16x2, acc) << 1)) ^ (carry & 0x100B100Bu);
-        acc ^= a & top_mask16x2(bv);
-        bv = __builtin_bit_cast(uint32_t, (u16x2)(__builtin_bit_cast(u16x2, bv) << 1));
-    }
-    return acc;
-}
-
 // dst[p] <- dst[p] * src2[p] symbol by symbol, rows [0, rows).
 template <int R, int LD>
 __global__ __launch_bounds__(64) void k_poly_mul(PolyArgs a, const uint32_t *__restrict__ lg,
@@ -99,13 +68,7 @@ __global__ __launch_bounds__(64) void k_poly_mul(PolyArgs a, const uint32_t *__r
     load_chunk<R, LD>(qrow(a.dst, p, a.row_bytes), ln.off, ln.act, ln.nsym, x);
     load_chunk<R, LD>(qrow(a.src2, p, a.row_bytes), ln.off, ln.act, ln.nsym, y);
     if (R == 16) {
-        uint32_t xw[2], yw[2], o[2];
-        Ops<16>::pack(x, xw[0], xw[1]);
-        Ops<16>::pack(y, yw[0], yw[1]);
-#pragma unroll
-        for (int w = 0; w < 2; w++)
-            o[w] = gf16_mul2(xw[w], yw[w]);
-        Ops<16>::unpack(o[0], o[1], x);
+        mul_symbols16(x, y);
     } else {
         uint32_t o = 0;
 #pragma unroll

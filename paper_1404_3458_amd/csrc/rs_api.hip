@@ -376,7 +376,7 @@ int validate_stripe(rs_ctx *ctx, const rs_stripe_desc &d, bool decode, const uin
 // rows [dst_lo, dst_hi) to `final_dst` when it is given.
 int run_passes(rs_ctx *ctx, hipStream_t s, bool inv, bool gen_l, int L, uint32_t l, const uint8_t *src,
                int src_rows, uint8_t *work, uint8_t *final_dst, int dst_lo, int dst_hi, uint64_t rb,
-               int ncols, bool aligned, bool pre_B_first, bool post_B_last)
+               int ncols, bool aligned, bool pre_B_first, bool post_B_last, const uint8_t *mul_last = nullptr)
 {
     // the L levels in as few passes as possible, as even as possible (e.g.
     // forward 13 = 5 + 4 + 4): every pass reads and writes all h rows, so the
@@ -427,6 +427,7 @@ int run_passes(rs_ctx *ctx, hipStream_t s, bool inv, bool gen_l, int L, uint32_t
             a.l = l;
             a.pre_B = first && pre_B_first;
             a.post_B = last && post_B_last;
+            a.mul = last ? mul_last : nullptr;
             a.nct = cp.ntiles;
             const int T = chunks[c].second;
             const uint32_t nblocks = (uint32_t)((h >> T) * cp.ntiles);
@@ -1643,8 +1644,10 @@ __attribute__((visibility("default"))) int nb_polymul(rs_ctx *ctx, int h, uint32
         if ((rc = run_passes(ctx, stream, false, gen_l, LH, l, (const uint8_t *)a, h, (uint8_t *)out, nullptr, 0, 0,
                              rb, ncols, vec_aligned(ctx, a, out, rb), false, false)))
             return rc;
-        if ((rc = run_passes(ctx, stream, false, gen_l, LH, l, (const uint8_t *)b, h, Z, nullptr, 0, 0, rb, ncols,
-                             vec_aligned(ctx, b, Z, rb), false, false)))
+        // B's last pass multiplies its values by A's, point by point, into out
+        if ((rc = run_passes(ctx, stream, false, gen_l, LH, l, (const uint8_t *)b, h, Z, (uint8_t *)out, 0, H, rb,
+                             ncols, vec_aligned(ctx, b, Z, rb) && vec_aligned(ctx, out, out, rb), false, false,
+                             (const uint8_t *)out)))
             return rc;
     } else {
         PolyArgs pa = poly_args(a, nullptr, out, rb, ncols);
@@ -1660,11 +1663,12 @@ __attribute__((visibility("default"))) int nb_polymul(rs_ctx *ctx, int h, uint32
             return rc;
         if ((rc = xform_locked(ctx, sc, MODE_FFT, H, l, Z, rb, stream)))
             return rc;
+        PolyArgs pm = poly_args(nullptr, Z, out, rb, ncols);
+        pm.rows = H;
+        if ((rc = poly_run(ctx, stream, PK_MUL, pm, vec_aligned(ctx, out, Z, rb), (uint32_t)H, ctx->d_log,
+                           ctx->d_exp)))
+            return rc;
     }
-    PolyArgs pm = poly_args(nullptr, Z, out, rb, ncols);
-    pm.rows = H;
-    if ((rc = poly_run(ctx, stream, PK_MUL, pm, vec_aligned(ctx, out, Z, rb), (uint32_t)H, ctx->d_log, ctx->d_exp)))
-        return rc;
     return xform_locked(ctx, sc, MODE_IFFT, H, l, (uint8_t *)out, rb, stream);
 }
 
