@@ -1,7 +1,9 @@
 // nb_poly.hip -- polynomial operations in the novel basis beyond the
 // transforms (Sec. 5 and its Table 1): the zero padding and the
-// point-by-point product of the product algorithm, the degree, and the
-// conversion between the novel basis and the monomial basis.
+// point-by-point product of the product algorithm (for products over at most
+// 256 points; above, the transform passes read the unpadded operands and
+// multiply in their last pass), the degree, and the conversion between the
+// novel basis and the monomial basis.
 //
 // Every kernel works on column tiles of 256 columns (64 lanes x 4 columns)
 // of row-major stripes, like the transform kernels; a workgroup of one wave
@@ -43,7 +45,8 @@ __global__ __launch_bounds__(64) void k_poly_pad(PolyArgs a)
     store_chunk<R, LD>(qrow(a.dst, p, a.row_bytes), ln.off, ln.act, ln.nsym, x);
 }
 
-// Product of two field elements through the logarithm tables (alpha = 2).
+// Product of two field elements through the logarithm tables (alpha = 2);
+// GF(2^8) only (GF(2^16) multiplies by shift and add, gf16_mul2).
 __device__ __forceinline__ uint32_t mul_log(uint32_t x, uint32_t y, const uint32_t *__restrict__ lg,
                                             const uint32_t *__restrict__ ex, uint32_t M)
 {
