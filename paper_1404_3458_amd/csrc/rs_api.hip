@@ -295,20 +295,33 @@ struct ColPart {
 
 int ntiles_of_chunks(long chunks) { return (int)((chunks + 63) / 64); }
 
-std::vector<ColPart> col_parts(bool aligned, int ncols)
+// The column parts of a row range: whole chunks of 4 columns read with vector
+// loads plus a ragged tail read per symbol, or one per-symbol part when the
+// rows are not aligned; at most two, held inline (this runs once per stripe
+// of every call, so it allocates nothing).
+struct ColParts {
+    ColPart p[2];
+    int n = 0;
+    const ColPart *begin() const { return p; }
+    const ColPart *end() const { return p + n; }
+    size_t size() const { return (size_t)n; }
+    const ColPart &operator[](size_t i) const { return p[i]; }
+};
+
+ColParts col_parts(bool aligned, int ncols)
 {
-    std::vector<ColPart> v;
+    ColParts v;
     if (ncols <= 0)
         return v;
     if (!aligned) {
-        v.push_back({LD_SYM, 0, ntiles_of_chunks((ncols + 3) / 4)});
+        v.p[v.n++] = {LD_SYM, 0, ntiles_of_chunks((ncols + 3) / 4)};
         return v;
     }
     const int full = ncols / 4;
     if (full)
-        v.push_back({LD_VEC, 0, ntiles_of_chunks(full)});
+        v.p[v.n++] = {LD_VEC, 0, ntiles_of_chunks(full)};
     if (ncols % 4)
-        v.push_back({LD_SYM, 4 * full, 1});
+        v.p[v.n++] = {LD_SYM, 4 * full, 1};
     return v;
 }
 
@@ -403,7 +416,7 @@ int run_passes(rs_ctx *ctx, hipStream_t s, bool inv, bool gen_l, int L, uint32_t
     if (chunks.empty())
         chunks.push_back({0, 0});
     const int h = 1 << L;
-    const std::vector<ColPart> parts = col_parts(aligned, ncols);
+    const ColParts parts = col_parts(aligned, ncols);
     for (size_t c = 0; c < chunks.size(); c++) {
         const bool first = c == 0, last = c + 1 == chunks.size();
         for (const ColPart &cp : parts) {
@@ -546,6 +559,7 @@ int launch_key(const Plan &p, int ld)
 struct Entry {
     int plan;
     ColPart cp;
+    int key;           // launch_key of the pair, computed once
 };
 
 // ------------------------------------------------------------------ 8-level pass pipelines
@@ -846,18 +860,16 @@ int build_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, 
         if (runs_wide(p))
             continue;
         for (const ColPart &c : col_parts(p.aligned, p.ds.ncols))
-            ents.push_back({act[q], c});
+            ents.push_back({act[q], c, launch_key(p, c.ld)});
     }
-    std::stable_sort(ents.begin(), ents.end(), [&](const Entry &x, const Entry &y) {
-        return launch_key(plans[x.plan], x.cp.ld) < launch_key(plans[y.plan], y.cp.ld);
-    });
+    std::stable_sort(ents.begin(), ents.end(), [](const Entry &x, const Entry &y) { return x.key < y.key; });
     const int ne = (int)ents.size();
     std::vector<DevStripe> eds((size_t)ne);
     for (int j = 0; j < ne;) {
         const Plan &pj = plans[ents[j].plan];
-        const int key = launch_key(pj, ents[j].cp.ld);
+        const int key = ents[j].key;
         int e = j, tiles = 0;
-        while (e < ne && launch_key(plans[ents[e].plan], ents[e].cp.ld) == key) {
+        while (e < ne && ents[e].key == key) {
             eds[e] = plans[ents[e].plan].ds;
             eds[e].col0 = ents[e].cp.col0;
             eds[e].tile0 = tiles;
@@ -1120,7 +1132,7 @@ int xform_locked(rs_ctx *ctx, Scratch *sc, int mode, int h, uint32_t l, uint8_t 
     if (mode == MODE_DERIV && L == 0)
         return fill_zero(ctx, stream, d, rb);
     if (L <= FUSED_MAX_L) {
-        const std::vector<ColPart> parts = col_parts(aligned, ncols);
+        const ColParts parts = col_parts(aligned, ncols);
         std::vector<DevStripe> st(parts.size());
         for (size_t i = 0; i < parts.size(); i++) {
             std::memset(&st[i], 0, sizeof(DevStripe));
