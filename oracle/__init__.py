@@ -371,7 +371,7 @@ def locator_direct(r, erased, basis=None):
     return out
 
 
-# ---------------------------------------------------------------- polynomial operations (Sec. 5)
+# ---------------------------------------------------------------- polynomial operations (Sec. 6.1, Table 1)
 def poly_mul(r, a, b):
     """Monomial-basis product (schoolbook)."""
     a, b = _u32(a), _u32(b)
@@ -395,7 +395,7 @@ def degree(d):
 
 
 def polymul(r, a, b, l=0, basis=None):
-    """Sec. 5 product of two novel-basis polynomials of h coefficients: 2h coefficients."""
+    """Sec. 6.1 (Table 1) product of two novel-basis polynomials of h coefficients: 2h coefficients."""
     bs = _basis(basis)
     a, b = _u32(a), _u32(b)
     assert len(a) == len(b)

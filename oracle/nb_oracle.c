@@ -889,7 +889,7 @@ ORC_EXPORT int orc_decode_lagrange(int r, const uint32_t *basis, int n, int k, c
 }
 
 /* ------------------------------------------------------------------ */
-/* Polynomial operations in the novel basis (Sec. 5, Table 1).         */
+/* Polynomial operations in the novel basis (Sec. 6.1, Table 1).       */
 /* ------------------------------------------------------------------ */
 
 /* Product in the monomial basis, schoolbook: out has la + lb - 1 entries. */
@@ -982,7 +982,7 @@ ORC_EXPORT int orc_from_monomial(int r, const uint32_t *basis, int h, const uint
     return 0;
 }
 
-/* Degree of [D_h](x) (Sec. 5): the largest j with d_j != 0, since
+/* Degree of [D_h](x) (Sec. 6.1, Table 1): the largest j with d_j != 0, since
  * deg X_j = j; -1 for the zero polynomial. */
 ORC_EXPORT int orc_degree(int h, const uint32_t *d)
 {
@@ -994,7 +994,7 @@ ORC_EXPORT int orc_degree(int h, const uint32_t *d)
     return -1;
 }
 
-/* Sec. 5, product of [A_h] and [B_h]: both padded with zeros to 2h
+/* Sec. 6.1 (Table 1), product of [A_h] and [B_h]: both padded with zeros to 2h
  * coefficients, transformed by Psi_2h^l (Sec. 3.2), multiplied point by
  * point, and transformed back by the inverse (Sec. 3.3).  out: 2h entries,
  * the novel-basis coefficients of the product (the last one is zero). */

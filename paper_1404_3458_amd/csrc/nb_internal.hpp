@@ -71,7 +71,7 @@ struct PassArgs {
     const uint8_t *mul;       // GF(2^16): output row p times row p of mul, symbol by symbol (null: none)
 };
 
-// Polynomial operations of Sec. 5 (nb_poly.hip): padding, point-by-point
+// Polynomial operations of Sec. 6.1, Table 1 (nb_poly.hip): padding, point-by-point
 // product, degree and basis conversion; each kernel reads the fields it needs.
 struct PolyArgs {
     const uint8_t *src;       // rows read

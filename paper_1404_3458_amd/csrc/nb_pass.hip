@@ -8,7 +8,7 @@
 // workgroup, so the skew factors are wave-uniform as in the fused kernels.
 // Rows may be multiplied by B_p before or after the levels (Sec. 4.2), and
 // (GF(2^16)) by the rows of another array after them, symbol by symbol (the
-// point-by-point product of Sec. 5).
+// point-by-point product of Sec. 6.1, Table 1).
 #include "nb_xform.hpp"
 
 namespace nb {

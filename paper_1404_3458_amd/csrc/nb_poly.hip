@@ -1,5 +1,5 @@
 // nb_poly.hip -- polynomial operations in the novel basis beyond the
-// transforms (Sec. 5 and its Table 1): the zero padding and the
+// transforms (Sec. 6.1 and its Table 1): the zero padding and the
 // point-by-point product of the product algorithm (for products over at most
 // 256 points; above, the transform passes read the unpadded operands and
 // multiply in their last pass), the degree, and the conversion between the
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(64) void k_poly_mul(PolyArgs a, const uint32_t *__r
 }
 
 // deg[c] = the last of the rows [0, rows) whose symbol c is nonzero, -1 if
-// none (deg X_j = j, Sec. 5).  One workgroup of four waves per column tile:
+// none (deg X_j = j, Sec. 6.1).  One workgroup of four waves per column tile:
 // wave w scans the rows w, w + 4, ...; the four results meet in LDS.
 template <int R, int LD>
 __global__ __launch_bounds__(256) void k_poly_degree(PolyArgs a)

@@ -1,4 +1,4 @@
-"""GPU parity of the polynomial operations of Sec. 5 through the C ABI: the
+"""GPU parity of the polynomial operations of Sec. 6.1 (Table 1) through the C ABI: the
 product by 2h-point transforms (nb_polymul), the degree (nb_degree) and the
 conversion between the novel and the monomial basis (nb_to_monomial,
 nb_from_monomial), bit for bit against the oracle on aligned and unaligned

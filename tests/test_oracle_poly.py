@@ -1,4 +1,4 @@
-"""Pins of the oracle's polynomial operations in the novel basis (Sec. 5:
+"""Pins of the oracle's polynomial operations in the novel basis (Sec. 6.1, Table 1:
 the product through 2h-point transforms, the degree, and the conversion
 between the novel and the monomial basis), against facts the mathematics
 fixes independently of the oracle's own formulas: values at field points by
