@@ -97,7 +97,7 @@ int nb_ifft(rs_ctx *ctx, int h, uint32_t l, void *data, size_t row_bytes, void *
  * [D_h](x) by those of [D_h]'(x), in place; h as for nb_fft. */
 int nb_derivative(rs_ctx *ctx, int h, void *data, size_t row_bytes, void *stream);
 
-/* Product in the novel basis (Sec. 5): for each column, out holds the 2h
+/* Product in the novel basis (Sec. 6.1, Table 1): for each column, out holds the 2h
  * coefficients of [A_h](x) [B_h](x), computed as the inverse transform
  * Psi_2h^l of the point-by-point product of the transforms Psi_2h^l of A and
  * B padded with h zero coefficients (the last output coefficient is zero).
@@ -108,7 +108,7 @@ int nb_derivative(rs_ctx *ctx, int h, void *data, size_t row_bytes, void *stream
 int nb_polymul(rs_ctx *ctx, int h, uint32_t l, const void *a, const void *b, void *out, size_t row_bytes,
                void *stream);
 
-/* Degree (Sec. 5): deg[c] (device, one int32 per column) = the largest j < h
+/* Degree (Sec. 6.1, Table 1): deg[c] (device, one int32 per column) = the largest j < h
  * whose coefficient in column c is nonzero (deg X_j = j), or -1.
  * 1 <= h <= 2^r (any h). */
 int nb_degree(rs_ctx *ctx, int h, const void *data, size_t row_bytes, int32_t *deg, void *stream);
@@ -184,7 +184,9 @@ void rs_plan_free(rs_plan *plan);
  * Completion times are CLOCK_MONOTONIC nanoseconds taken when the batch's
  * event is observed complete.  Buffers must stay valid until the request's
  * completion is returned; requests whose buffers overlap are the caller's
- * race.  A request larger than the budget is admitted alone. */
+ * race.  A request larger than the budget is admitted alone, and nothing
+ * else is admitted while it is in flight.  The server's streams do not
+ * follow any stream of the caller's unless a request names one (`after`). */
 typedef struct rs_server rs_server;
 enum { RS_OP_ENCODE = 0, RS_OP_DECODE = 1 };
 typedef struct rs_request {
@@ -192,15 +194,39 @@ typedef struct rs_request {
     rs_stripe_desc desc;    /* as in the batched calls */
     const uint8_t *mask;    /* decode: n bytes, host, copied by rs_server_submit */
     uint64_t tag;           /* returned with the completion */
+    void *after;            /* a hipStream_t or NULL: the request's kernels start only
+                               after the work queued on that stream before the
+                               submit (the producer of its input) has finished */
 } rs_request;
 typedef struct rs_completion {
     uint64_t tag;
-    int32_t status;         /* RS_OK or the error of the batch */
+    int32_t status;         /* RS_OK, or the error of this request's batched call
+                               (a failed batch is retried request by request, so
+                               a request reports its own error) */
     int64_t t_done_ns;
 } rs_completion;
 int rs_server_create(rs_ctx *ctx, size_t budget_bytes, int max_batch, int nstreams, rs_server **out);
-/* Validates (as the single calls do) and queues; never blocks on the device. */
+/* Runs the checks the batched calls run on a descriptor (mother code
+ * n' <= 2^r, 1 <= k < n, row_bytes a multiple of r/8, non-null rows, at most
+ * n - k erasures) and returns their error without queueing anything, then
+ * queues; never blocks on the device.  RS_EDEVICE if the `after` stream
+ * cannot be marked. */
 int rs_server_submit(rs_server *srv, const rs_request *req);
+/* Admission record of a server, for checking the budget: bytes are the
+ * in-flight bytes of the admission rule above. */
+typedef struct rs_server_stats {
+    uint64_t budget;              /* the budget given to rs_server_create */
+    uint64_t inflight_bytes;      /* now */
+    uint64_t peak_bytes;          /* largest in-flight total after any admission */
+    uint64_t peak_shared_bytes;   /* the same, over admissions under the budget rule
+                                     (every one but a lone oversized request) */
+    uint64_t oversize_admitted;   /* requests admitted alone above the budget */
+    uint64_t largest_oversize;    /* bytes of the largest of them (0 if none) */
+    uint64_t admitted;            /* requests admitted */
+    uint64_t batches;             /* batched calls queued */
+    uint64_t retried;             /* requests rerun alone after their batch failed */
+} rs_server_stats;
+int rs_server_get_stats(rs_server *srv, rs_server_stats *out);
 /* Returns up to `max` completions (count >= 0), waiting up to timeout_ms
  * (0: do not wait, < 0: until at least one) when none is ready. */
 int rs_server_poll(rs_server *srv, rs_completion *out, int max, int timeout_ms);

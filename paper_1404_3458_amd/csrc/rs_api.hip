@@ -1230,7 +1230,7 @@ bool basis_independent(int r, const uint32_t *b)
     return rank == r;
 }
 
-// ------------------------------------------------------------------ polynomial operations (Sec. 5)
+// ------------------------------------------------------------------ polynomial operations (Sec. 6.1, Table 1)
 
 // Launch one nb_poly kernel over every column part of a call; per_tile:
 // workgroups per column tile (rows of the operation, or 1 for the degree).
@@ -1400,6 +1400,20 @@ bool apply_schedule_env(rs_ctx *ctx)
 }
 
 }  // namespace
+
+namespace nb {
+
+// The checks a batched call makes on one descriptor, for callers that must
+// refuse a bad stripe before it joins a batch (the serving loop).
+int check_stripe(rs_ctx *ctx, const rs_stripe_desc &d, bool decode, const uint8_t *mask)
+{
+    if (!ctx)
+        return RS_EINVAL;
+    Plan pl;
+    return validate_stripe(ctx, d, decode, mask, pl);
+}
+
+}  // namespace nb
 
 // ------------------------------------------------------------------ C ABI
 

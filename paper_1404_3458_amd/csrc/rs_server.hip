@@ -7,7 +7,8 @@
 // has completed, stamping their requests' completion time and releasing
 // their bytes, and (2) while a stream has no batch in flight, admits queued
 // requests in arrival order while they fit the budget and launches them as
-// one encode batch and one decode batch on that stream.
+// one encode batch and one decode batch on that stream (after waiting, on
+// that stream, for the events of the producer streams the requests name).
 #include "rs.h"
 
 #include <hip/hip_runtime.h>
@@ -42,14 +43,15 @@ struct Req {
     rs_request r;
     std::vector<uint8_t> mask;
     size_t bytes;
+    hipEvent_t ready;         // recorded on the request's producer stream, or null
 };
 
 struct Batch {
     int stream;
     hipEvent_t ev;
     std::vector<Req> reqs;
+    std::vector<int> status;  // per request
     size_t bytes;
-    int status;
 };
 
 // Device bytes a request keeps in flight: its codeword rows, the scratch of
@@ -74,6 +76,10 @@ size_t request_bytes(const rs_request &q)
 
 }  // namespace
 
+namespace nb {
+int check_stripe(rs_ctx *ctx, const rs_stripe_desc &d, bool decode, const uint8_t *mask);
+}
+
 struct rs_server {
     rs_ctx *ctx = nullptr;
     int device = 0;
@@ -90,12 +96,70 @@ struct rs_server {
     std::deque<Batch> inflight;
     std::deque<rs_completion> done;
     size_t inflight_bytes = 0;
+    rs_server_stats stats = {};
     int pending = 0;
     bool stop = false;
     std::thread thr;
 
+    hipEvent_t take_event();              // caller holds mu
+    void launch(Batch &b);                // without mu
     void loop();
 };
+
+hipEvent_t rs_server::take_event()
+{
+    if (ev_pool.empty()) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return nullptr;
+        return e;
+    }
+    hipEvent_t e = ev_pool.back();
+    ev_pool.pop_back();
+    return e;
+}
+
+// Queue the batch's requests on its stream: first the waits on their
+// producers, then one batched encode call and one batched decode call.  A
+// batched call that fails is rerun request by request, so that every
+// request gets its own status (the checks at submit make this rare: it
+// takes a device or allocation failure).
+void rs_server::launch(Batch &b)
+{
+    hipStream_t s = streams[b.stream];
+    b.status.assign(b.reqs.size(), RS_OK);
+    for (size_t i = 0; i < b.reqs.size(); i++)
+        if (b.reqs[i].ready && hipStreamWaitEvent(s, b.reqs[i].ready, 0) != hipSuccess)
+            b.status[i] = RS_EDEVICE;
+    for (int op = RS_OP_ENCODE; op <= RS_OP_DECODE; op++) {
+        std::vector<rs_stripe_desc> descs;
+        std::vector<uint8_t> masks;
+        std::vector<size_t> idx;
+        for (size_t i = 0; i < b.reqs.size(); i++) {
+            const Req &r = b.reqs[i];
+            if (r.r.op != op || b.status[i] != RS_OK)
+                continue;
+            descs.push_back(r.r.desc);
+            masks.insert(masks.end(), r.mask.begin(), r.mask.end());
+            idx.push_back(i);
+        }
+        if (descs.empty())
+            continue;
+        int rc = op == RS_OP_ENCODE ? rs_encode_batch(ctx, descs.data(), (int)descs.size(), s)
+                                    : rs_decode_batch(ctx, descs.data(), masks.data(), (int)descs.size(), s);
+        if (rc == RS_OK)
+            continue;
+        size_t moff = 0;
+        for (size_t j = 0; j < idx.size(); j++) {
+            const Req &r = b.reqs[idx[j]];
+            b.status[idx[j]] = op == RS_OP_ENCODE ? rs_encode_batch(ctx, &r.r.desc, 1, s)
+                                                  : rs_decode_batch(ctx, &r.r.desc, masks.data() + moff, 1, s);
+            moff += r.mask.size();
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        stats.retried += idx.size();
+    }
+}
 
 void rs_server::loop()
 {
@@ -111,9 +175,12 @@ void rs_server::loop()
                 continue;
             }
             const int64_t t = now_ns();
-            const int st = q == hipSuccess ? it->status : RS_EDEVICE;
-            for (const Req &r : it->reqs)
-                done.push_back({r.r.tag, st, t});
+            for (size_t i = 0; i < it->reqs.size(); i++) {
+                const Req &r = it->reqs[i];
+                done.push_back({r.r.tag, q == hipSuccess ? it->status[i] : RS_EDEVICE, t});
+                if (r.ready)
+                    ev_pool.push_back(r.ready);
+            }
             inflight_bytes -= it->bytes;
             busy[it->stream]--;
             ev_pool.push_back(it->ev);
@@ -129,57 +196,56 @@ void rs_server::loop()
             Batch b;
             b.stream = (int)si;
             b.bytes = 0;
-            b.status = RS_OK;
+            bool oversize = false;
             while (!queue.empty() && (int)b.reqs.size() < max_batch) {
                 const size_t need = queue.front().bytes;
                 const bool alone = inflight_bytes == 0 && b.reqs.empty();
                 if (!alone && inflight_bytes + b.bytes + need > budget)
                     break;
+                oversize = alone && need > budget;
                 b.bytes += need;
                 b.reqs.push_back(std::move(queue.front()));
                 queue.pop_front();
+                if (oversize)
+                    break;                  // nothing joins a request above the budget
             }
             if (b.reqs.empty())
                 break;                      // the head does not fit yet
             inflight_bytes += b.bytes;
+            stats.admitted += b.reqs.size();
+            stats.batches++;
+            stats.peak_bytes = std::max<uint64_t>(stats.peak_bytes, inflight_bytes);
+            if (oversize) {
+                stats.oversize_admitted++;
+                stats.largest_oversize = std::max<uint64_t>(stats.largest_oversize, b.bytes);
+            } else {
+                stats.peak_shared_bytes = std::max<uint64_t>(stats.peak_shared_bytes, inflight_bytes);
+            }
             busy[si]++;
-            if (ev_pool.empty()) {
-                hipEvent_t e;
-                if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
-                    e = nullptr;
-                ev_pool.push_back(e);
-            }
-            b.ev = ev_pool.back();
-            ev_pool.pop_back();
+            b.ev = take_event();
             lk.unlock();
-            // build the two batches outside the lock
-            std::vector<rs_stripe_desc> enc, dec;
-            std::vector<uint8_t> masks;
-            for (const Req &r : b.reqs) {
-                if (r.r.op == RS_OP_ENCODE) {
-                    enc.push_back(r.r.desc);
-                } else {
-                    dec.push_back(r.r.desc);
-                    masks.insert(masks.end(), r.mask.begin(), r.mask.end());
-                }
+            launch(b);                      // outside the lock
+            hipEvent_t unused = nullptr;
+            if (b.ev && hipEventRecord(b.ev, streams[si]) != hipSuccess) {
+                unused = b.ev;
+                b.ev = nullptr;
             }
-            hipStream_t s = streams[si];
-            int rc = RS_OK;
-            if (!enc.empty())
-                rc = rs_encode_batch(ctx, enc.data(), (int)enc.size(), s);
-            if (!rc && !dec.empty())
-                rc = rs_decode_batch(ctx, dec.data(), masks.data(), (int)dec.size(), s);
-            if (!b.ev || hipEventRecord(b.ev, s) != hipSuccess) {
-                if (!rc)
-                    rc = RS_EDEVICE;
-                (void)hipStreamSynchronize(s);
+            if (!b.ev) {                    // no completion event: wait here instead
+                (void)hipStreamSynchronize(streams[si]);
+                for (int &st : b.status)
+                    if (st == RS_OK)
+                        st = RS_EDEVICE;
             }
-            b.status = rc;
             lk.lock();
-            if (!b.ev) {                    // no event: completed synchronously above
+            if (unused)
+                ev_pool.push_back(unused);
+            if (!b.ev) {                    // no event: waited for the stream above
                 const int64_t t = now_ns();
-                for (const Req &r : b.reqs)
-                    done.push_back({r.r.tag, rc, t});
+                for (size_t i = 0; i < b.reqs.size(); i++) {
+                    done.push_back({b.reqs[i].r.tag, b.status[i], t});
+                    if (b.reqs[i].ready)
+                        ev_pool.push_back(b.reqs[i].ready);
+                }
                 inflight_bytes -= b.bytes;
                 busy[si]--;
                 cv_done.notify_all();
@@ -244,29 +310,34 @@ __attribute__((visibility("default"))) int rs_server_submit(rs_server *s, const 
     const rs_stripe_desc &d = req->desc;
     if (req->op != RS_OP_ENCODE && req->op != RS_OP_DECODE)
         return RS_EINVAL;
-    if (d.k < 1 || d.n <= d.k)
-        return RS_ESHAPE;
+    const bool decode = req->op == RS_OP_DECODE;
+    if (decode && !req->mask)
+        return RS_EINVAL;
+    const int rc = nb::check_stripe(s->ctx, d, decode, decode ? req->mask : nullptr);
+    if (rc != RS_OK)
+        return rc;
     Req r;
     r.r = *req;
-    if (req->op == RS_OP_DECODE) {
-        if (!req->mask)
-            return RS_EINVAL;
+    if (decode)
         r.mask.assign(req->mask, req->mask + d.n);
-        int e = 0;
-        for (int t = 0; t < d.n; t++)
-            e += r.mask[t] ? 1 : 0;
-        if (e > d.n - d.k)
-            return RS_ETOOMANY;
-    }
     r.r.mask = nullptr;
+    r.r.after = nullptr;
     r.bytes = request_bytes(r.r);
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        if (s->stop)
-            return RS_EINVAL;
-        s->queue.push_back(std::move(r));
-        s->pending++;
+    r.ready = nullptr;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop)
+        return RS_EINVAL;
+    if (req->after) {
+        r.ready = s->take_event();
+        if (!r.ready)
+            return RS_EDEVICE;
+        if (hipEventRecord(r.ready, (hipStream_t)req->after) != hipSuccess) {
+            s->ev_pool.push_back(r.ready);
+            return RS_EDEVICE;
+        }
     }
+    s->queue.push_back(std::move(r));
+    s->pending++;
     s->cv_work.notify_one();
     return RS_OK;
 }
@@ -298,6 +369,17 @@ __attribute__((visibility("default"))) int rs_server_pending(rs_server *s)
         return RS_EINVAL;
     std::lock_guard<std::mutex> lk(s->mu);
     return s->pending;
+}
+
+__attribute__((visibility("default"))) int rs_server_get_stats(rs_server *s, rs_server_stats *out)
+{
+    if (!s || !out)
+        return RS_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->stats;
+    out->budget = s->budget;
+    out->inflight_bytes = s->inflight_bytes;
+    return RS_OK;
 }
 
 __attribute__((visibility("default"))) void rs_server_free(rs_server *s)

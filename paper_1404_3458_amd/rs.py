@@ -92,7 +92,14 @@ RS_OP_ENCODE, RS_OP_DECODE = 0, 1
 
 
 class Request(ctypes.Structure):
-    _fields_ = [("op", ctypes.c_int32), ("desc", StripeDesc), ("mask", ctypes.c_void_p), ("tag", ctypes.c_uint64)]
+    _fields_ = [("op", ctypes.c_int32), ("desc", StripeDesc), ("mask", ctypes.c_void_p), ("tag", ctypes.c_uint64),
+                ("after", ctypes.c_void_p)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_uint64) for name in (
+        "budget", "inflight_bytes", "peak_bytes", "peak_shared_bytes", "oversize_admitted", "largest_oversize",
+        "admitted", "batches", "retried")]
 
 
 class Completion(ctypes.Structure):
@@ -110,27 +117,54 @@ class Server:
         _check(load().rs_server_create(codec._ctx, int(budget_bytes), max_batch, nstreams, ctypes.byref(self._h)),
                "rs_server_create")
         self._buf = (Completion * 4096)()
+        self._live = {}              # tag -> [(src, dst)] of requests not yet returned by poll
 
-    def submit(self, op, n, k, src, dst, mask=None, tag=0, row_bytes=None):
+    def submit(self, op, n, k, src, dst, mask=None, tag=0, row_bytes=None, after=None):
         """op RS_OP_ENCODE: src = k message rows, dst = n - k parity rows;
-        RS_OP_DECODE: src = n shards, dst = n output rows (may be src)."""
+        RS_OP_DECODE: src = n shards, dst = n output rows (may be src).
+        The request runs after the work queued so far on `after` (default:
+        torch's current stream; False: no ordering).  src and dst are kept
+        referenced until poll() returns the request's completion."""
+        enc = op == RS_OP_ENCODE
         if row_bytes is None:
-            row_bytes = _rows(src, k if op == RS_OP_ENCODE else n)[1]
-        req = Request(op, StripeDesc(n, k, row_bytes, _ptr(src), _ptr(dst)), None, tag)
+            row_bytes = _rows(src, k if enc else n)[1]
+            if _rows(dst, n - k if enc else n)[1] != row_bytes:
+                raise ValueError("dst rows differ in length from src rows")
+        if after is False:
+            after_ptr = None
+        else:
+            after_ptr = _stream(after)
+        req = Request(op, StripeDesc(n, k, row_bytes, _ptr(src), _ptr(dst)), None, tag, after_ptr)
         mk = None
         if op == RS_OP_DECODE:
             mk = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
-            assert mk.shape == (n,)
+            if mk.shape != (n,):
+                raise ValueError("mask must hold n bytes")
             req.mask = mk.ctypes.data_as(ctypes.c_void_p)
-        return _check(load().rs_server_submit(self._h, ctypes.cast(ctypes.pointer(req), ctypes.c_void_p)),
-                      "rs_server_submit")
+        rc = _check(load().rs_server_submit(self._h, ctypes.cast(ctypes.pointer(req), ctypes.c_void_p)),
+                    "rs_server_submit")
+        self._live.setdefault(tag, []).append((src, dst))
+        return rc
 
     def poll(self, timeout_ms=0):
         """List of (tag, status, t_done_ns) of completed requests."""
         n = load().rs_server_poll(self._h, ctypes.cast(self._buf, ctypes.c_void_p), len(self._buf), int(timeout_ms))
         if n < 0:
             raise RSError(n, "rs_server_poll")
-        return [(self._buf[i].tag, self._buf[i].status, self._buf[i].t_done_ns) for i in range(n)]
+        out = [(self._buf[i].tag, self._buf[i].status, self._buf[i].t_done_ns) for i in range(n)]
+        for tag, _, _ in out:
+            held = self._live.get(tag)
+            if held:
+                held.pop(0)
+                if not held:
+                    del self._live[tag]
+        return out
+
+    def stats(self):
+        """The server's admission record (rs_server_get_stats) as a dict."""
+        st = ServerStats()
+        _check(load().rs_server_get_stats(self._h, ctypes.byref(st)), "rs_server_get_stats")
+        return {name: int(getattr(st, name)) for name, _ in ServerStats._fields_}
 
     def pending(self):
         return load().rs_server_pending(self._h)
@@ -178,6 +212,7 @@ def load():
             "rs_server_submit": (i32, [vp, vp]),
             "rs_server_poll": (i32, [vp, vp, i32, i32]),
             "rs_server_pending": (i32, [vp]),
+            "rs_server_get_stats": (i32, [vp, vp]),
             "rs_server_free": (None, [vp]),
             "rs_schedule_set": (i32, [vp, i32, i32, i32]),
             "rs_schedule_get": (i32, [vp, i32, i32, ctypes.POINTER(i32)]),
@@ -234,9 +269,10 @@ def _rows(t, nrows=None):
     """(rows, row_bytes) of a contiguous uint8 tensor; raw ints pass through."""
     import torch
 
-    assert t.dtype == torch.uint8 and t.is_contiguous(), "expected a contiguous uint8 tensor"
-    if nrows is not None:
-        assert t.dim() == 2 and t.shape[0] == nrows, (t.shape, nrows)
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or not t.is_contiguous():
+        raise ValueError("expected a contiguous uint8 tensor")
+    if nrows is not None and (t.dim() != 2 or t.shape[0] != nrows):
+        raise ValueError("expected %d rows, got shape %s" % (nrows, tuple(t.shape)))
     return t.shape[0], (t.shape[1] if t.dim() == 2 else 0)
 
 
@@ -356,7 +392,7 @@ class Codec:
         return _check(load().nb_derivative(self._ctx, h, _ptr(data), row_bytes, _stream(stream)),
                       "nb_derivative")
 
-    # ------------------------------------------------------------ polynomial operations (Sec. 5)
+    # ------------------------------------------------------------ polynomial operations (Sec. 6.1, Table 1)
     def polymul(self, h, l, a, b, out, row_bytes=None, stream=None):
         """out (2h rows) = product of the novel-basis polynomials in a and b (h rows each)."""
         if row_bytes is None:
