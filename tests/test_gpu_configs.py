@@ -1,10 +1,24 @@
 """GPU parity at the full sizes of the measured workloads, seeded and launched
-as the benchmark launches them: the (16, 8) GF(2^8) batch element by element
-against the oracle; the (256, 128) GF(2^16) batch on sampled columns against
-the oracle and whole-codeword recovery; the 8192-stripe mixed batch through
-autotuned plans replayed in HIP graphs, on sampled columns against the oracle
-and recovery of every stripe (row and column sums of each stripe before
-erasure and after decode, over its bytes as int64 words)."""
+as the benchmark launches them, against the oracle:
+
+  * the (16, 8) GF(2^8) batch: every stripe, element by element;
+  * the (256, 128) GF(2^16) batch of 64 stripes x 64 KiB: every parity byte
+    element by element against the oracle's encoder run here; every decoded
+    byte element by element against that oracle-checked codeword, by SHA-256
+    against the oracle decoder's output for every stripe (digests written by
+    tests/golden/make_fullsize.py from the oracle alone), and element by
+    element against the oracle decoder run here on two stripes;
+  * the 8192-stripe mixed batch through autotuned plans replayed in HIP
+    graphs: every stripe on a seeded sample of columns that includes its
+    first and last column (parity and decode against the oracle run here),
+    and a seeded 1 % of the stripes on every column (parity and decoded rows
+    by SHA-256 against the oracle's, from the same golden file), plus every
+    stripe's recovery by row and column sums."""
+import concurrent.futures as cf
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -14,6 +28,44 @@ from paper_1404_3458_amd import rs, synth, tune
 from gpu_util import first_diff, to_host
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize.json")
+THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def _sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def _blocks(ncols, parts):
+    per = max(1, -(-ncols // parts))
+    return [(c0, min(ncols, c0 + per)) for c0 in range(0, ncols, per)]
+
+
+def _oracle_encode_par(ex, n, k, msg):
+    """The oracle's parity of a GF(2^16) stripe, columns split over the pool."""
+    par = np.zeros((n - k, msg.shape[1]), dtype=np.uint8)
+
+    def one(b):
+        par[:, 2 * b[0]:2 * b[1]] = oracle.encode(16, n, k, np.ascontiguousarray(msg[:, 2 * b[0]:2 * b[1]]))
+
+    list(ex.map(one, _blocks(msg.shape[1] // 2, 4 * THREADS)))
+    return par
+
+
+def _oracle_decode_par(ex, n, k, mask, rx):
+    out = np.zeros_like(rx)
+
+    def one(b):
+        out[:, 2 * b[0]:2 * b[1]] = oracle.decode(16, n, k, mask, np.ascontiguousarray(rx[:, 2 * b[0]:2 * b[1]]))
+
+    list(ex.map(one, _blocks(rx.shape[1] // 2, 4 * THREADS)))
+    return out
 
 
 def _fill(cws, cfg_id, k):
@@ -46,30 +98,29 @@ def test_c1_full_config(codec8):
 def test_c2_full_config(codec16):
     # 64 stripes of (256, 128) over GF(2^16), 64 KiB shards, 128 erasures each
     n, k, ns, S, e = 256, 128, 64, 65536, 128
+    gold = _golden()["c2"]
+    assert [g["stripe"] for g in gold] == list(range(ns))
     cw = torch.empty((ns, n, S), dtype=torch.uint8, device="cuda")
     _fill(cw, 2, k)
     masks = [synth.erasure_mask(synth.key(2, s, synth.ERASURE), n, e) for s in range(ns)]
     codec16.encode_batch([(n, k, cw[s, :k], cw[s, k:]) for s in range(ns)])
-    torch.cuda.synchronize()
-    ref = cw.clone()
-    ncol = S // 2
-    for s in range(ns):
-        cw[s][torch.from_numpy(masks[s]).bool().cuda()] = 0
-    rx_dev = cw.clone()
-    codec16.decode_batch([(n, k, masks[s], cw[s], cw[s]) for s in range(ns)])
-    torch.cuda.synchronize()
-    assert torch.equal(cw, ref), "decode did not restore every codeword"
-    for s in (0, 37, ns - 1):
-        cols = sorted({0, 1, ncol - 1} | set(int(c) for c in synth.uniform_int(synth.key(2, s, 90), 24, 0, ncol - 1)))
-
-        def sample(t):
-            return np.ascontiguousarray(t[s].cpu().numpy().reshape(n, ncol, 2)[:, cols, :].reshape(n, 2 * len(cols)))
-
-        full, rx = sample(ref), sample(rx_dev)
-        exp = oracle.encode(16, n, k, full[:k])
-        assert (full[k:] == exp).all(), (s, first_diff(full[k:], exp))
-        dec = oracle.decode(16, n, k, masks[s], rx)
-        assert (sample(cw) == dec).all(), (s, first_diff(sample(cw), dec))
+    enc = to_host(cw)
+    with cf.ThreadPoolExecutor(max_workers=THREADS) as ex:
+        for s in range(ns):                          # every parity byte against the oracle's encoder
+            exp = _oracle_encode_par(ex, n, k, enc[s, :k])
+            assert (enc[s, k:] == exp).all(), (s, first_diff(enc[s, k:], exp))
+            assert _sha(enc[s, k:]) == gold[s]["parity_sha256"], s
+        for s in range(ns):
+            cw[s][torch.from_numpy(masks[s]).bool().cuda()] = 0
+        rx_host = to_host(cw)
+        codec16.decode_batch([(n, k, masks[s], cw[s], cw[s]) for s in range(ns)])
+        got = to_host(cw)
+        for s in range(ns):                          # every decoded byte
+            assert (got[s] == enc[s]).all(), (s, first_diff(got[s], enc[s]))
+            assert _sha(got[s]) == gold[s]["decoded_sha256"], s
+        for s in (0, ns - 1):                        # the oracle's decoder run here, every column
+            exp = _oracle_decode_par(ex, n, k, masks[s], rx_host[s])
+            assert (got[s] == exp).all(), (s, first_diff(got[s], exp))
 
 
 def _sums(t, n, sb):
@@ -107,22 +158,22 @@ def test_c4_full_config():
             graphs.append(g)
         graphs[0].replay()
         torch.cuda.synchronize()
-        # parity of one stripe per class (the first with erasures) on sampled columns
-        picks = {}
+        # every stripe on a seeded column sample with its first and last column
+        samples = []
         for s, (n, k, sb, e) in enumerate(shapes):
-            if e and (n, k) not in picks:
-                picks[(n, k)] = s
-        assert len(picks) == len(synth.MIXED_CLASSES)
-        samples = {}
-        for (n, k), s in picks.items():
-            sb = shapes[s][2]
-            cols = sorted({0, sb // 2 - 1} | set(int(c) for c in synth.uniform_int(synth.key(4, s, 90), 6, 0,
-                                                                                      sb // 2 - 1)))
-            full = np.ascontiguousarray(cws[s].cpu().numpy().reshape(n, sb // 2, 2)[:, cols, :]
-                                        .reshape(n, 2 * len(cols)))
-            exp = oracle.encode(16, n, k, full[:k])
-            assert (full[k:] == exp).all(), ((n, k), s, first_diff(full[k:], exp))
-            samples[s] = (cols, full)
+            nc = sb // 2
+            cols = sorted({0, nc - 1} | set(int(c) for c in synth.uniform_int(synth.key(4, s, 90), 6, 0, nc - 1)))
+            idx = torch.tensor(cols, device="cuda")
+            samples.append((cols, cws[s].view(n, nc, 2).index_select(1, idx).reshape(n, 2 * len(cols)).cpu().numpy()))
+        # a seeded 1 % of the stripes on every column (digests of the oracle's results)
+        gold = {g["stripe"]: g for g in _golden()["c4"]}
+        assert len(gold) == 82
+        full_par = {}
+        for s, g in gold.items():
+            n, k, sb, e = shapes[s]
+            assert (g["n"], g["k"], g["shard_bytes"], g["erasures"]) == (n, k, sb, e), s
+            full_par[s] = _sha(cws[s][k:].cpu().numpy())
+        assert sorted(synth.MIXED_CLASSES) == sorted({shapes[s][:2] for s in gold})
         before = [_sums(cws[s], n, sb) for s, (n, k, sb, e) in enumerate(shapes)]
         for s, (n, k, sb, e) in enumerate(shapes):
             if e:
@@ -133,15 +184,34 @@ def test_c4_full_config():
             after = _sums(cws[s], n, sb)
             assert torch.equal(after[0], before[s][0]) and torch.equal(after[1], before[s][1]), \
                 ("stripe not restored", s, shapes[s])
-        # the oracle's decode of the sampled columns of each picked stripe
-        for s, (cols, full) in samples.items():
+        for s, g in gold.items():
             n, k, sb, e = shapes[s]
+            assert full_par[s] == g["parity_sha256"], ("parity differs from the oracle's", s, shapes[s])
+            assert _sha(cws[s].cpu().numpy()) == g["decoded_sha256"], ("decode differs from the oracle's", s)
+
+        # the oracle on every stripe's sampled columns: parity, then the
+        # decode of the sample with its erased rows zeroed
+        decoded = []
+        for s, (n, k, sb, e) in enumerate(shapes):
+            idx = torch.tensor(samples[s][0], device="cuda")
+            decoded.append(cws[s].view(n, sb // 2, 2).index_select(1, idx).reshape(n, -1).cpu().numpy())
+
+        def check(s):
+            n, k, sb, e = shapes[s]
+            cols, full = samples[s]
+            exp = oracle.encode(16, n, k, np.ascontiguousarray(full[:k]))
+            if not (full[k:] == exp).all():
+                return ("parity", s, shapes[s], first_diff(full[k:], exp))
             rx = full.copy()
             rx[masks[s] == 1] = 0
             dec = oracle.decode(16, n, k, masks[s], rx)
-            got = np.ascontiguousarray(cws[s].cpu().numpy().reshape(n, sb // 2, 2)[:, cols, :]
-                                       .reshape(n, 2 * len(cols)))
-            assert (got == dec).all(), (s, first_diff(got, dec))
+            if not (decoded[s] == dec).all():
+                return ("decode", s, shapes[s], first_diff(decoded[s], dec))
+            return None
+
+        with cf.ThreadPoolExecutor(max_workers=THREADS) as ex:
+            bad = [x for x in ex.map(check, range(ns)) if x is not None]
+        assert not bad, bad[:3]
         del graphs
         pe.close()
         pd.close()

@@ -53,14 +53,18 @@ def test_log_exp_tables(codec8):
 def test_multiply_by_constant_exhaustive(r, codec16, codec8):
     # A 2-point transform at shift l maps (0, a) to (s a, (s + 1) a) with
     # s = W_0(omega_l) / W_0(omega_1) = l for the default basis: every symbol a
-    # times each seeded constant, including 0, 1 and the largest element.
+    # times every constant of GF(2^8), and times 0, 1, the largest element and
+    # 60 seeded constants of GF(2^16).
     c = codec16 if r == 16 else codec8
     q = 1 << r
     sym = r // 8
     syms = np.arange(q, dtype=np.uint16 if r == 16 else np.uint8)
     data = np.zeros((2, q * sym), dtype=np.uint8)
     data[1] = syms.view(np.uint8)
-    consts = [0, 1, 2, q - 1] + [int(v) for v in synth.uniform_int(synth.key(41, r), 60 if r == 16 else 40, 0, q - 1)]
+    if r == 8:
+        consts = list(range(q))
+    else:
+        consts = [0, 1, 2, q - 1] + [int(v) for v in synth.uniform_int(synth.key(41, r), 60, 0, q - 1)]
     for l in consts:
         d = to_dev(data)
         c.fft(2, l, d)
