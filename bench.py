@@ -10,13 +10,14 @@ n - k = 128 uniformly drawn erasures per stripe.
 Prints one JSON line.  `value` is message bytes per second of the whole step
 (each message byte is encoded and then decoded once per step).  `roofline`
 describes the dominant launch (the decode for the default workload), timed
-with HIP events on the launch stream: the fused kernels are bound by the
-VALU issue rate of the GF multiply-by-constant, so the roofline is the
-paper's multiplication count per launch over its average duration against
-the chip's multiply peak with this multiply, with the HBM rate (algorithmic
-bytes n * S per stripe: survivors read and erased rows written) beside it.
+with HIP events on the launch stream: its algorithmic HBM bytes (n * S per
+stripe: survivors read and erased rows written, or message read and parity
+written) over its average duration, against the 8 TB/s HBM peak and against a
+device-to-device copy measured in the same run.  Beside it, `alu` gives the
+same launch against the integer-ALU ceiling of this implementation's
+multiply (the kernels are bound by its issue rate, not by HBM).
 `cpu_baseline` times the CPU oracle on a bounded sample of the same workload
-on this host's cores.
+on this host's cores, and on one core.
 """
 import argparse
 import hashlib
@@ -46,7 +47,7 @@ CONFIGS = {
                         "(n,k) and shards as the mixed workload (5000 resident stripes), 64 GB admission budget; "
                         "saturated rate mu, then lambda = 0.5, 0.7, 0.9 mu with 5000 requests each after 500 warm-up"),
     "poly": dict(r=16, h=4096, cols=32768, poly="mul",
-                 workload="GF(2^16) mod 0x1100B novel-basis product (Sec. 5): two operands of h = 4096 "
+                 workload="GF(2^16) mod 0x1100B novel-basis product (Sec. 6.1, Table 1): two operands of h = 4096 "
                           "coefficients x 32768 columns, 8192-point transforms, point-by-point product, inverse"),
     "conv": dict(r=16, h=4096, cols=32768, poly="conv",
                  workload="GF(2^16) mod 0x1100B basis conversion novel -> monomial -> novel: h = 4096 "
@@ -114,16 +115,76 @@ def paper_mults_per_column(n, k, decode):
     return m0(kp) + (npr // kp - 1) * m(kp)
 
 
-# VALU lane-ops of one multiply-accumulate of 4 symbols by a wave-uniform
-# constant with v_perm lookups: r = 16: 12 v_perm + 6 three-input XOR + 10
-# selector shifts/masks; r = 8: 3 v_perm + 2 XOR + 5 selector ops.
-LANE_OPS_PER_4_MACS = {16: 28, 8: 10}
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz of 32-bit integer VALU issue.
-VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+# Integer-ALU ceiling of the multiply-by-constant, from the chip's unit
+# counts and clock: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6 T 32-bit
+# lane operations per second for plain VALU operations (the rate behind the
+# 157.3 TFLOP/s fp32 figure); v_perm_b32, and any VALU operation with a
+# scalar-register operand, issue at half that rate (measured on this chip).
+# One multiply-accumulate of 4 symbols by a wave-uniform constant costs, in
+# full-rate slots: r = 16: 12 v_perm (24) + 6 three-input XOR + 10 selector
+# shifts/masks = 40; r = 8: 3 v_perm (6) + 2 XOR + 5 selector ops = 13.
+VALU_LANE_OPS_PER_S = 256 * 4 * 32 * 2.4e9
+SLOTS_PER_4_MACS = {16: 40, 8: 13}
 
 
 def mult_peak_per_s(r):
-    return VALU_LANE_OPS_PER_S * 4 / LANE_OPS_PER_4_MACS[r]
+    return VALU_LANE_OPS_PER_S * 4 / SLOTS_PER_4_MACS[r]
+
+
+def copy_gbps(nbytes=1 << 30, reps=10):
+    """Device-to-device copy rate (bytes read + bytes written per second) of
+    a plain torch copy of nbytes, timed with events: the practical HBM
+    ceiling the roofline is also quoted against."""
+    import numpy as np
+    import torch
+
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    dst.copy_(src)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record()
+        dst.copy_(src)
+        b.record()
+    torch.cuda.synchronize()
+    ms = float(np.median([a.elapsed_time(b) for a, b in evs]))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def hbm_roofline(kernel, algo_bytes, launch_s, traffic, copy_rate, extra=None):
+    """The roofline object of a launch: algorithmic bytes over its duration
+    against the HBM peak, and against the measured copy rate."""
+    achieved = algo_bytes / launch_s / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
+            "algorithmic_bytes_per_launch": algo_bytes,
+            "copy_GBps": round(copy_rate, 1) if copy_rate else None,
+            "frac_of_copy": round(achieved / copy_rate, 4) if copy_rate else None}
+    if extra:
+        roof.update(extra)
+    return roof
+
+
+def alu_figures(mults, launch_s, r):
+    peak = mult_peak_per_s(r)
+    return {"alu": {"achieved_Tmul_s": round(mults / launch_s / 1e12, 4), "peak_Tmul_s": round(peak / 1e12, 4),
+                    "frac": round(mults / launch_s / peak, 4), "mults_per_launch": mults,
+                    "peak_basis": "this implementation's multiply: %d full-rate VALU slots per 4 symbols, "
+                                  "78.6 T slots/s" % SLOTS_PER_4_MACS[r]}}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def cpu_baseline(cfg, sample_stripes, sample_cols, threads, target_s=12.0):
@@ -172,9 +233,17 @@ def cpu_baseline(cfg, sample_stripes, sample_cols, threads, target_s=12.0):
     if more > 0:
         nb2, dt2 = run(range(1, 1 + more))
         nbytes, dt = nbytes + nb2, dt + dt2
+    # one core: the first 1/threads of stripe 0's column blocks, one at a time
+    items1 = blocks_of(0)[:1]
+    t1 = time.perf_counter()
+    nb1 = sum(work(it) for it in items1)
+    dt1 = time.perf_counter() - t1
     return {"value": nbytes / dt / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "affinity_cores": len(os.sched_getaffinity(0)), "cpu_model": cpu_model(),
+            "single_core_GBps": nb1 / dt1 / 1e9,
             "sample": "%d stripe(s) x %d columns of the same workload (%d B of message), encode + decode, "
-                      "%.2f s wall" % (1 + max(more, 0), cols, nbytes, dt)}
+                      "%.2f s wall on %d threads; single core: %d columns of one stripe, %.2f s"
+                      % (1 + max(more, 0), cols, nbytes, dt, threads, items1[0][0].shape[1] // sym, dt1)}
 
 
 def schedule_for(args, codec, shapes, target_bytes=256 << 20):
@@ -216,7 +285,7 @@ def conv_mults_per_column(h):
 
 
 def run_poly(args, cfg):
-    """Polynomial operations of Sec. 5 on a fixed synthetic batch of columns:
+    """Polynomial operations of Sec. 6.1 (Table 1) on a fixed synthetic batch of columns:
     the product (nb_polymul) or the conversion round trip (nb_to_monomial then
     nb_from_monomial)."""
     import numpy as np
@@ -285,7 +354,6 @@ def run_poly(args, cfg):
         nbytes = 2 * h * rb                                                 # two conversions of h rows
         algo_bytes = 4 * h * rb
     mults = per_col * nc
-    peak = mult_peak_per_s(r)
     cpu = None
     if not args.no_cpu:
         threads = min(16, len(os.sched_getaffinity(0)))
@@ -321,12 +389,8 @@ def run_poly(args, cfg):
         "data": "synthetic (seeded splitmix64 bytes)",
         "config": {"workload": cfg["workload"], "field_bits": r, "h": h, "columns": nc,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": round(mults / t / 1e12, 4), "peak": round(peak / 1e12, 4),
-                     "unit": "Tmul/s", "frac": round(mults / t / peak, 4), "traffic": None,
-                     "kernel": "whole call (all launches)", "algorithmic_mults_per_step": mults,
-                     "algorithmic_bytes_per_step": algo_bytes,
-                     "hbm_GBps": round(algo_bytes / t / 1e9, 1), "hbm_peak_GBps": HBM_PEAK_GBS,
-                     "hbm_frac": round(algo_bytes / t / 1e9 / HBM_PEAK_GBS, 4)},
+        "roofline": hbm_roofline("whole call (all launches)", algo_bytes, t, None, copy_gbps(),
+                                 alu_figures(mults, t, r)),
         "cpu_baseline": cpu,
         "detail": {"step_ms_p50": round(float(np.percentile(ms, 50)), 4),
                    "step_ms_p99": round(float(np.percentile(ms, 99)), 4), "wall_ms_per_step": round(wall, 4),
@@ -482,7 +546,6 @@ def run_mixed(args, cfg):
     hbm = 2 * cw_bytes / (wall_g * 1e-3) / 1e9        # encode n*S + decode n*S per stripe
     mults = sum(sb // 2 * (paper_mults_per_column(n, k, False) + paper_mults_per_column(n, k, True))
                 for n, k, sb, e in shapes)
-    peak = mult_peak_per_s(16)
     out = {
         "metric": "RS encode/decode GB/s of message data (% HBM peak); batched vs per-stripe; p99",
         "value": round(value, 2),
@@ -499,13 +562,8 @@ def run_mixed(args, cfg):
         "config": {"workload": cfg["workload"], "field_bits": 16, "stripes": ns,
                    "message_GB": round(msg_bytes / 1e9, 2), "codeword_GB": round(cw_bytes / 1e9, 2),
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": round(mults / (wall_g * 1e-3) / 1e12, 4),
-                     "peak": round(peak / 1e12, 4), "unit": "Tmul/s",
-                     "frac": round(mults / (wall_g * 1e-3) / peak, 4), "traffic": None,
-                     "kernel": "whole step (encode and decode plans of every class)",
-                     "algorithmic_mults_per_step": mults, "algorithmic_bytes_per_step": 2 * cw_bytes,
-                     "hbm_GBps": round(hbm, 1), "hbm_peak_GBps": HBM_PEAK_GBS,
-                     "hbm_frac": round(hbm / HBM_PEAK_GBS, 4)},
+        "roofline": hbm_roofline("whole step (encode and decode plans of every class)", 2 * cw_bytes,
+                                 wall_g * 1e-3, None, None, alu_figures(mults, wall_g * 1e-3, 16)),
         "cpu_baseline": None,
         "detail": {
             "graph_step_ms_p50": round(float(np.percentile(ev_g, 50)), 3),
@@ -568,10 +626,12 @@ def run_serving(args, cfg):
         s = i % pool_n
         n, k, sb, e = shapes[s]
         op = ops_cache.setdefault(i, op_of(i))
+        # the payloads were written and synchronized before serving began, so
+        # requests need not wait for a producer stream (after=False)
         if op == rs.RS_OP_ENCODE:
-            srv.submit(op, n, k, cws[s][:k], cws[s][k:], tag=tag)
+            srv.submit(op, n, k, cws[s][:k], cws[s][k:], tag=tag, after=False)
         else:
-            srv.submit(op, n, k, cws[s], cws[s], mask=masks[s], tag=tag)
+            srv.submit(op, n, k, cws[s], cws[s], mask=masks[s], tag=tag, after=False)
         return k * sb
 
     def run(first, count, arrivals_ns):
@@ -784,18 +844,12 @@ def main():
     dom_ms = float((dec_ms if dom == "decode" else enc_ms).mean())
     cols = S // (r // 8)
     mults = ns * cols * paper_mults_per_column(n, k, dom == "decode")
-    peak = mult_peak_per_s(r)
-    achieved = mults / (dom_ms * 1e-3)
-    hbm = algo_bytes / (dom_ms * 1e-3) / 1e9
     lg = int(np.log2(pow2ceil(k) if dom == "encode" else pow2ceil(pow2ceil(k) + n - k)))
-    roof = {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(peak / 1e12, 4),
-            "unit": "Tmul/s", "frac": round(achieved / peak, 4),
-            "traffic": traffic_from_profiles(args.config),
-            "kernel": "%s launch (%s, L=%d)" % (dom, "k_tiled" if 4 < lg <= 8 else
-                                                ("k_small" if lg <= 4 else "multi-pass"), lg),
-            "algorithmic_mults_per_launch": mults,
-            "algorithmic_bytes_per_launch": algo_bytes,
-            "hbm_GBps": round(hbm, 1), "hbm_peak_GBps": HBM_PEAK_GBS, "hbm_frac": round(hbm / HBM_PEAK_GBS, 4)}
+    copy_rate = copy_gbps()
+    roof = hbm_roofline("%s launch (%s, L=%d)" % (dom, "k_tiled" if 4 < lg <= 8 else
+                                                  ("k_small" if lg <= 4 else "multi-pass"), lg),
+                        algo_bytes, dom_ms * 1e-3, traffic_from_profiles(args.config), copy_rate,
+                        alu_figures(mults, dom_ms * 1e-3, r))
 
     extra = {
         "encode_ms": round(float(enc_ms.mean()), 4), "decode_ms": round(float(dec_ms.mean()), 4),
