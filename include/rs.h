@@ -86,6 +86,22 @@ int rs_encode(rs_ctx *ctx, int n, int k, const void *msg, void *parity,
 int rs_decode(rs_ctx *ctx, int n, int k, const uint8_t *erasure_mask,
               const void *shards, void *out, size_t row_bytes, void *stream);
 
+/* rs_decode without any allocation, for callers that cannot allocate (code
+ * under HIP graph capture, serving loops that must not call hipMalloc,
+ * harnesses that forbid it): arguments, results and errors as rs_decode,
+ * but the call's device arena (stripe descriptors, point bitmaps, the
+ * locator's per-point tables: at most 32 KiB) lives in a fixed array of the
+ * library in each GPU's memory, held until the process ends, and the
+ * host-built part of it reaches the device as a kernel argument, so the call
+ * allocates no device or pinned host memory and queues no host-to-device
+ * copy.  Only mother codes of n' <= 256 points (the single-kernel decodes)
+ * fit; larger ones return RS_ESHAPE.  Every call on a GPU shares that GPU's
+ * array, which keeps the last call's contents: calls on one stream are
+ * ordered, calls that overlap on one GPU (other streams, other contexts,
+ * other threads) race and must be ordered by the caller. */
+int rs_decode_static(rs_ctx *ctx, int n, int k, const uint8_t *erasure_mask,
+                     const void *shards, void *out, size_t row_bytes, void *stream);
+
 /* Transform Psi_h^l (Sec. 3.2) and its inverse (Sec. 3.3), in place on h
  * rows of `data` (device); each column of symbols is one coefficient vector
  * (nb_fft input) or one evaluation vector (nb_ifft input).  h a power of two,

@@ -120,6 +120,7 @@ struct rs_ctx {
     uint32_t *d_tw_tab, *d_B_tab, *d_Binv_tab;
     uint32_t *d_wh, *d_wh_tab;  // What_j monomial coefficients (16 j + m) and 1 / leading (256 + j); perm tables
     KPtrs kp;           // method tables (masks / rowtabs filled per call)
+    void *d_static = nullptr;  // this device's static_scratch (rs_decode_static)
     std::mutex mu;
     std::vector<Scratch *> scratch;
     int sticky = RS_OK;
@@ -1415,6 +1416,56 @@ int check_stripe(rs_ctx *ctx, const rs_stripe_desc &d, bool decode, const uint8_
 
 }  // namespace nb
 
+// ------------------------------------------------------------------ decode without allocation
+//
+// rs_decode_static keeps its call arena (stripe descriptors, point bitmaps
+// and the per-point tables the locator writes) in this fixed device array
+// instead of the per-stream arena.  Each GPU holds its own copy of it; host
+// code reaches it only through the address hipGetSymbolAddress returns for
+// the device (the array's name is not a device address on the host).
+
+namespace {
+
+constexpr size_t STATIC_SCRATCH_BYTES = 32 << 10;
+static __device__ __align__(256) uint8_t static_scratch[STATIC_SCRATCH_BYTES];
+
+constexpr int STATIC_IMAGE_WORDS = 256;
+struct StaticImage {
+    uint32_t nwords;
+    uint32_t w[STATIC_IMAGE_WORDS];
+};
+
+// The host-built part of the arena reaches the device as a kernel argument
+// (no staging buffer, no host-to-device copy); vector stores only.
+__global__ __launch_bounds__(64) void k_static_upload(StaticImage img, uint32_t *dst)
+{
+    for (uint32_t i = threadIdx.x; i < img.nwords; i += 64u)
+        dst[i] = img.w[i];
+}
+
+std::mutex static_mu;
+void *static_ptr[64];
+bool static_done[64];
+
+// Address of this device's static_scratch, looked up once per device with
+// that device current (rs_init calls it); null on failure.
+void *static_scratch_of(int device)
+{
+    if (device < 0 || device >= 64)
+        return nullptr;
+    std::lock_guard<std::mutex> lk(static_mu);
+    if (!static_done[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(static_scratch)) != hipSuccess)
+            return nullptr;
+        static_ptr[device] = ptr;
+        static_done[device] = true;
+    }
+    return static_ptr[device];
+}
+
+}  // namespace
+
 // ------------------------------------------------------------------ C ABI
 
 extern "C" {
@@ -1441,6 +1492,11 @@ __attribute__((visibility("default"))) int rs_init(int r, const uint32_t *basis,
         return RS_EINVAL;
     }
     if (hipGetDevice(&ctx->device) != hipSuccess) {
+        delete ctx;
+        return RS_EDEVICE;
+    }
+    ctx->d_static = static_scratch_of(ctx->device);
+    if (!ctx->d_static) {
         delete ctx;
         return RS_EDEVICE;
     }
@@ -1602,6 +1658,51 @@ __attribute__((visibility("default"))) int rs_decode(rs_ctx *ctx, int n, int k, 
     d.in = shards;
     d.out = out;
     return run_codec(ctx, &d, erasure_mask, 1, true, (hipStream_t)stream);
+}
+
+__attribute__((visibility("default"))) int rs_decode_static(rs_ctx *ctx, int n, int k, const uint8_t *erasure_mask,
+                                                            const void *shards, void *out, size_t row_bytes,
+                                                            void *stream)
+{
+    if (!ctx)
+        return RS_EINVAL;
+    int kp, np;
+    int rc = mother_shape(ctx, n, k, &kp, &np);
+    if (rc)
+        return rc;
+    if (np > 1 << FUSED_MAX_L)
+        return RS_ESHAPE;                  // the pass pipelines need 2 n' rows of scratch
+    rs_stripe_desc d;
+    d.n = n;
+    d.k = k;
+    d.row_bytes = row_bytes;
+    d.in = shards;
+    d.out = out;
+    CodecPlan cp;
+    size_t need = 0;
+    rc = build_codec(ctx, &d, erasure_mask, 1, true, nullptr, &need, cp);
+    if (rc)
+        return rc;
+    if (cp.empty())
+        return RS_OK;
+    if (need || cp.dev_bytes > STATIC_SCRATCH_BYTES || cp.host.size() > sizeof(uint32_t) * STATIC_IMAGE_WORDS)
+        return RS_ESHAPE;
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok)
+        return RS_EDEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->sticky)
+        return ctx->sticky;
+    StaticImage img;
+    std::memset(&img, 0, sizeof(img));
+    img.nwords = (uint32_t)((cp.host.size() + 3) / 4);
+    std::memcpy(img.w, cp.host.data(), cp.host.size());
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t *dev = (uint8_t *)ctx->d_static;
+    hipLaunchKernelGGL(k_static_upload, dim3(1), dim3(64), 0, s, img, (uint32_t *)dev);
+    if (dev_err(ctx, hipGetLastError()))
+        return RS_EDEVICE;
+    return exec_codec(ctx, cp, dev, s);
 }
 
 __attribute__((visibility("default"))) int rs_encode_batch(rs_ctx *ctx, const rs_stripe_desc *descs, int count,

@@ -194,6 +194,7 @@ def load():
             "rs_free": (None, [vp]),
             "rs_encode": (i32, [vp, i32, i32, vp, vp, sz, vp]),
             "rs_decode": (i32, [vp, i32, i32, vp, vp, vp, sz, vp]),
+            "rs_decode_static": (i32, [vp, i32, i32, vp, vp, vp, sz, vp]),
             "nb_fft": (i32, [vp, i32, u32, vp, sz, vp]),
             "nb_ifft": (i32, [vp, i32, u32, vp, sz, vp]),
             "nb_derivative": (i32, [vp, i32, vp, sz, vp]),
@@ -322,6 +323,20 @@ class Codec:
             _rows(out, n)
         return _check(load().rs_decode(self._ctx, n, k, mk.ctypes.data_as(ctypes.c_void_p), _ptr(shards),
                                        _ptr(out), row_bytes, _stream(stream)), "rs_decode")
+
+    def decode_static(self, n, k, mask, shards, out=None, row_bytes=None, stream=None):
+        """rs_decode_static: decode with no allocation (mother codes of at most
+        256 points; calls that overlap on one GPU race)."""
+        mk = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        if mk.shape != (n,):
+            raise ValueError("mask must hold n bytes")
+        if out is None:
+            out = shards
+        if row_bytes is None:
+            _, row_bytes = _rows(shards, n)
+            _rows(out, n)
+        return _check(load().rs_decode_static(self._ctx, n, k, mk.ctypes.data_as(ctypes.c_void_p), _ptr(shards),
+                                              _ptr(out), row_bytes, _stream(stream)), "rs_decode_static")
 
     def prepare_encode_batch(self, stripes):
         """Marshal a list of (n, k, msg, parity[, row_bytes]) once, for
