@@ -17,7 +17,10 @@ device-to-device copy measured in the same run.  Beside it, `alu` gives the
 same launch against the integer-ALU ceiling of this implementation's
 multiply (the kernels are bound by its issue rate, not by HBM).
 `cpu_baseline` times the CPU oracle on a bounded sample of the same workload
-on this host's cores, and on one core.
+on this host's cores, and on one core.  The default line's detail also
+carries the 8192-stripe mixed workload (batched plans in a HIP graph against
+per-stripe calls, and per-stripe completion p50/p99), measured after the
+default workload's buffers are released (--no-mixed skips it).
 """
 import argparse
 import hashlib
@@ -580,10 +583,24 @@ def run_mixed(args, cfg):
             "schedule": sched,
         },
     }
-    print(json.dumps(out))
     pe.close()
     pd.close()
     codec.close()
+    return out
+
+
+def mixed_summary(out):
+    """The figures of a mixed-workload line that the default line carries."""
+    d = out["detail"]
+    return {"workload": out["config"]["workload"], "steps": out["steps"], "msg_GBps": out["value"],
+            "ms_per_step": out["ms_per_step"], "hbm_frac": out["roofline"]["frac"],
+            "batched_graph_over_per_stripe": d["graph_over_per_stripe"],
+            "batched_calls_over_per_stripe": d["batched_calls_over_per_stripe"],
+            "per_stripe_step_ms": d["per_stripe_step_ms"],
+            "stripe_done_ms_p50": d["stripe_done_ms_p50"], "stripe_done_ms_p99": d["stripe_done_ms_p99"],
+            "per_class": {c: {key: v[key] for key in ("stripes", "factor", "done_ms_p50", "done_ms_p99",
+                                                      "graph_msg_GBps")}
+                          for c, v in d["per_class"].items()}}
 
 
 def run_serving(args, cfg):
@@ -719,6 +736,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-per-stripe", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="default workload: skip the mixed-workload block of the detail")
     ap.add_argument("--stripes", type=int, default=0, help="mixed workload: stripe count (default 8192)")
     ap.add_argument("--schedule", default="", help="mixed workloads: schedule table (JSON) instead of autotuning")
     ap.add_argument("--no-tune", action="store_true", help="mixed workloads: default schedules")
@@ -751,7 +770,8 @@ def main():
     if cfg.get("poly"):
         return run_poly(args, cfg)
     if cfg.get("mixed"):
-        return run_mixed(args, cfg)
+        print(json.dumps(run_mixed(args, cfg)))
+        return
     if cfg.get("serving"):
         return run_serving(args, cfg)
     r, n, k, S, ns, e = cfg["r"], cfg["n"], cfg["k"], cfg["shard_bytes"], cfg["stripes"], cfg["erasures"]
@@ -912,6 +932,18 @@ def main():
         ps_ms = (time.perf_counter() - t1) * 1e3 / reps
         extra["per_stripe_ms_per_step"] = round(ps_ms, 3)
         extra["batched_over_per_stripe"] = round(ps_ms / ms_per_step, 3)
+
+    if args.config == "c2" and not args.no_mixed:
+        # the batched-vs-per-stripe figures of the 8192-stripe mixed workload
+        # (its own line with --config c4): measured after this workload's
+        # buffers are released
+        del cws, cw, enc_sets, dec_sets, enc_items, dec_items
+        torch.cuda.empty_cache()
+        margs = argparse.Namespace(**vars(args))
+        margs.steps, margs.warmup, margs.stripes = 3, 1, 0
+        mcfg = dict(CONFIGS["c4"])
+        mcfg["id"] = 4
+        extra["mixed"] = mixed_summary(run_mixed(margs, mcfg))
 
     cpu = None
     if not args.no_cpu:

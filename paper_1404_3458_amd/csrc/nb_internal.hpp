@@ -107,7 +107,7 @@ struct WideStripe {
     DevStripe st;             // decode: shards, output, point bitmaps and tables
     const uint8_t *src;       // rows read (row = point index); rows >= src_rows read as zero
     uint8_t *dst;             // rows written; rows >= dst_rows are not written
-    const uint8_t *src2;      // decode derivative: partial sums read
+    const uint8_t *src2;      // decode derivative: partial sums read (W_D3, W_DPM) or the low part's rows A (W_DL)
     uint8_t *dst2;            // decode derivative: partial sums written; encode: coefficients kept
     int32_t src_rows, dst_rows;
     int32_t tile0, nct;

@@ -32,11 +32,27 @@
 // passes, in place on the same buffers.
 //     W_D4   high forward levels
 //     W_D5   low forward levels and step 6 (erased rows over Pi')
+//   decode of a two-part pipeline, three passes (W_D1, W_DH, W_DL):
+//     The derivative of Sec. 4.2 is Binv (.) S (.) B with S the sum over the
+//     bits l of the shifts j <- j + 2^l.  B_j is the product of W'_l over the
+//     set bits of j, so it factors into a low-bit and a high-bit part, S is
+//     the sum of a low-bit and a high-bit part, and the derivative splits
+//     into D_lo + D_hi, each acting on one part of the row index only.  The
+//     high levels of both transforms act on the high index alone (their
+//     factors depend only on the high bits), so
+//       Psi[D Psi^-1[Phi]] = Psi_lo[ Psi_hi D_hi Psi_hi^-1 A + D_lo A ],
+//     where A = Psi_lo^-1[Phi] is what W_D1 writes and Psi_lo, Psi_lo^-1 are
+//     the low levels (per high index, at that index's shift).
+//     W_DH   high inverse levels, D_hi, high forward levels: U
+//     W_DL   U + D_lo A, low forward levels and step 6
 #include "nb_xform.hpp"
 
 namespace nb {
 
-enum WideKind { W_E1 = 0, W_E2 = 1, W_E2F = 2, W_E3 = 3, W_D1 = 4, W_D2 = 5, W_D3 = 6, W_D4 = 7, W_D5 = 8, W_DPM = 9 };
+enum WideKind {
+    W_E1 = 0, W_E2 = 1, W_E2F = 2, W_E3 = 3, W_D1 = 4, W_D2 = 5, W_D3 = 6, W_D4 = 7, W_D5 = 8, W_DPM = 9,
+    W_DH = 10, W_DL = 11
+};
 
 __device__ __forceinline__ int find_wide(const WideStripe *__restrict__ st, int n, int tile)
 {
@@ -69,13 +85,213 @@ struct WideLds {
     static constexpr int TILE = T > WREG ? H * 64 * NW : 0;
     static constexpr int EX = (KIND == W_D3 || KIND == W_DPM) ? 0 : H - 1;
     static constexpr int EX2 = KIND == W_E2 ? H - 1 : 0;
-    static constexpr int EB = (KIND == W_D2 || KIND == W_D3) ? H : 0;
-    static constexpr int ERT = (KIND == W_D1 || KIND == W_D5) ? H : 0;
+    static constexpr int EB = (KIND == W_D2 || KIND == W_D3) ? H : (KIND == W_DH || KIND == W_DL) ? 2 * H : 0;
+    static constexpr int ERT = (KIND == W_D1 || KIND == W_D5 || KIND == W_DL) ? H : 0;
     static constexpr size_t BYTES = 4 * ((size_t)TILE + (size_t)NV * (EX + EX2 + EB + ERT));
     static_assert(BYTES <= 160 * 1024, "pass tile and tables exceed the LDS of a workgroup");
 };
 
 #define NB_WIDE_THREADS(T) ((T) > WREG ? (64 << ((T) - 4)) : 64)
+
+// W_DH and W_DL on one group of 2^T rows (the rows gbase + (p << lo)):
+// x holds a wave's consecutive rows (16 g + j, or all rows when the group is
+// not tiled), y its stride groups (rows r0 + 16 j); cb / my are the wave's and
+// the lane's views of the LDS tile.  The part's derivative factors are
+// B_(p << lo) and its inverse (staged at vb / vbi), local index p.
+template <int T, int KIND, int LD, class TW, class STAGE>
+__device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y)[T > WREG ? (1 << (T - 4)) : 1][2],
+                                                  const WideStripe &ws, const DevStripe &st, const Lane &ln,
+                                                  uint32_t gbase, uint32_t lo, int wave, int g, uint32_t *cb,
+                                                  uint32_t *my, const uint32_t *__restrict__ bits,
+                                                  const uint32_t *__restrict__ rowtab,
+                                                  const uint32_t *__restrict__ p_B,
+                                                  const uint32_t *__restrict__ p_Binv, const uint32_t *vb,
+                                                  const uint32_t *vbi, const uint32_t *vrt, const TW &tw,
+                                                  const STAGE &stage_tables)
+{
+    constexpr int R = 16, NW = 2, H = 1 << T;
+    typedef typename Ops<R>::Tab Tab;
+    constexpr bool TILED = T > WREG;
+    constexpr int L2 = TILED ? T - 4 : 0, NR2 = 1 << L2, GPW = TILED ? 16 >> L2 : 1;
+    constexpr int RS = 64 * NW;
+    const uint64_t rb = st.row_bytes;
+    auto grow = [&](int p) -> uint32_t { return gbase + ((uint32_t)p << lo); };
+    auto lds_put = [&](uint32_t *base, int rows, const uint32_t *v) {
+        *reinterpret_cast<uint2 *>(base + RS * rows) = make_uint2(v[0], v[1]);
+    };
+    auto lds_get = [&](const uint32_t *base, int rows, uint32_t *v) {
+        const uint2 t = *reinterpret_cast<const uint2 *>(base + RS * rows);
+        v[0] = t.x;
+        v[1] = t.y;
+    };
+    auto xorv = [&](uint32_t *a, const uint32_t *b) {
+        a[0] ^= b[0];
+        a[1] ^= b[1];
+    };
+
+    if constexpr (!TILED) {
+        // the whole group in one wave's registers
+        uint32_t a[H][NW];
+#pragma unroll
+        for (int j = 0; j < H; j++) {
+            load_chunk<R, LD>(wrow(ws.src, grow(j), rb), ln.off, ln.act, ln.nsym, x[j]);
+            if (KIND == W_DL)
+                load_chunk<R, LD>(wrow(ws.src2, grow(j), rb), ln.off, ln.act, ln.nsym, a[j]);
+        }
+        stage_tables();
+        uint32_t (*d)[NW] = KIND == W_DH ? x : a;
+        if (KIND == W_DH)
+            reg_levels<R, T, true, SH_ZERO, false>(x, 0u, 0, tw);
+        // d = B (.) rows, then in place, rows in ascending order: the sum of
+        // d over the rows p + 2^l with bit l of p clear, over B_p
+        pipelined<Tab, H>([&](int j) { return row_tab<R>(p_B, vb, j, (uint32_t)j << lo); },
+                          [&](int j, const Tab &t) {
+                              if (j)
+                                  scale<R>(d[j], t);
+                          });
+#pragma unroll
+        for (int j = 0; j < H; j++) {
+            uint32_t z[NW] = {0u, 0u};
+#pragma unroll
+            for (int l = 0; l < T; l++)
+                if (!((j >> l) & 1))
+                    xorv(z, d[j + (1 << l)]);
+            d[j][0] = z[0];
+            d[j][1] = z[1];
+        }
+        pipelined<Tab, H>([&](int j) { return row_tab<R>(p_Binv, vbi, j, (uint32_t)j << lo); },
+                          [&](int j, const Tab &t) {
+                              if (j && j + 1 < H)
+                                  scale<R>(d[j], t);
+                              if (KIND == W_DL)
+                                  xorv(x[j], d[j]);
+                          });
+        reg_levels<R, T, false, SH_ZERO, false>(x, 0u, 0, tw);
+        if (KIND == W_DH) {
+#pragma unroll
+            for (int j = 0; j < H; j++)
+                store_chunk<R, LD>(wrow(ws.dst, fresh(grow(j)), rb), ln.off, ln.act, ln.nsym, x[j]);
+        } else {
+            pipelined<Tab, H>([&](int j) { return row_tab<R>(rowtab, vrt, j, grow(j)); },
+                              [&](int j, const Tab &t) {
+                                  dec_store<R, LD>(x[j], (int)grow(j), st, ln, bits, [&](int) { return t; });
+                              });
+        }
+    } else {
+        // stride layout for the derivative: the partners 16 * 2^l away are in
+        // a wave's registers, those 2^l away (l < 4) in other waves' rows of
+        // the LDS tile
+        uint32_t a[GPW][NR2][NW];                    // W_DL: the rows of A; W_DH: unused
+        uint32_t (*d)[NR2][NW] = KIND == W_DH ? y : a;
+        if (KIND == W_DH) {
+#pragma unroll
+            for (int j = 0; j < 16; j++)
+                load_chunk<R, LD>(wrow(ws.src, grow(16 * g + j), rb), ln.off, ln.act, ln.nsym, x[j]);
+            stage_tables();
+            reg_levels<R, 4, true, SH_ZERO, false>(x, (uint32_t)(16 * g), 0, tw);
+#pragma unroll
+            for (int j = 0; j < 16; j++)
+                lds_put(cb, j, x[j]);
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < GPW; u++) {
+                const int r0 = wave * GPW + u;
+#pragma unroll
+                for (int j = 0; j < NR2; j++)
+                    lds_get(my + RS * r0, 16 * j, y[u][j]);
+                reg_levels<R, L2, true, SH_ZERO, false>(y[u], (uint32_t)r0, 4, tw);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < GPW; u++) {
+                const int r0 = wave * GPW + u;
+#pragma unroll
+                for (int j = 0; j < NR2; j++) {
+                    load_chunk<R, LD>(wrow(ws.src, grow(r0 + 16 * j), rb), ln.off, ln.act, ln.nsym, y[u][j]);
+                    load_chunk<R, LD>(wrow(ws.src2, grow(r0 + 16 * j), rb), ln.off, ln.act, ln.nsym, a[u][j]);
+                }
+            }
+            stage_tables();
+        }
+        // d = B (.) rows; each wave rewrites only its own tile rows, which it
+        // alone has read, so no barrier is needed before the writes
+#pragma unroll
+        for (int u = 0; u < GPW; u++) {
+            const int r0 = wave * GPW + u;
+            pipelined<Tab, NR2>([&](int j) { return row_tab<R>(p_B, vb, r0 + 16 * j, (uint32_t)(r0 + 16 * j) << lo); },
+                                [&](int j, const Tab &t) {
+                                    if (r0 + 16 * j)
+                                        scale<R>(d[u][j], t);
+                                    lds_put(my + RS * r0, 16 * j, d[u][j]);
+                                });
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < GPW; u++) {
+            const int r0 = wave * GPW + u;
+            // in place, j ascending: row j's sum reads only rows above it
+#pragma unroll
+            for (int j = 0; j < NR2; j++) {
+                uint32_t z[NW] = {0u, 0u};
+#pragma unroll
+                for (int l = 0; l < L2; l++)
+                    if (!((j >> l) & 1))
+                        xorv(z, d[u][j + (1 << l)]);
+#pragma unroll
+                for (int l = 0; l < 4; l++) {
+                    if (!((r0 >> l) & 1)) {
+                        uint32_t v[NW];
+                        lds_get(my + RS * r0, (1 << l) + 16 * j, v);
+                        xorv(z, v);
+                    }
+                }
+                d[u][j][0] = z[0];
+                d[u][j][1] = z[1];
+            }
+            pipelined<Tab, NR2>([&](int j) { return row_tab<R>(p_Binv, vbi, r0 + 16 * j,
+                                                               (uint32_t)(r0 + 16 * j) << lo); },
+                                [&](int j, const Tab &t) {
+                                    if (r0 + 16 * j && r0 + 16 * j + 1 < H)
+                                        scale<R>(d[u][j], t);
+                                    if (KIND == W_DL)
+                                        xorv(y[u][j], d[u][j]);
+                                });
+            reg_levels<R, L2, false, SH_ZERO, false>(y[u], (uint32_t)r0, 4, tw);
+        }
+        __syncthreads();                             // every partner read is done
+#pragma unroll
+        for (int u = 0; u < GPW; u++) {
+            const int r0 = wave * GPW + u;
+#pragma unroll
+            for (int j = 0; j < NR2; j++)
+                lds_put(my + RS * r0, 16 * j, y[u][j]);
+        }
+        __syncthreads();
+        if (KIND == W_DL) {
+            // only the 16 consecutive rows that hold an erased stored point
+            // need the last levels
+            const uint32_t *__restrict__ sbm = bits + bitmap_words(st.np);
+            const uint32_t p0 = grow(16 * g);
+            if (!fresh((sbm[p0 >> 5] >> (p0 & 31)) & 0xFFFFu))
+                return;
+        }
+#pragma unroll
+        for (int j = 0; j < 16; j++)
+            lds_get(cb, j, x[j]);
+        reg_levels<R, 4, false, SH_ZERO, false>(x, (uint32_t)(16 * g), 0, tw);
+        if (KIND == W_DH) {
+#pragma unroll
+            for (int j = 0; j < 16; j++)
+                store_chunk<R, LD>(wrow(ws.dst, fresh(grow(16 * g + j)), rb), ln.off, ln.act, ln.nsym, x[j]);
+        } else {
+            pipelined<Tab, 16>([&](int j) { return row_tab<R>(rowtab, vrt, 16 * g + j, grow(16 * g + j)); },
+                               [&](int j, const Tab &t) {
+                                   dec_store<R, LD>(x[j], (int)grow(16 * g + j), st, ln, bits,
+                                                    [&](int) { return t; });
+                               });
+        }
+    }
+}
 
 template <int T, int KIND, int LD>
 __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per_eu(4))) void k_wide(
@@ -126,7 +342,7 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
     // Pruning: a consecutive group none of whose rows is written has nothing
     // to compute in the last pass (decode: no erased stored point, encode:
     // rows past the stored parity).  The test is workgroup-uniform.
-    if (KIND == W_D5) {
+    if (KIND == W_D5 || KIND == W_DL) {
         const uint32_t *__restrict__ sbm = bits + bitmap_words(st.np);
         uint32_t any = 0;
         for (uint32_t w = gbase >> 5; w <= (gbase + H - 1) >> 5; w++)
@@ -166,6 +382,10 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
             stage_rows<R>(vB, p_B, H, tid, NT, lo, gbase);
         if (KIND == W_D3)
             stage_rows<R>(vB, p_Binv, H, tid, NT, lo, gbase);
+        if (KIND == W_DH || KIND == W_DL) {          // the part's own factors: entries j << lo
+            stage_rows<R>(vB, p_B, H, tid, NT, lo, 0u);
+            stage_rows<R>(vB + NV * H, p_Binv, H, tid, NT, lo, 0u);
+        }
         if (LY::ERT)
             stage_rows<R>(vRT, rowtab, H, tid, NT, lo, gbase);
         __syncthreads();
@@ -192,6 +412,12 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
                 store_chunk<R, LD>(wrow(d, fresh(grow(j)), rb), ln.off, ln.act, ln.nsym, x[j]);
         }
     };
+
+    if constexpr (KIND == W_DH || KIND == W_DL) {
+        split_decode_pass<T, KIND, LD>(x, y, ws, st, ln, gbase, lo, wave, g, cb, my, bits, rowtab, p_B, p_Binv,
+                                        vB, vB + NV * H, vRT, twI, stage_tables);
+        return;
+    }
 
     // ------------------------------------------------ input
     bool rcv[NX];
@@ -487,6 +713,8 @@ static hipError_t wide_launch_ld(int kind, int T, const WideArgs &a, const KPtrs
     case W_DPM: return wide_launch_T<W_DPM, LD>(T, a, k, ntiles, s);
     case W_D4: return wide_launch_T<W_D4, LD>(T, a, k, ntiles, s);
     case W_D5: return wide_launch_T<W_D5, LD>(T, a, k, ntiles, s);
+    case W_DH: return wide_launch_T<W_DH, LD>(T, a, k, ntiles, s);
+    case W_DL: return wide_launch_T<W_DL, LD>(T, a, k, ntiles, s);
     }
     return hipErrorInvalidValue;
 }
@@ -507,7 +735,7 @@ hipError_t wide_prepare()
     if ((f = wide_prep_T<K, LD_SYM>()) != hipSuccess) e = f;
     NB_WPREP(W_E1) NB_WPREP(W_E2) NB_WPREP(W_E2F) NB_WPREP(W_E3) NB_WPREP(W_D1) NB_WPREP(W_D2) NB_WPREP(W_D3)
     NB_WPREP(W_DPM)
-    NB_WPREP(W_D4) NB_WPREP(W_D5)
+    NB_WPREP(W_D4) NB_WPREP(W_D5) NB_WPREP(W_DH) NB_WPREP(W_DL)
 #undef NB_WPREP
     return e;
 }

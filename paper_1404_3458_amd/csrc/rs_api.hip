@@ -60,7 +60,8 @@ constexpr int FUSED_MAX_L = 8;      // fused single-launch kernels cover h <= 25
 constexpr int PASS_MAX_T_FWD = 5, PASS_MAX_T_INV = 4;
 constexpr int LOC_ONE_WG_MAX = 4096; // larger mother codes use the multi-workgroup locator
 // pass kinds of nb_wide.hip
-enum { W_E1 = 0, W_E2 = 1, W_E2F = 2, W_E3 = 3, W_D1 = 4, W_D2 = 5, W_D3 = 6, W_D4 = 7, W_D5 = 8, W_DPM = 9 };
+enum { W_E1 = 0, W_E2 = 1, W_E2F = 2, W_E3 = 3, W_D1 = 4, W_D2 = 5, W_D3 = 6, W_D4 = 7, W_D5 = 8, W_DPM = 9,
+       W_DH = 10, W_DL = 11 };
 // scratch of the 8-level pass pipelines: stripes are processed in chunks
 // whose scratch fits this budget (a stripe larger than it runs alone)
 constexpr size_t WIDE_SCRATCH_BUDGET = (size_t)2 << 30;
@@ -656,7 +657,13 @@ void plan_wide(const std::vector<Plan> &plans, const std::vector<int> &idx, bool
             // middle parts (pipelines of three or four parts), the high part
             struct Step { int kind, lo, T, blk; bool mid; };
             std::vector<Step> steps;
-            if (decode) {
+            if (decode && m == 2) {
+                // three passes: the derivative split into its low-bit and
+                // high-bit parts (see nb_wide.hip)
+                steps.push_back({W_D1, 0, T1, 0, false});
+                steps.push_back({W_DH, LH, TH, 0, false});
+                steps.push_back({W_DL, 0, T1, 0, false});
+            } else if (decode) {
                 steps.push_back({W_D1, 0, T1, 0, false});
                 for (int i = 1; i + 1 < m; i++)
                     steps.push_back({W_E1, los[i], parts[i], 0, true});
@@ -744,6 +751,8 @@ void plan_wide(const std::vector<Plan> &plans, const std::vector<int> &idx, bool
                         case W_DPM: w.src = A; w.src2 = Z; w.dst = Z; break;
                         case W_D4: w.src = A; w.dst = A; break;
                         case W_D5: w.src = A; break;
+                        case W_DH: w.src = A; w.dst = Z; break;
+                        case W_DL: w.src = Z; w.src2 = A; break;
                         }
                         for (const ColPart &cp : col_parts(p.aligned, d.ncols)) {
                             if (cp.ld != ld)
