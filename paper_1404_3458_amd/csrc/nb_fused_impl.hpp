@@ -139,10 +139,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == M_EN
 
 // LDS of k_tiled: the tile (2^L rows x 64 lanes x NW dwords), then the V words
 // of every perm table the kernel multiplies by, staged once per workgroup.
+// HALF: the encode of a code with one parity block over at most 2^7 points
+// exchanges the tile one dword of each lane's symbol group at a time (two
+// rounds per exchange), so the LDS holds half a tile: 40 KB per workgroup,
+// which lets four workgroups (32 waves) share a CU instead of two.
 template <int R, int L, int MODE>
 struct TiledLds {
     static constexpr int H = 1 << L, NV = Ops<R>::NV, NW = Traits<R>::NW;
-    static constexpr int TILE = H * 64 * NW;                             // dwords
+    static constexpr bool HALF = R == 16 && MODE == M_ENC2 && L <= 7;
+    static constexpr int TILE = H * 64 * (HALF ? 1 : NW);               // dwords
     static constexpr int EX = MODE == M_DERIV ? 0 : H - 1;               // factors of the main transform
     static constexpr int EY = MODE == M_ENC ? 2 * (H - 1) : MODE == M_ENC2 ? H - 1 : 0;  // parity blocks
     static constexpr int EB = (MODE == M_DERIV || MODE == M_DEC) ? H : 0;  // B_j, and as many 1/B_j
@@ -301,9 +306,14 @@ struct DecTile {
 
 // M_ENC keeps the coefficients in registers across the parity blocks: below
 // 2^8 points its workgroup has at most 8 waves, so it may use the registers
-// of two waves per SIMD instead of spilling.
+// of two waves per SIMD instead of spilling.  The half-tile encodes (HALF)
+// are held to six waves per SIMD (at most 80 registers), so that three
+// workgroups share a CU: a SIMD issues VALU work at close to its peak rate
+// only with more than four waves to pick from.  Their pruned variants keep
+// four (they would spill at six).
 template <int R, int L, int MODE, int SH, int LD, bool PR = false>
-__global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(MODE == M_ENC && L < 8 ? 2 : 4))) void k_tiled(NB_FUSED_PARAMS)
+__global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(
+    MODE == M_ENC && L < 8 ? 2 : (TiledLds<R, L, MODE>::HALF && !PR) ? 6 : 4))) void k_tiled(NB_FUSED_PARAMS)
 {
     typedef TiledLds<R, L, MODE> LY;
     typedef typename Ops<R>::Tab Tab;
@@ -473,18 +483,39 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(M
         return;
     }
     reg_levels<R, 4, true, (MODE == M_IFFT ? SH : SH_ZERO), false>(x, (uint32_t)(16 * g), 0, twX);
+    if constexpr (LY::HALF) {
+        // two rounds through half a tile: row t, lane l at dword 64 t + l
+        uint32_t *const hl = lds + lane;
 #pragma unroll
-    for (int j = 0; j < 16; j++)
-        lds_put(cb, j, x[j]);
-    __syncthreads();
+        for (int w = 0; w < NW; w++) {
+            if (w)
+                __syncthreads();                     // the previous round's words are read
+#pragma unroll
+            for (int j = 0; j < 16; j++)
+                hl[64 * (16 * g + j)] = x[j][w];
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < GPW; u++)
+#pragma unroll
+                for (int j = 0; j < NR2; j++)
+                    y[u][j][w] = hl[64 * (wave * GPW + u + 16 * j)];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; j++)
+            lds_put(cb, j, x[j]);
+        __syncthreads();
+    }
 
     // ---- phase 2 (stride groups): inverse levels 4..L-1
 #pragma unroll
     for (int u = 0; u < GPW; u++) {
         const int r0 = wave * GPW + u;
+        if constexpr (!LY::HALF) {
 #pragma unroll
-        for (int j = 0; j < NR2; j++)
-            lds_get(my + RS * r0, 16 * j, y[u][j]);
+            for (int j = 0; j < NR2; j++)
+                lds_get(my + RS * r0, 16 * j, y[u][j]);
+        }
         reg_levels<R, L2, true, (MODE == M_IFFT ? SH : SH_ZERO), true>(y[u], (uint32_t)r0, 4, twX);
     }
 
@@ -512,17 +543,44 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(M
         for (int u = 0; u < GPW; u++) {
             const int r0 = wave * GPW + u;
             reg_levels<R, L2, false, SH_ALIGNED, true>(y[u], (uint32_t)r0, 4, twY, need);
+            if constexpr (!LY::HALF) {
 #pragma unroll
-            for (int j = 0; j < NR2; j++)
-                if (!PR || j < ng)
-                    lds_put(my + RS * r0, 16 * j, y[u][j]);
+                for (int j = 0; j < NR2; j++)
+                    if (!PR || j < ng)
+                        lds_put(my + RS * r0, 16 * j, y[u][j]);
+            }
         }
-        __syncthreads();
+        if constexpr (LY::HALF) {
+            // each wave rewrites only the rows it read itself, so the first
+            // round needs no barrier before its writes
+            uint32_t *const hl = lds + lane;
+#pragma unroll
+            for (int w = 0; w < NW; w++) {
+                if (w)
+                    __syncthreads();
+#pragma unroll
+                for (int u = 0; u < GPW; u++)
+#pragma unroll
+                    for (int j = 0; j < NR2; j++)
+                        if (!PR || j < ng)
+                            hl[64 * (wave * GPW + u + 16 * j)] = y[u][j][w];
+                __syncthreads();
+                if (!PR || g < ng) {
+#pragma unroll
+                    for (int j = 0; j < 16; j++)
+                        x[j][w] = hl[64 * (16 * g + j)];
+                }
+            }
+        } else {
+            __syncthreads();
+        }
         if (PR && g >= ng)
             return;
+        if constexpr (!LY::HALF) {
 #pragma unroll
-        for (int j = 0; j < 16; j++)
-            lds_get(cb, j, x[j]);
+            for (int j = 0; j < 16; j++)
+                lds_get(cb, j, x[j]);
+        }
         reg_levels<R, 4, false, SH_ALIGNED, false>(x, (uint32_t)(16 * g), 0, twY);
 #pragma unroll
         for (int j = 0; j < 16; j++) {
