@@ -271,12 +271,21 @@ typedef __attribute__((address_space(1))) uint8_t gu8;
 typedef __attribute__((address_space(1))) uint16_t gu16;
 typedef __attribute__((address_space(1))) uint32_t gu32;
 typedef __attribute__((address_space(1))) uint64_t gu64;
+// The same accesses at any symbol alignment: the ROCm runtime runs global
+// memory in unaligned-access mode, so an 8-byte (4-byte) access at a 2-byte
+// (1-byte) aligned address is one global_load/store_dwordx2 (dword) of
+// exactly the bytes named.
+typedef uint64_t __attribute__((aligned(2))) u64_a2;
+typedef uint32_t __attribute__((aligned(1))) u32_a1;
+typedef __attribute__((address_space(1))) u64_a2 gu64_a2;
+typedef __attribute__((address_space(1))) u32_a1 gu32_a1;
 
 // How a lane reaches its 4 symbols of a row:
 //   LD_VEC  one 8-byte (r = 16) or 4-byte (r = 8) access; rows are aligned
 //           and only full chunks are touched;
-//   LD_SYM  one access per symbol (only symbol alignment is required), with
-//           a bound nsym on the symbols that exist (the last partial chunk).
+//   LD_SYM  only symbol alignment is required: a full chunk is one access at
+//           symbol alignment, the last partial chunk one access per symbol,
+//           bounded by nsym.
 enum { LD_VEC = 0, LD_SYM = 1 };
 
 // Uniform value the compiler must treat as freshly computed, so that row
@@ -408,9 +417,8 @@ template <int R, int LD>
 __device__ __forceinline__ void load_chunk(const uint8_t *row_, uint32_t off, bool act, int nsym, uint32_t *v)
 {
     const gu8 *row = (const gu8 *)row_ + off;
-    // LD_SYM: a full chunk is read with the widest accesses its address
-    // allows (the same for every lane of a row); a partial one per symbol
-    const uint32_t mis = (uint32_t)(uintptr_t)row & 3u;
+    // LD_SYM: a full chunk in one access at symbol alignment; a partial one
+    // per symbol
     if (R == 16) {
         uint32_t w0 = 0, w1 = 0;
         if (act) {
@@ -418,15 +426,10 @@ __device__ __forceinline__ void load_chunk(const uint8_t *row_, uint32_t off, bo
                 const uint64_t t = *(const gu64 *)row;
                 w0 = (uint32_t)t;
                 w1 = (uint32_t)(t >> 32);
-            } else if (nsym == 4 && mis == 0) {
-                w0 = *(const gu32 *)row;
-                w1 = *(const gu32 *)(row + 4);
-            } else if (nsym == 4) {               // 2 mod 4: 2 + 4 + 2 bytes
-                const uint32_t lo = *(const gu16 *)row;
-                const uint32_t mid = *(const gu32 *)(row + 2);
-                const uint32_t hi = *(const gu16 *)(row + 6);
-                w0 = lo | (mid << 16);
-                w1 = (mid >> 16) | (hi << 16);
+            } else if (nsym == 4) {
+                const uint64_t t = *(const gu64_a2 *)row;
+                w0 = (uint32_t)t;
+                w1 = (uint32_t)(t >> 32);
             } else {
                 const gu16 *r16 = (const gu16 *)row;
                 const uint32_t s0 = r16[0];
@@ -440,12 +443,10 @@ __device__ __forceinline__ void load_chunk(const uint8_t *row_, uint32_t off, bo
     } else {
         uint32_t w = 0;
         if (act) {
-            if (LD == LD_VEC || (nsym == 4 && mis == 0)) {
+            if (LD == LD_VEC) {
                 w = *(const gu32 *)row;
-            } else if (nsym == 4 && mis == 2) {
-                w = (uint32_t) * (const gu16 *)row | ((uint32_t) * (const gu16 *)(row + 2) << 16);
-            } else if (nsym == 4) {               // odd: 1 + 2 + 1 bytes
-                w = (uint32_t)row[0] | ((uint32_t) * (const gu16 *)(row + 1) << 8) | ((uint32_t)row[3] << 24);
+            } else if (nsym == 4) {
+                w = *(const gu32_a1 *)row;
             } else {
                 w = row[0];
                 if (nsym > 1) w |= (uint32_t)row[1] << 8;
@@ -461,19 +462,13 @@ __device__ __forceinline__ void store_chunk(uint8_t *row_, uint32_t off, bool ac
     if (!act)
         return;
     gu8 *row = (gu8 *)row_ + off;
-    const uint32_t mis = (uint32_t)(uintptr_t)row & 3u;
     if (R == 16) {
         uint32_t w0, w1;
         Ops<16>::pack(v, w0, w1);
         if (LD == LD_VEC) {
             *(gu64 *)row = (uint64_t)w0 | ((uint64_t)w1 << 32);
-        } else if (nsym == 4 && mis == 0) {
-            *(gu32 *)row = w0;
-            *(gu32 *)(row + 4) = w1;
         } else if (nsym == 4) {
-            *(gu16 *)row = (uint16_t)w0;
-            *(gu32 *)(row + 2) = (w0 >> 16) | (w1 << 16);
-            *(gu16 *)(row + 6) = (uint16_t)(w1 >> 16);
+            *(gu64_a2 *)row = (uint64_t)w0 | ((uint64_t)w1 << 32);
         } else {
             gu16 *r16 = (gu16 *)row;
             r16[0] = (uint16_t)w0;
@@ -482,15 +477,10 @@ __device__ __forceinline__ void store_chunk(uint8_t *row_, uint32_t off, bool ac
         }
     } else {
         const uint32_t w = v[0];
-        if (LD == LD_VEC || (nsym == 4 && mis == 0)) {
+        if (LD == LD_VEC) {
             *(gu32 *)row = w;
-        } else if (nsym == 4 && mis == 2) {
-            *(gu16 *)row = (uint16_t)w;
-            *(gu16 *)(row + 2) = (uint16_t)(w >> 16);
         } else if (nsym == 4) {
-            row[0] = (uint8_t)w;
-            *(gu16 *)(row + 1) = (uint16_t)(w >> 8);
-            row[3] = (uint8_t)(w >> 24);
+            *(gu32_a1 *)row = w;
         } else {
             row[0] = (uint8_t)w;
             if (nsym > 1) row[1] = (uint8_t)(w >> 8);
