@@ -158,13 +158,16 @@ int rs_decode_batch(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *mas
 
 /* Reusable batch plans (the batched calls above, planned once).  A plan
  * validates its stripes, builds their descriptors and point bitmaps and
- * allocates their scratch once, on the context's device; rs_plan_launch then
- * queues only kernels and device-to-device copies (no host-to-device copy,
- * no allocation), so a launch can be captured in a HIP graph and replayed.
+ * allocates their scratch once, on the context's device; a decode plan also
+ * runs the erasure locator once (Algorithm 2 step 1 depends only on the
+ * erasure patterns, which the plan fixes), so its launches run steps 2-6
+ * only.  rs_plan_launch queues only kernels and device-to-device copies (no
+ * host-to-device copy, no allocation), so a launch can be captured in a HIP
+ * graph and replayed.
  * The buffers the descriptors name must stay valid for the plan's life; their
  * contents may change between launches (a decode plan fixes the erasure
  * pattern).  Launches of one plan must be ordered (one stream, or events):
- * the plan's locator tables live in its own device memory.  Errors as for
+ * the plan's scratch rows live in its own device memory.  Errors as for
  * the batched calls; RS_ENOMEM if the plan's device memory cannot be
  * allocated. */
 typedef struct rs_plan rs_plan;

@@ -1025,19 +1025,10 @@ int stamp_ranges(const CodecPlan &cp, int count, StampMap &sm, std::vector<uint3
     return RS_OK;
 }
 
-// Queue a built plan on `stream` with its arena at `dev` (the uploaded part
-// already in place).  Launches kernels and device-to-device copies only.
-// sm, ts: completion stamps (ts[0] the launch start, ts[1 + i] stripe i's
-// last workgroup), or null.
-int exec_codec(rs_ctx *ctx, const CodecPlan &cp, uint8_t *dev, hipStream_t stream, const StampMap *sm = nullptr,
-               uint64_t *ts = nullptr, int nstripes = 0)
+// Decode step 1 of a built plan: the erasure locator's per-point tables in
+// the arena at `dev` (they depend only on the erasure patterns).
+int run_locator(rs_ctx *ctx, const CodecPlan &cp, uint8_t *dev, hipStream_t stream)
 {
-    if (sm && dev_err(ctx, stamp_start(ts, sm->slots, sm->nslots, stream)))
-        return RS_EDEVICE;
-    for (size_t i = 0; i < cp.copies.size(); i++)
-        if (dev_err(ctx, hipMemcpyAsync(cp.copies[i].first, cp.copies[i].second, cp.copy_bytes[i],
-                                        hipMemcpyDeviceToDevice, stream)))
-            return RS_EDEVICE;
     KPtrs kp = ctx->kp;
     kp.bits = (const uint32_t *)(dev + cp.off_bits);
     kp.rowtabs = (const uint32_t *)(dev + cp.off_rt);
@@ -1061,6 +1052,31 @@ int exec_codec(rs_ctx *ctx, const CodecPlan &cp, uint8_t *dev, hipStream_t strea
                     return RS_EDEVICE;
             }
         }
+    }
+    return RS_OK;
+}
+
+// Queue a built plan on `stream` with its arena at `dev` (the uploaded part
+// already in place).  Launches kernels and device-to-device copies only.
+// sm, ts: completion stamps (ts[0] the launch start, ts[1 + i] stripe i's
+// last workgroup), or null.  located: the locator's tables are already in
+// the arena (a reusable plan computes them once).
+int exec_codec(rs_ctx *ctx, const CodecPlan &cp, uint8_t *dev, hipStream_t stream, const StampMap *sm = nullptr,
+               uint64_t *ts = nullptr, int nstripes = 0, bool located = false)
+{
+    if (sm && dev_err(ctx, stamp_start(ts, sm->slots, sm->nslots, stream)))
+        return RS_EDEVICE;
+    for (size_t i = 0; i < cp.copies.size(); i++)
+        if (dev_err(ctx, hipMemcpyAsync(cp.copies[i].first, cp.copies[i].second, cp.copy_bytes[i],
+                                        hipMemcpyDeviceToDevice, stream)))
+            return RS_EDEVICE;
+    KPtrs kp = ctx->kp;
+    kp.bits = (const uint32_t *)(dev + cp.off_bits);
+    kp.rowtabs = (const uint32_t *)(dev + cp.off_rt);
+    if (!located) {
+        const int rc = run_locator(ctx, cp, dev, stream);
+        if (rc)
+            return rc;
     }
     const DevStripe *d_ents = (const DevStripe *)dev;
     for (size_t i = 0; i < cp.fused.size(); i++) {
@@ -1914,6 +1930,7 @@ struct rs_plan {
     int count = 0;                // stripes of the batch
     uint64_t *ts = nullptr;       // completion timestamps (rs_plan_set_timestamps)
     StampMap *sm = nullptr;       // their slots, built on the first rs_plan_set_timestamps
+    bool located = false;         // decode: the locator's tables were computed at creation
 };
 
 static int plan_batch(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, int count, bool decode,
@@ -1949,6 +1966,20 @@ static int plan_batch(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *m
                        hipSuccess) {
             rc = RS_EDEVICE;
         }
+    }
+    if (!rc && decode && pl->cp.dev_bytes) {
+        // the locator's tables depend only on the plan's fixed erasure
+        // patterns: computed here once, so launches run the decode passes only
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+            rc = RS_EDEVICE;
+        else {
+            rc = run_locator(ctx, pl->cp, pl->arena, st);
+            if (hipStreamSynchronize(st) != hipSuccess && !rc)
+                rc = RS_EDEVICE;
+            (void)hipStreamDestroy(st);
+        }
+        pl->located = rc == RS_OK;
     }
     if (rc) {
         if (pl->arena)
@@ -1997,7 +2028,7 @@ __attribute__((visibility("default"))) int rs_plan_launch(rs_plan *plan, void *s
             return RS_EDEVICE;
         return RS_OK;
     }
-    return exec_codec(ctx, plan->cp, plan->arena, (hipStream_t)stream, sm, plan->ts, plan->count);
+    return exec_codec(ctx, plan->cp, plan->arena, (hipStream_t)stream, sm, plan->ts, plan->count, plan->located);
 }
 
 __attribute__((visibility("default"))) int rs_plan_set_timestamps(rs_plan *plan, uint64_t *dev_ts, int *clock_khz)
