@@ -231,6 +231,38 @@ __device__ __forceinline__ void touch(const TabT<NV, NS> &T)
 
 template <int R> struct Ops;
 
+// A GF(2^16) perm table whose every word is a per-lane value (both halves
+// of a wave may multiply by different constants): read whole from LDS, the
+// "S words" then sit in vector registers too.  The multiply is unchanged;
+// only the registers its operands live in differ.
+struct Tab16V : Tab16 {
+};
+
+__device__ __forceinline__ void touch(const Tab16V &T)
+{
+    asm volatile("" ::"v"(T.v[0]), "v"(T.v[1]), "v"(T.v[2]), "v"(T.v[3]), "v"(T.v[4]), "v"(T.v[5]), "v"(T.v[6]),
+                 "v"(T.v[7]));
+    asm volatile("" ::"v"(T.s[0]), "v"(T.s[1]), "v"(T.s[2]), "v"(T.s[3]), "v"(T.s[4]), "v"(T.s[5]), "v"(T.s[6]),
+                 "v"(T.s[7]), "v"(T.s[8]), "v"(T.s[9]), "v"(T.s[10]), "v"(T.s[11]));
+}
+
+// All TAB16 words of a table staged in LDS (16-byte aligned), per lane.
+__device__ __forceinline__ Tab16V tab_lds_all(const uint32_t *p)
+{
+    Tab16V r;
+    const uint4 a = *reinterpret_cast<const uint4 *>(p);
+    const uint4 b = *reinterpret_cast<const uint4 *>(p + 4);
+    const uint4 c = *reinterpret_cast<const uint4 *>(p + 8);
+    const uint4 d = *reinterpret_cast<const uint4 *>(p + 12);
+    const uint4 e = *reinterpret_cast<const uint4 *>(p + 16);
+    r.v[0] = a.x; r.v[1] = a.y; r.v[2] = a.z; r.v[3] = a.w;
+    r.v[4] = b.x; r.v[5] = b.y; r.v[6] = b.z; r.v[7] = b.w;
+    r.s[0] = c.x; r.s[1] = c.y; r.s[2] = c.z; r.s[3] = c.w;
+    r.s[4] = d.x; r.s[5] = d.y; r.s[6] = d.z; r.s[7] = d.w;
+    r.s[8] = e.x; r.s[9] = e.y; r.s[10] = e.z; r.s[11] = e.w;
+    return r;
+}
+
 template <> struct Ops<16> {
     static constexpr int NW = 2, NV = VW16, NS = SW16;
     typedef Tab16 Tab;
@@ -404,11 +436,46 @@ struct PipeStep<Tab, N, N> {
 // Runs work(k, table_k) for k < N with table k + 1 fetched before work k, so
 // that one table fetch is in flight while a block is computed; work ends
 // with pin() on what it produced.
+// Two tables in flight: table K + 2 is fetched while block K is computed and
+// table K + 1 is still arriving (per-lane tables come from LDS, five loads
+// each, in waves that have few others to hide their latency behind).
+template <class Tab, int K, int N>
+struct PipeStep2 {
+    template <class F, class W>
+    __device__ static __forceinline__ void run(const F &fetch, const W &work, Tab &cur, Tab &nxt)
+    {
+        touch(cur);
+        asm volatile("" ::: "memory");
+        Tab far = cur;
+        if (K + 2 < N)
+            far = fetch(K + 2);
+        asm volatile("" ::: "memory");
+        work(K, cur);
+        PipeStep2<Tab, K + 1, N>::run(fetch, work, nxt, far);
+    }
+};
+template <class Tab, int N>
+struct PipeStep2<Tab, N, N> {
+    template <class F, class W>
+    __device__ static __forceinline__ void run(const F &, const W &, Tab &, Tab &)
+    {
+    }
+};
+
+template <class Tab> struct PipeDepth { static constexpr int D = 1; };
+template <> struct PipeDepth<Tab16V> { static constexpr int D = 2; };
+
 template <class Tab, int N, class F, class W>
 __device__ __forceinline__ void pipelined(const F &fetch, const W &work)
 {
-    Tab cur = fetch(0);
-    PipeStep<Tab, 0, N>::run(fetch, work, cur);
+    if constexpr (PipeDepth<Tab>::D == 2 && N > 1) {
+        Tab cur = fetch(0);
+        Tab nxt = fetch(1);
+        PipeStep2<Tab, 0, N>::run(fetch, work, cur, nxt);
+    } else {
+        Tab cur = fetch(0);
+        PipeStep<Tab, 0, N>::run(fetch, work, cur);
+    }
 }
 
 // Load this lane's chunk (byte offset `off` in the row) into byte-sliced

@@ -77,12 +77,59 @@ __device__ __forceinline__ uint8_t *wrow(uint8_t *b, uint32_t t, uint64_t rb) { 
 // to 190 registers, leaving two or three waves per SIMD.)
 constexpr int WREG = 4;
 
-// LDS of a pass: the group tile, then the staged V words of the factor
-// tables (a second set for W_E2's forward part) and of the per-point tables.
-template <int T, int KIND>
+// Rows of at most 128 symbols fill only half of a wave (32 lanes of 4
+// columns).  For them a tiled pass can run "packed": a workgroup of half the
+// waves, each wave's two halves holding the rows of two of the original
+// waves (virtual wave 2 w + half).  The halves then multiply by different
+// constants, so every table is staged whole in LDS and read per lane
+// (Tab16V) instead of V words from LDS plus S words from scalar loads.
+// Packed passes exist for the kinds of the two-part pipelines.
+__host__ __device__ constexpr bool packable(int T, int kind)
+{
+    return T > WREG && (kind == W_E1 || kind == W_E2 || kind == W_E3 || kind == W_D1 || kind == W_DH || kind == W_DL);
+}
+
+// Table access of a pass: uniform tables (V words staged in LDS, S words read
+// with scalar loads), or per-lane tables staged whole (packed passes).
+template <bool PK> struct WTab;
+template <> struct WTab<false> {
+    typedef Tab16 Tab;
+    static constexpr int WPE = VW16;                // staged words per table
+    template <int T> using Tw = TwLds<16, T>;
+    __device__ static __forceinline__ Tab row(const uint32_t *__restrict__ g, const uint32_t *vt, int jl, uint32_t jg)
+    {
+        return row_tab<16>(g, vt, jl, jg);
+    }
+    template <int T>
+    __device__ static __forceinline__ Tw<T> tw(const uint32_t *p_tw, uint32_t l, const uint32_t *vt, uint32_t lo,
+                                               uint32_t gbase)
+    {
+        return {p_tw, l, vt, lo, gbase};
+    }
+    __device__ static __forceinline__ uint32_t uni(uint32_t v) { return fresh(v); }
+};
+template <> struct WTab<true> {
+    typedef Tab16V Tab;
+    static constexpr int WPE = TAB16;
+    template <int T> using Tw = TwLdsV<T>;
+    __device__ static __forceinline__ Tab row(const uint32_t *__restrict__, const uint32_t *vt, int jl, uint32_t)
+    {
+        return tab_lds_all(vt + TAB16 * jl);
+    }
+    template <int T>
+    __device__ static __forceinline__ Tw<T> tw(const uint32_t *, uint32_t l, const uint32_t *vt, uint32_t lo, uint32_t)
+    {
+        return {l, vt, lo};
+    }
+    __device__ static __forceinline__ uint32_t uni(uint32_t v) { return v; }   // per lane: no broadcast
+};
+
+// LDS of a pass: the group tile, then the staged words of the factor tables
+// (a second set for W_E2's forward part) and of the per-point tables.
+template <int T, int KIND, bool PK = false>
 struct WideLds {
-    static constexpr int R = 16, H = 1 << T, NV = Ops<R>::NV, NW = Traits<R>::NW;
-    static constexpr int TILE = T > WREG ? H * 64 * NW : 0;
+    static constexpr int R = 16, H = 1 << T, NV = WTab<PK>::WPE, NW = Traits<R>::NW;
+    static constexpr int TILE = T > WREG ? H * (PK ? 32 : 64) * NW : 0;
     static constexpr int EX = (KIND == W_D3 || KIND == W_DPM) ? 0 : H - 1;
     static constexpr int EX2 = KIND == W_E2 ? H - 1 : 0;
     static constexpr int EB = (KIND == W_D2 || KIND == W_D3) ? H : (KIND == W_DH || KIND == W_DL) ? 2 * H : 0;
@@ -92,13 +139,15 @@ struct WideLds {
 };
 
 #define NB_WIDE_THREADS(T) ((T) > WREG ? (64 << ((T) - 4)) : 64)
+#define NB_WIDE_THREADS_PK(T, PK) (NB_WIDE_THREADS(T) >> ((PK) ? 1 : 0))
 
 // W_DH and W_DL on one group of 2^T rows (the rows gbase + (p << lo)):
 // x holds a wave's consecutive rows (16 g + j, or all rows when the group is
 // not tiled), y its stride groups (rows r0 + 16 j); cb / my are the wave's and
 // the lane's views of the LDS tile.  The part's derivative factors are
-// B_(p << lo) and its inverse (staged at vb / vbi), local index p.
-template <int T, int KIND, int LD, class TW, class STAGE>
+// B_(p << lo) and its inverse (staged at vb / vbi), local index p.  PK: a
+// packed pass (wave and g are then per-lane virtual wave indices).
+template <int T, int KIND, int LD, bool PK, class TW, class STAGE>
 __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y)[T > WREG ? (1 << (T - 4)) : 1][2],
                                                   const WideStripe &ws, const DevStripe &st, const Lane &ln,
                                                   uint32_t gbase, uint32_t lo, int wave, int g, uint32_t *cb,
@@ -110,10 +159,12 @@ __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y
                                                   const STAGE &stage_tables)
 {
     constexpr int R = 16, NW = 2, H = 1 << T;
-    typedef typename Ops<R>::Tab Tab;
+    typedef WTab<PK> WT;
+    typedef typename WT::Tab Tab;
     constexpr bool TILED = T > WREG;
+    static_assert(TILED || !PK, "packed passes are tiled");
     constexpr int L2 = TILED ? T - 4 : 0, NR2 = 1 << L2, GPW = TILED ? 16 >> L2 : 1;
-    constexpr int RS = 64 * NW;
+    constexpr int RS = (PK ? 32 : 64) * NW;
     const uint64_t rb = st.row_bytes;
     auto grow = [&](int p) -> uint32_t { return gbase + ((uint32_t)p << lo); };
     auto lds_put = [&](uint32_t *base, int rows, const uint32_t *v) {
@@ -144,7 +195,7 @@ __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y
             reg_levels<R, T, true, SH_ZERO, false>(x, 0u, 0, tw);
         // d = B (.) rows, then in place, rows in ascending order: the sum of
         // d over the rows p + 2^l with bit l of p clear, over B_p
-        pipelined<Tab, H>([&](int j) { return row_tab<R>(p_B, vb, j, (uint32_t)j << lo); },
+        pipelined<Tab, H>([&](int j) { return WT::row(p_B, vb, j, (uint32_t)j << lo); },
                           [&](int j, const Tab &t) {
                               if (j)
                                   scale<R>(d[j], t);
@@ -159,7 +210,7 @@ __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y
             d[j][0] = z[0];
             d[j][1] = z[1];
         }
-        pipelined<Tab, H>([&](int j) { return row_tab<R>(p_Binv, vbi, j, (uint32_t)j << lo); },
+        pipelined<Tab, H>([&](int j) { return WT::row(p_Binv, vbi, j, (uint32_t)j << lo); },
                           [&](int j, const Tab &t) {
                               if (j && j + 1 < H)
                                   scale<R>(d[j], t);
@@ -170,9 +221,9 @@ __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y
         if (KIND == W_DH) {
 #pragma unroll
             for (int j = 0; j < H; j++)
-                store_chunk<R, LD>(wrow(ws.dst, fresh(grow(j)), rb), ln.off, ln.act, ln.nsym, x[j]);
+                store_chunk<R, LD>(wrow(ws.dst, WT::uni(grow(j)), rb), ln.off, ln.act, ln.nsym, x[j]);
         } else {
-            pipelined<Tab, H>([&](int j) { return row_tab<R>(rowtab, vrt, j, grow(j)); },
+            pipelined<Tab, H>([&](int j) { return WT::row(rowtab, vrt, j, grow(j)); },
                               [&](int j, const Tab &t) {
                                   dec_store<R, LD>(x[j], (int)grow(j), st, ln, bits, [&](int) { return t; });
                               });
@@ -218,7 +269,7 @@ __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y
 #pragma unroll
         for (int u = 0; u < GPW; u++) {
             const int r0 = wave * GPW + u;
-            pipelined<Tab, NR2>([&](int j) { return row_tab<R>(p_B, vb, r0 + 16 * j, (uint32_t)(r0 + 16 * j) << lo); },
+            pipelined<Tab, NR2>([&](int j) { return WT::row(p_B, vb, r0 + 16 * j, (uint32_t)(r0 + 16 * j) << lo); },
                                 [&](int j, const Tab &t) {
                                     if (r0 + 16 * j)
                                         scale<R>(d[u][j], t);
@@ -248,7 +299,7 @@ __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y
                 d[u][j][0] = z[0];
                 d[u][j][1] = z[1];
             }
-            pipelined<Tab, NR2>([&](int j) { return row_tab<R>(p_Binv, vbi, r0 + 16 * j,
+            pipelined<Tab, NR2>([&](int j) { return WT::row(p_Binv, vbi, r0 + 16 * j,
                                                                (uint32_t)(r0 + 16 * j) << lo); },
                                 [&](int j, const Tab &t) {
                                     if (r0 + 16 * j && r0 + 16 * j + 1 < H)
@@ -272,7 +323,8 @@ __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y
             // need the last levels
             const uint32_t *__restrict__ sbm = bits + bitmap_words(st.np);
             const uint32_t p0 = grow(16 * g);
-            if (!fresh((sbm[p0 >> 5] >> (p0 & 31)) & 0xFFFFu))
+            const uint32_t need = (sbm[p0 >> 5] >> (p0 & 31)) & 0xFFFFu;
+            if (PK ? !__builtin_amdgcn_ballot_w64(need != 0u) : !fresh(need))
                 return;
         }
 #pragma unroll
@@ -282,32 +334,34 @@ __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y
         if (KIND == W_DH) {
 #pragma unroll
             for (int j = 0; j < 16; j++)
-                store_chunk<R, LD>(wrow(ws.dst, fresh(grow(16 * g + j)), rb), ln.off, ln.act, ln.nsym, x[j]);
+                store_chunk<R, LD>(wrow(ws.dst, WT::uni(grow(16 * g + j)), rb), ln.off, ln.act, ln.nsym, x[j]);
         } else {
-            pipelined<Tab, 16>([&](int j) { return row_tab<R>(rowtab, vrt, 16 * g + j, grow(16 * g + j)); },
+            pipelined<Tab, 16>([&](int j) { return WT::row(rowtab, vrt, 16 * g + j, grow(16 * g + j)); },
                                [&](int j, const Tab &t) {
-                                   dec_store<R, LD>(x[j], (int)grow(16 * g + j), st, ln, bits,
-                                                    [&](int) { return t; });
+                                   dec_store<R, LD, !PK>(x[j], (int)grow(16 * g + j), st, ln, bits,
+                                                         [&](int) { return t; });
                                });
         }
     }
 }
 
-template <int T, int KIND, int LD>
-__global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per_eu(4))) void k_wide(
+template <int T, int KIND, int LD, bool PK>
+__global__ __launch_bounds__(NB_WIDE_THREADS_PK(T, PK)) __attribute__((amdgpu_waves_per_eu(PK ? 2 : 4))) void k_wide(
     WideArgs a, const uint32_t *__restrict__ p_tw, const uint32_t *__restrict__ p_B,
     const uint32_t *__restrict__ p_Binv, const uint32_t *__restrict__ p_bits, const uint32_t *__restrict__ p_rowtabs)
 {
     constexpr int R = 16;
-    typedef WideLds<T, KIND> LY;
-    typedef typename Ops<R>::Tab Tab;
-    constexpr int NW = Traits<R>::NW, NV = Ops<R>::NV, H = 1 << T;
+    typedef WideLds<T, KIND, PK> LY;
+    typedef WTab<PK> WT;
+    typedef typename WT::Tab Tab;
+    static_assert(!PK || packable(T, KIND), "no packed variant of this pass");
+    constexpr int NW = Traits<R>::NW, NV = WT::WPE, H = 1 << T;
     constexpr bool TILED = T > WREG;               // LDS exchange between two register groupings
     constexpr int TA = TILED ? 4 : T;              // levels of the consecutive (register) phase
     constexpr int L2 = TILED ? T - 4 : 0;          // levels of the stride phase
     constexpr int NR2 = 1 << L2;
     constexpr int GPW = TILED ? 16 >> L2 : 1;
-    constexpr int NT = NB_WIDE_THREADS(T);
+    constexpr int NT = NB_WIDE_THREADS_PK(T, PK);
     constexpr int NX = 1 << TA;                    // rows of a consecutive register group
     constexpr bool INV_FIRST = KIND == W_E1 || KIND == W_E2 || KIND == W_D1 || KIND == W_D2;
     constexpr bool PSUM = KIND == W_D3 || KIND == W_DPM;     // partial sums of the derivative
@@ -323,6 +377,7 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
     const int tid = (int)threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int vw = PK ? 2 * wave + (lane >> 5) : wave;     // (virtual) wave of this lane's rows
     const int tile = blockIdx.x;
     const int s = find_wide(a.stripes, a.nstripes, tile);
     const WideStripe ws = a.stripes[s];
@@ -333,7 +388,8 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
     const int ct = rel % ws.nct;
     const uint32_t lo = (uint32_t)a.lo;
     const uint32_t gbase = (gi & ((1u << lo) - 1u)) | ((gi >> lo) << (lo + T));
-    const Lane ln = lane_of<R, LD>(ct, lane, st.col0, st.ncols);
+    const Lane ln = PK ? lane_of<R, LD>(0, 32 * ct + (lane & 31), st.col0, st.ncols)
+                       : lane_of<R, LD>(ct, lane, st.col0, st.ncols);
     const uint64_t rb = st.row_bytes;
     const uint32_t *__restrict__ bits = p_bits + st.bits_off;
     const uint32_t *__restrict__ rowtab = p_rowtabs + st.rowtab_off;
@@ -359,11 +415,11 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
     // (encode) or 0 (decode)
     const uint32_t lf = (KIND == W_E2) ? (uint32_t)st.kp
                       : (KIND == W_E2F || KIND == W_E3) ? (uint32_t)a.blk * (uint32_t)st.kp : 0u;
-    const TwLds<R, T> twI = {p_tw, 0u, vX, lo, gbase};
-    const TwLds<R, T> twF = {p_tw, lf, KIND == W_E2 ? vX2 : vX, lo, gbase};
+    const auto twI = WT::template tw<T>(p_tw, 0u, vX, lo, gbase);
+    const auto twF = WT::template tw<T>(p_tw, lf, KIND == W_E2 ? vX2 : vX, lo, gbase);
 
-    constexpr int RS = 64 * NW;
-    uint32_t *const my = lds + lane * NW;
+    constexpr int RS = (PK ? 32 : 64) * NW;
+    uint32_t *const my = lds + (PK ? (lane & 31) : lane) * NW;
     auto lds_put = [&](uint32_t *base, int rows, const uint32_t *v) {
         uint32_t *p = base + RS * rows;
         *reinterpret_cast<uint2 *>(p) = make_uint2(v[0], v[1]);
@@ -375,23 +431,23 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
     };
     auto stage_tables = [&]() {
         if (LY::EX)
-            stage_levels<R, T>(vX, p_tw, INV_FIRST ? 0u : lf, tid, NT, lo, gbase);
+            stage_levels<R, T, NV>(vX, p_tw, INV_FIRST ? 0u : lf, tid, NT, lo, gbase);
         if (LY::EX2)
-            stage_levels<R, T>(vX2, p_tw, lf, tid, NT, lo, gbase);
+            stage_levels<R, T, NV>(vX2, p_tw, lf, tid, NT, lo, gbase);
         if (KIND == W_D2)
-            stage_rows<R>(vB, p_B, H, tid, NT, lo, gbase);
+            stage_rows<R, NV>(vB, p_B, H, tid, NT, lo, gbase);
         if (KIND == W_D3)
-            stage_rows<R>(vB, p_Binv, H, tid, NT, lo, gbase);
+            stage_rows<R, NV>(vB, p_Binv, H, tid, NT, lo, gbase);
         if (KIND == W_DH || KIND == W_DL) {          // the part's own factors: entries j << lo
-            stage_rows<R>(vB, p_B, H, tid, NT, lo, 0u);
-            stage_rows<R>(vB + NV * H, p_Binv, H, tid, NT, lo, 0u);
+            stage_rows<R, NV>(vB, p_B, H, tid, NT, lo, 0u);
+            stage_rows<R, NV>(vB + NV * H, p_Binv, H, tid, NT, lo, 0u);
         }
         if (LY::ERT)
-            stage_rows<R>(vRT, rowtab, H, tid, NT, lo, gbase);
+            stage_rows<R, NV>(vRT, rowtab, H, tid, NT, lo, gbase);
         __syncthreads();
     };
 
-    const int g = wave;                             // consecutive register group of this wave
+    const int g = vw;                               // consecutive register group of this wave
     uint32_t *const cb = my + RS * 16 * g;
     uint32_t x[NX][NW];                             // consecutive-phase registers (local rows NX g + j)
     uint32_t y[GPW][NR2][NW];                       // stride-phase registers (local rows r0 + 16 j)
@@ -404,18 +460,18 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
             for (int u = 0; u < GPW; u++)
 #pragma unroll
                 for (int j = 0; j < NR2; j++)
-                    store_chunk<R, LD>(wrow(d, fresh(grow(wave * GPW + u + 16 * j)), rb), ln.off, ln.act, ln.nsym,
+                    store_chunk<R, LD>(wrow(d, WT::uni(grow(vw * GPW + u + 16 * j)), rb), ln.off, ln.act, ln.nsym,
                                        y[u][j]);
         } else {
 #pragma unroll
             for (int j = 0; j < NX; j++)
-                store_chunk<R, LD>(wrow(d, fresh(grow(j)), rb), ln.off, ln.act, ln.nsym, x[j]);
+                store_chunk<R, LD>(wrow(d, WT::uni(grow(j)), rb), ln.off, ln.act, ln.nsym, x[j]);
         }
     };
 
     if constexpr (KIND == W_DH || KIND == W_DL) {
-        split_decode_pass<T, KIND, LD>(x, y, ws, st, ln, gbase, lo, wave, g, cb, my, bits, rowtab, p_B, p_Binv,
-                                        vB, vB + NV * H, vRT, twI, stage_tables);
+        split_decode_pass<T, KIND, LD, PK>(x, y, ws, st, ln, gbase, lo, vw, g, cb, my, bits, rowtab, p_B, p_Binv,
+                                            vB, vB + NV * H, vRT, twI, stage_tables);
         return;
     }
 
@@ -436,7 +492,7 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
             for (int u = 0; u < GPW; u++)
 #pragma unroll
                 for (int j = 0; j < NR2; j++) {
-                    const uint32_t p = grow(wave * GPW + u + 16 * j);
+                    const uint32_t p = grow(vw * GPW + u + 16 * j);
                     load_chunk<R, LD>(wrow(ws.src, p, rb), ln.off, ln.act && (int)p < ws.src_rows, ln.nsym, y[u][j]);
                 }
         }
@@ -466,14 +522,14 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
             if (KIND == W_DPM) {
 #pragma unroll
                 for (int j = 0; j < NC; j++)
-                    store_chunk<R, LD>(wrow(ws.dst, fresh(grow(c + j)), rb), ln.off, ln.act, ln.nsym, z[j]);
+                    store_chunk<R, LD>(wrow(ws.dst, WT::uni(grow(c + j)), rb), ln.off, ln.act, ln.nsym, z[j]);
             } else {
-                pipelined<Tab, NC>([&](int j) { return row_tab<R>(p_Binv, vB, c + j, grow(c + j)); },
+                pipelined<Tab, NC>([&](int j) { return WT::row(p_Binv, vB, c + j, grow(c + j)); },
                                    [&](int j, const Tab &t) {
                                        const uint32_t p = grow(c + j);
                                        if (p)
                                            scale<R>(z[j], t);
-                                       store_chunk<R, LD>(wrow(ws.dst, fresh(p), rb), ln.off, ln.act, ln.nsym, z[j]);
+                                       store_chunk<R, LD>(wrow(ws.dst, WT::uni(p), rb), ln.off, ln.act, ln.nsym, z[j]);
                                    });
             }
         }
@@ -516,14 +572,14 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
         if (KIND == W_DPM) {
 #pragma unroll
             for (int j = 0; j < NX; j++)
-                store_chunk<R, LD>(wrow(ws.dst, fresh(grow(xrow(j))), rb), ln.off, ln.act, ln.nsym, z[j]);
+                store_chunk<R, LD>(wrow(ws.dst, WT::uni(grow(xrow(j))), rb), ln.off, ln.act, ln.nsym, z[j]);
         } else {
-            pipelined<Tab, NX>([&](int j) { return row_tab<R>(p_Binv, vB, xrow(j), grow(xrow(j))); },
+            pipelined<Tab, NX>([&](int j) { return WT::row(p_Binv, vB, xrow(j), grow(xrow(j))); },
                                [&](int j, const Tab &t) {
                                    const uint32_t p = grow(xrow(j));
                                    if (p)
                                        scale<R>(z[j], t);
-                                   store_chunk<R, LD>(wrow(ws.dst, fresh(p), rb), ln.off, ln.act, ln.nsym, z[j]);
+                                   store_chunk<R, LD>(wrow(ws.dst, WT::uni(p), rb), ln.off, ln.act, ln.nsym, z[j]);
                                });
         }
         return;
@@ -531,7 +587,7 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
 
     if (INV_FIRST) {
         if (KIND == W_D1)
-            pipelined<Tab, NX>([&](int j) { return row_tab<R>(rowtab, vRT, xrow(j), grow(xrow(j))); },
+            pipelined<Tab, NX>([&](int j) { return WT::row(rowtab, vRT, xrow(j), grow(xrow(j))); },
                                [&](int j, const Tab &t) { dec_weigh<R>(x[j], rcv[j], t); });
         reg_levels<R, TA, true, SH_ZERO, false>(x, (uint32_t)(NX * g), 0, twI);
         if constexpr (TILED) {
@@ -541,7 +597,7 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
             __syncthreads();
 #pragma unroll
             for (int u = 0; u < GPW; u++) {
-                const int r0 = wave * GPW + u;
+                const int r0 = vw * GPW + u;
 #pragma unroll
                 for (int j = 0; j < NR2; j++)
                     lds_get(my + RS * r0, 16 * j, y[u][j]);
@@ -562,8 +618,8 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
             if constexpr (TILED) {
 #pragma unroll
                 for (int u = 0; u < GPW; u++) {
-                    const int r0 = wave * GPW + u;
-                    pipelined<Tab, NR2>([&](int j) { return row_tab<R>(p_B, vB, r0 + 16 * j, grow(r0 + 16 * j)); },
+                    const int r0 = vw * GPW + u;
+                    pipelined<Tab, NR2>([&](int j) { return WT::row(p_B, vB, r0 + 16 * j, grow(r0 + 16 * j)); },
                                         [&](int j, const Tab &t) {
                                             if (grow(r0 + 16 * j))
                                                 scale<R>(y[u][j], t);
@@ -574,7 +630,7 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
                 __syncthreads();
 #pragma unroll
                 for (int u = 0; u < GPW; u++) {
-                    const int r0 = wave * GPW + u;
+                    const int r0 = vw * GPW + u;
 #pragma unroll
                     for (int j = 0; j < NR2; j++) {
                         uint32_t z[NW];
@@ -595,12 +651,12 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
                                     z[w] ^= v[w];
                             }
                         }
-                        store_chunk<R, LD>(wrow(ws.dst2, fresh(grow(r0 + 16 * j)), rb), ln.off, ln.act, ln.nsym,
+                        store_chunk<R, LD>(wrow(ws.dst2, WT::uni(grow(r0 + 16 * j)), rb), ln.off, ln.act, ln.nsym,
                                            z);
                     }
                 }
             } else {
-                pipelined<Tab, NX>([&](int j) { return row_tab<R>(p_B, vB, j, grow(j)); },
+                pipelined<Tab, NX>([&](int j) { return WT::row(p_B, vB, j, grow(j)); },
                                    [&](int j, const Tab &t) {
                                        if (grow(j))
                                            scale<R>(x[j], t);
@@ -616,7 +672,7 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
 #pragma unroll
                             for (int w = 0; w < NW; w++)
                                 z[w] ^= x[j + (1 << lv)][w];
-                    store_chunk<R, LD>(wrow(ws.dst2, fresh(grow(j)), rb), ln.off, ln.act, ln.nsym, z);
+                    store_chunk<R, LD>(wrow(ws.dst2, WT::uni(grow(j)), rb), ln.off, ln.act, ln.nsym, z);
                 }
             }
             return;
@@ -630,7 +686,7 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
         if constexpr (TILED) {
 #pragma unroll
             for (int u = 0; u < GPW; u++) {
-                const int r0 = wave * GPW + u;
+                const int r0 = vw * GPW + u;
                 reg_levels<R, L2, false, SHF, false>(y[u], (uint32_t)r0, 4, twF);
 #pragma unroll
                 for (int j = 0; j < NR2; j++)
@@ -643,9 +699,9 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
         }
         reg_levels<R, TA, false, SHF, false>(x, (uint32_t)(NX * g), 0, twF);
         if (KIND == W_D5) {
-            pipelined<Tab, NX>([&](int j) { return row_tab<R>(rowtab, vRT, xrow(j), grow(xrow(j))); },
+            pipelined<Tab, NX>([&](int j) { return WT::row(rowtab, vRT, xrow(j), grow(xrow(j))); },
                                [&](int j, const Tab &t) {
-                                   dec_store<R, LD>(x[j], (int)grow(xrow(j)), st, ln, bits, [&](int) { return t; });
+                                   dec_store<R, LD, !PK>(x[j], (int)grow(xrow(j)), st, ln, bits, [&](int) { return t; });
                                });
             return;
         }
@@ -653,86 +709,100 @@ __global__ __launch_bounds__(NB_WIDE_THREADS(T)) __attribute__((amdgpu_waves_per
         for (int j = 0; j < NX; j++) {
             const uint32_t p = grow(xrow(j));
             if ((int)p < ws.dst_rows)
-                store_chunk<R, LD>(wrow(ws.dst, fresh(p), rb), ln.off, ln.act, ln.nsym, x[j]);
+                store_chunk<R, LD>(wrow(ws.dst, WT::uni(p), rb), ln.off, ln.act, ln.nsym, x[j]);
         }
     }
 }
 
-template <int T, int KIND, int LD>
+template <int T, int KIND, int LD, bool PK>
 static hipError_t wide_launch_one(const WideArgs &a, const KPtrs &k, int ntiles, hipStream_t s)
 {
-    const size_t lds = WideLds<T, KIND>::BYTES;
-    hipLaunchKernelGGL((k_wide<T, KIND, LD>), dim3(ntiles), dim3(NB_WIDE_THREADS(T)), lds, s, a, k.tw, k.B, k.Binv,
-                       k.bits, k.rowtabs);
-    return hipGetLastError();
+    if constexpr (PK && !packable(T, KIND)) {
+        return hipErrorInvalidValue;
+    } else {
+        const size_t lds = WideLds<T, KIND, PK>::BYTES;
+        hipLaunchKernelGGL((k_wide<T, KIND, LD, PK>), dim3(ntiles), dim3(NB_WIDE_THREADS_PK(T, PK)), lds, s, a, k.tw,
+                           k.B, k.Binv, k.bits, k.rowtabs);
+        return hipGetLastError();
+    }
 }
 
-template <int T, int KIND, int LD>
+template <int T, int KIND, int LD, bool PK>
 static hipError_t wide_prep_one()
 {
-    return hipFuncSetAttribute((const void *)k_wide<T, KIND, LD>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)WideLds<T, KIND>::BYTES);
+    if constexpr (PK && !packable(T, KIND))
+        return hipSuccess;
+    else
+        return hipFuncSetAttribute((const void *)k_wide<T, KIND, LD, PK>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)WideLds<T, KIND, PK>::BYTES);
 }
 
-template <int KIND, int LD>
+template <int KIND, int LD, bool PK>
 static hipError_t wide_launch_T(int T, const WideArgs &a, const KPtrs &k, int ntiles, hipStream_t s)
 {
     switch (T) {
-    case 4: return wide_launch_one<4, KIND, LD>(a, k, ntiles, s);
-    case 5: return wide_launch_one<5, KIND, LD>(a, k, ntiles, s);
-    case 6: return wide_launch_one<6, KIND, LD>(a, k, ntiles, s);
-    case 7: return wide_launch_one<7, KIND, LD>(a, k, ntiles, s);
-    case 8: return wide_launch_one<8, KIND, LD>(a, k, ntiles, s);
+    case 4: return wide_launch_one<4, KIND, LD, PK>(a, k, ntiles, s);
+    case 5: return wide_launch_one<5, KIND, LD, PK>(a, k, ntiles, s);
+    case 6: return wide_launch_one<6, KIND, LD, PK>(a, k, ntiles, s);
+    case 7: return wide_launch_one<7, KIND, LD, PK>(a, k, ntiles, s);
+    case 8: return wide_launch_one<8, KIND, LD, PK>(a, k, ntiles, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <int KIND, int LD>
+template <int KIND, int LD, bool PK>
 static hipError_t wide_prep_T()
 {
     hipError_t e = hipSuccess, f;
-    if ((f = wide_prep_one<4, KIND, LD>()) != hipSuccess) e = f;
-    if ((f = wide_prep_one<5, KIND, LD>()) != hipSuccess) e = f;
-    if ((f = wide_prep_one<6, KIND, LD>()) != hipSuccess) e = f;
-    if ((f = wide_prep_one<7, KIND, LD>()) != hipSuccess) e = f;
-    if ((f = wide_prep_one<8, KIND, LD>()) != hipSuccess) e = f;
+    if ((f = wide_prep_one<4, KIND, LD, PK>()) != hipSuccess) e = f;
+    if ((f = wide_prep_one<5, KIND, LD, PK>()) != hipSuccess) e = f;
+    if ((f = wide_prep_one<6, KIND, LD, PK>()) != hipSuccess) e = f;
+    if ((f = wide_prep_one<7, KIND, LD, PK>()) != hipSuccess) e = f;
+    if ((f = wide_prep_one<8, KIND, LD, PK>()) != hipSuccess) e = f;
     return e;
 }
 
-template <int LD>
+template <int LD, bool PK>
 static hipError_t wide_launch_ld(int kind, int T, const WideArgs &a, const KPtrs &k, int ntiles, hipStream_t s)
 {
     switch (kind) {
-    case W_E1: return wide_launch_T<W_E1, LD>(T, a, k, ntiles, s);
-    case W_E2: return wide_launch_T<W_E2, LD>(T, a, k, ntiles, s);
-    case W_E2F: return wide_launch_T<W_E2F, LD>(T, a, k, ntiles, s);
-    case W_E3: return wide_launch_T<W_E3, LD>(T, a, k, ntiles, s);
-    case W_D1: return wide_launch_T<W_D1, LD>(T, a, k, ntiles, s);
-    case W_D2: return wide_launch_T<W_D2, LD>(T, a, k, ntiles, s);
-    case W_D3: return wide_launch_T<W_D3, LD>(T, a, k, ntiles, s);
-    case W_DPM: return wide_launch_T<W_DPM, LD>(T, a, k, ntiles, s);
-    case W_D4: return wide_launch_T<W_D4, LD>(T, a, k, ntiles, s);
-    case W_D5: return wide_launch_T<W_D5, LD>(T, a, k, ntiles, s);
-    case W_DH: return wide_launch_T<W_DH, LD>(T, a, k, ntiles, s);
-    case W_DL: return wide_launch_T<W_DL, LD>(T, a, k, ntiles, s);
+    case W_E1: return wide_launch_T<W_E1, LD, PK>(T, a, k, ntiles, s);
+    case W_E2: return wide_launch_T<W_E2, LD, PK>(T, a, k, ntiles, s);
+    case W_E2F: return wide_launch_T<W_E2F, LD, PK>(T, a, k, ntiles, s);
+    case W_E3: return wide_launch_T<W_E3, LD, PK>(T, a, k, ntiles, s);
+    case W_D1: return wide_launch_T<W_D1, LD, PK>(T, a, k, ntiles, s);
+    case W_D2: return wide_launch_T<W_D2, LD, PK>(T, a, k, ntiles, s);
+    case W_D3: return wide_launch_T<W_D3, LD, PK>(T, a, k, ntiles, s);
+    case W_DPM: return wide_launch_T<W_DPM, LD, PK>(T, a, k, ntiles, s);
+    case W_D4: return wide_launch_T<W_D4, LD, PK>(T, a, k, ntiles, s);
+    case W_D5: return wide_launch_T<W_D5, LD, PK>(T, a, k, ntiles, s);
+    case W_DH: return wide_launch_T<W_DH, LD, PK>(T, a, k, ntiles, s);
+    case W_DL: return wide_launch_T<W_DL, LD, PK>(T, a, k, ntiles, s);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t wide_launch(int kind, int ld, int T, const WideArgs &a, const KPtrs &k, int ntiles, hipStream_t s)
+bool wide_packable(int kind, int T) { return packable(T, kind); }
+
+hipError_t wide_launch(int kind, int ld, int T, bool pk, const WideArgs &a, const KPtrs &k, int ntiles, hipStream_t s)
 {
     if (ntiles <= 0)
         return hipSuccess;
-    return ld == LD_VEC ? wide_launch_ld<LD_VEC>(kind, T, a, k, ntiles, s)
-                        : wide_launch_ld<LD_SYM>(kind, T, a, k, ntiles, s);
+    if (pk)
+        return ld == LD_VEC ? wide_launch_ld<LD_VEC, true>(kind, T, a, k, ntiles, s)
+                            : wide_launch_ld<LD_SYM, true>(kind, T, a, k, ntiles, s);
+    return ld == LD_VEC ? wide_launch_ld<LD_VEC, false>(kind, T, a, k, ntiles, s)
+                        : wide_launch_ld<LD_SYM, false>(kind, T, a, k, ntiles, s);
 }
 
 hipError_t wide_prepare()
 {
     hipError_t e = hipSuccess, f;
 #define NB_WPREP(K)                                                                                                \
-    if ((f = wide_prep_T<K, LD_VEC>()) != hipSuccess) e = f;                                                       \
-    if ((f = wide_prep_T<K, LD_SYM>()) != hipSuccess) e = f;
+    if ((f = wide_prep_T<K, LD_VEC, false>()) != hipSuccess) e = f;                                                \
+    if ((f = wide_prep_T<K, LD_SYM, false>()) != hipSuccess) e = f;                                                \
+    if ((f = wide_prep_T<K, LD_VEC, true>()) != hipSuccess) e = f;                                                 \
+    if ((f = wide_prep_T<K, LD_SYM, true>()) != hipSuccess) e = f;
     NB_WPREP(W_E1) NB_WPREP(W_E2) NB_WPREP(W_E2F) NB_WPREP(W_E3) NB_WPREP(W_D1) NB_WPREP(W_D2) NB_WPREP(W_D3)
     NB_WPREP(W_DPM)
     NB_WPREP(W_D4) NB_WPREP(W_D5) NB_WPREP(W_DH) NB_WPREP(W_DL)

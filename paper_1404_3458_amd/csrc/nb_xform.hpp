@@ -6,6 +6,8 @@
 // a += s b), with Delta_i^m(omega_c + omega_l) stored at index c + m, so rows
 // come out in natural order.
 #pragma once
+#include <type_traits>
+
 #include "nb_device.hpp"
 #include "nb_internal.hpp"
 
@@ -41,6 +43,7 @@ enum { SH_ZERO = 0, SH_ALIGNED = 1, SH_GENERAL = 2 };
 template <int R>
 struct TwGlobal {
     static constexpr int TS = Traits<R>::TS;
+    typedef typename Ops<R>::Tab Tab;
     const uint32_t *__restrict__ tw;
     uint32_t l;
     __device__ __forceinline__ uint32_t plus1(int i) const { return ((l >> i) & 1u) ? ~0u : 0u; }
@@ -61,6 +64,7 @@ struct TwGlobal {
 template <int R, int LT>
 struct TwLds {
     static constexpr int TS = Traits<R>::TS, NV = Ops<R>::NV;
+    typedef typename Ops<R>::Tab Tab;
     const uint32_t *__restrict__ tw;
     uint32_t l;
     const uint32_t *vt;
@@ -77,15 +81,35 @@ struct TwLds {
     }
 };
 
-// Cooperative copy (all threads of the block) of the V words of the factor
-// tables TwLds reads: local level i holds the 2^(LT-i-1) entries starting at
+// The same factors with every word of a table staged in LDS (stage_levels
+// with WPE = TAB16) and read per lane: for a wave whose two halves hold rows
+// of different blocks (GF(2^16) only).
+template <int LT>
+struct TwLdsV {
+    typedef Tab16V Tab;
+    uint32_t l;
+    const uint32_t *vt;
+    uint32_t lo = 0;
+    __device__ __forceinline__ uint32_t plus1(int i) const { return ((l >> (lo + i)) & 1u) ? ~0u : 0u; }
+    __device__ __forceinline__ Tab tab(int i, uint32_t c) const
+    {
+        const uint32_t q = ((c ^ (l >> lo)) & ((1u << LT) - 1u)) >> (i + 1);
+        return tab_lds_all(vt + TAB16 * ((1u << LT) - (1u << (LT - i)) + q));
+    }
+};
+
+// Cooperative copy (all threads of the block) of the first WPE words (the V
+// words by default, the whole table with WPE = TAB16) of the factor tables
+// TwLds / TwLdsV read: local level i holds the 2^(LT-i-1) entries starting at
 // table index 2^r - 2^(r-lo-i) + (((gbase ^ l) >> (lo + LT)) << (LT - i - 1)).
-template <int R, int LT>
+template <int R, int LT, int WPE = Ops<R>::NV>
 __device__ __forceinline__ void stage_levels(uint32_t *vt, const uint32_t *__restrict__ tw, uint32_t l, int tid,
                                              int nthreads, uint32_t lo = 0, uint32_t gbase = 0)
 {
-    constexpr int TS = Traits<R>::TS, NV = Ops<R>::NV, H = 1 << LT;
-    constexpr int PER = NV / 2;            // 8-byte pieces per entry
+    constexpr int TS = Traits<R>::TS, NV = WPE, H = 1 << LT;
+    // 16-byte pieces when every table (and the staged copy) is 16-byte aligned
+    typedef typename std::conditional<(TS % 4 == 0 && NV % 4 == 0), uint4, uint2>::type Piece;
+    constexpr int PW = sizeof(Piece) / 4, PER = NV / PW;     // words per piece, pieces per entry
     const uint32_t hi = (gbase ^ l) >> (lo + LT);
     for (int u = tid; u < (H - 1) * PER; u += nthreads) {
         const int e = u / PER, w = u % PER;
@@ -94,23 +118,25 @@ __device__ __forceinline__ void stage_levels(uint32_t *vt, const uint32_t *__res
         const int q = e - (H - (H >> i));
         const int I = (int)lo + i;
         const uint32_t g = (1u << R) - (1u << (R - I)) + (hi << (LT - i - 1)) + (uint32_t)q;
-        const uint2 v = *reinterpret_cast<const uint2 *>(tw + (size_t)TS * g + 2 * w);
-        *reinterpret_cast<uint2 *>(vt + NV * e + 2 * w) = v;
+        const Piece v = *reinterpret_cast<const Piece *>(tw + (size_t)TS * g + PW * w);
+        *reinterpret_cast<Piece *>(vt + NV * e + PW * w) = v;
     }
 }
 
-// Cooperative copy of the V words of `count` perm tables: entries
+// Cooperative copy of the first WPE words of `count` perm tables: entries
 // first + (j << lo) of src for j < count.
-template <int R>
+template <int R, int WPE = Ops<R>::NV>
 __device__ __forceinline__ void stage_rows(uint32_t *vt, const uint32_t *__restrict__ src, int count, int tid,
                                            int nthreads, uint32_t lo = 0, uint32_t first = 0)
 {
-    constexpr int TS = Traits<R>::TS, NV = Ops<R>::NV, PER = NV / 2;
+    constexpr int TS = Traits<R>::TS, NV = WPE;
+    typedef typename std::conditional<(TS % 4 == 0 && NV % 4 == 0), uint4, uint2>::type Piece;
+    constexpr int PW = sizeof(Piece) / 4, PER = NV / PW;
     for (int u = tid; u < count * PER; u += nthreads) {
         const int e = u / PER, w = u % PER;
         const size_t g = (size_t)first + ((size_t)e << lo);
-        const uint2 v = *reinterpret_cast<const uint2 *>(src + (size_t)TS * g + 2 * w);
-        *reinterpret_cast<uint2 *>(vt + NV * e + 2 * w) = v;
+        const Piece v = *reinterpret_cast<const Piece *>(src + (size_t)TS * g + PW * w);
+        *reinterpret_cast<Piece *>(vt + NV * e + PW * w) = v;
     }
 }
 
@@ -206,7 +232,7 @@ template <int R, int T, bool INV, int SH, bool CT_BASE, class TW>
 __device__ __forceinline__ void reg_levels(uint32_t (*x)[Traits<R>::NW], uint32_t base, int LO, const TW &tw,
                                            uint64_t need = ~0ull)
 {
-    typedef typename Ops<R>::Tab Tab;
+    typedef typename TW::Tab Tab;
     constexpr int NW = Traits<R>::NW, NB = (1 << T) - 1;
     static_assert(T <= 6, "a 64-bit row mask");
     auto used = [&](int t, int blk) {
@@ -316,12 +342,13 @@ __device__ __forceinline__ void dec_weigh(uint32_t *x, bool rcv, const typename 
 }
 
 // Decode step 6 (eq. F(j)) for one point: erased stored rows get
-// Phi^d[p] / Pi'(omega_p); tabf(p) yields the point's perm table.
-template <int R, int LD, class TABF>
+// Phi^d[p] / Pi'(omega_p); tabf(p) yields the point's perm table.  UNI:
+// the point is the same for the whole wave (else per lane).
+template <int R, int LD, bool UNI = true, class TABF>
 __device__ __forceinline__ void dec_store(const uint32_t *v, int p_, const DevStripe &st, const Lane &ln,
                                           const uint32_t *__restrict__ bits, const TABF &tabf)
 {
-    const int p = (int)fresh((uint32_t)p_);
+    const int p = UNI ? (int)fresh((uint32_t)p_) : p_;
     if (point_bit(bits + bitmap_words(st.np), p)) {
         const int t = point_row(p, st);
         uint32_t o[Traits<R>::NW];

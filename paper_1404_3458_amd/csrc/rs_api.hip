@@ -11,9 +11,12 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <mutex>
 #include <new>
 #include <vector>
+
+#include <emmintrin.h>
 
 namespace nb {
 hipError_t init_tables(int r, const uint32_t *d_basis, uint32_t *d_Wv, uint32_t *d_S, uint32_t *d_wp,
@@ -42,7 +45,8 @@ hipError_t pass_launch(int r, int ld, int T, bool inv, bool gen_l, const PassArg
                        uint32_t nblocks, hipStream_t s);
 hipError_t dpart_launch(int r, int ld, int T, const DerivPassArgs &a, const KPtrs &k, uint32_t nblocks,
                         hipStream_t s);
-hipError_t wide_launch(int kind, int ld, int T, const WideArgs &a, const KPtrs &k, int ntiles, hipStream_t s);
+hipError_t wide_launch(int kind, int ld, int T, bool pk, const WideArgs &a, const KPtrs &k, int ntiles, hipStream_t s);
+bool wide_packable(int kind, int T);
 hipError_t wide_prepare();
 }  // namespace nb
 
@@ -293,6 +297,7 @@ struct ColPart {
     int ld;
     int col0;
     int ntiles;
+    long chunks;        // 4-column chunks of the part
 };
 
 int ntiles_of_chunks(long chunks) { return (int)((chunks + 63) / 64); }
@@ -316,14 +321,14 @@ ColParts col_parts(bool aligned, int ncols)
     if (ncols <= 0)
         return v;
     if (!aligned) {
-        v.p[v.n++] = {LD_SYM, 0, ntiles_of_chunks((ncols + 3) / 4)};
+        v.p[v.n++] = {LD_SYM, 0, ntiles_of_chunks((ncols + 3) / 4), (ncols + 3) / 4};
         return v;
     }
     const int full = ncols / 4;
     if (full)
-        v.p[v.n++] = {LD_VEC, 0, ntiles_of_chunks(full)};
+        v.p[v.n++] = {LD_VEC, 0, ntiles_of_chunks(full), full};
     if (ncols % 4)
-        v.p[v.n++] = {LD_SYM, 4 * full, 1};
+        v.p[v.n++] = {LD_SYM, 4 * full, 1, 1};
     return v;
 }
 
@@ -361,7 +366,7 @@ int validate_stripe(rs_ctx *ctx, const rs_stripe_desc &d, bool decode, const uin
             return RS_EINVAL;
         int e = 0;
         for (int t = 0; t < d.n; t++)
-            e += mask[t] ? 1 : 0;
+            e += mask[t] != 0;
         if (e > d.n - d.k)
             return RS_ETOOMANY;
         pl.erasures = e;
@@ -570,6 +575,7 @@ struct Entry {
 // the uploaded array.
 struct WideLaunch {
     int kind, ld, T, lo, blk;
+    bool pk;                     // packed: rows of at most 32 chunks, two row sets per wave
     size_t first, count;
     int ntiles;
 };
@@ -687,10 +693,17 @@ void plan_wide(const std::vector<Plan> &plans, const std::vector<int> &idx, bool
                 }
             }
             for (const Step &stp : steps) {
-                for (int ld = 0; ld < 2; ld++) {
+                // one launch per row-access variant, plain or packed (parts
+                // of at most 32 chunks, which fill half a wave)
+                for (int var = 0; var < 4; var++) {
+                    const int ld = var & 1;
+                    const bool pk = var >> 1;
+                    if (pk && !wide_packable(stp.kind, stp.T))
+                        continue;
                     WideLaunch wl;
                     wl.kind = stp.kind;
                     wl.ld = ld;
+                    wl.pk = pk;
                     wl.T = stp.T;
                     wl.lo = stp.lo;
                     wl.blk = stp.blk;
@@ -755,13 +768,14 @@ void plan_wide(const std::vector<Plan> &plans, const std::vector<int> &idx, bool
                         case W_DL: w.src = Z; w.src2 = A; break;
                         }
                         for (const ColPart &cp : col_parts(p.aligned, d.ncols)) {
-                            if (cp.ld != ld)
+                            const bool part_pk = cp.chunks <= 32 && wide_packable(stp.kind, stp.T);
+                            if (cp.ld != ld || part_pk != pk)
                                 continue;
                             WideStripe e = w;
                             e.st.col0 = cp.col0;
-                            e.nct = cp.ntiles;
+                            e.nct = part_pk ? 1 : cp.ntiles;
                             e.tile0 = tiles;
-                            tiles += (1 << (N - stp.T)) * cp.ntiles;
+                            tiles += (1 << (N - stp.T)) * e.nct;
                             wp.descs.push_back(e);
                         }
                     }
@@ -809,11 +823,38 @@ struct CodecPlan {
     bool empty() const { return fused.empty() && wp.launches.empty() && copies.empty() && m_small == 0 && loc_large.empty(); }
 };
 
-// Validate the call and build its plan.  `scratch` gives the scratch of the
-// 8-level passes: called with (nullptr, &need) to size it, then with a
-// buffer of that size.
+// Scratch of the pass pipelines: get(need, &base) yields `need` bytes of
+// device memory, or an error code.
+typedef std::function<int(size_t, uint8_t **)> ScratchFn;
+
+// The point bitmaps of one stripe: bit p of rx (received) or er (erased) for
+// every stored row; message row t is point t, parity row t point k' + t - k.
+// 16 rows at a time where the points of a run start on a word boundary.
+static void pack_points(const uint8_t *mk, int t0, int count, int pt0, uint32_t *rx, uint32_t *er)
+{
+    int i = 0;
+    if ((pt0 & 31) == 0) {
+        const __m128i zero = _mm_setzero_si128();
+        for (; i + 16 <= count; i += 16) {
+            const __m128i v = _mm_loadu_si128(reinterpret_cast<const __m128i *>(mk + t0 + i));
+            const uint32_t z = (uint32_t)_mm_movemask_epi8(_mm_cmpeq_epi8(v, zero));   // bit j: row not erased
+            const int pt = pt0 + i;
+            rx[pt >> 5] |= z << (pt & 31);
+            er[pt >> 5] |= (~z & 0xFFFFu) << (pt & 31);
+        }
+    }
+    for (; i < count; i++) {
+        const int pt = pt0 + i;
+        uint32_t *w = mk[t0 + i] ? er : rx;
+        w[pt >> 5] |= 1u << (pt & 31);
+    }
+}
+
+// Validate the call and build its plan.  get_scratch is called once, with
+// the size the pass pipelines need, when they need any (an empty function:
+// such calls fail with RS_ESHAPE).
 int build_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, int count, bool decode,
-                uint8_t *scratch, size_t *scratch_need, CodecPlan &cp)
+                const ScratchFn &get_scratch, CodecPlan &cp)
 {
     if (!ctx || (count > 0 && !descs) || count < 0)
         return RS_EINVAL;
@@ -925,11 +966,14 @@ int build_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, 
         int sc[17];
         for (int N = 0; N < 17; N++)
             sc[N] = ctx->sched[decode ? 1 : 0][N].load(std::memory_order_relaxed);
-        plan_wide(plans, widx, decode, scratch, sc, cp.wp);
-        if (scratch_need)
-            *scratch_need = cp.wp.scratch;
-    } else if (scratch_need) {
-        *scratch_need = 0;
+        plan_wide(plans, widx, decode, nullptr, sc, cp.wp);        // sizes the scratch
+        if (cp.wp.scratch) {
+            uint8_t *base = nullptr;
+            const int rc = get_scratch ? get_scratch(cp.wp.scratch, &base) : RS_ESHAPE;
+            if (rc)
+                return rc;
+            plan_wide(plans, widx, decode, base, sc, cp.wp);
+        }
     }
 
     // Arena: [entries | locator stripes | point bitmaps | pass descriptors |
@@ -954,12 +998,8 @@ int build_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, 
             const uint8_t *mk = masks + p.mask_src;
             const int W = (p.ds.np + 31) / 32;
             uint32_t *rx = bits + p.ds.bits_off, *er = rx + W;
-            // message rows are points 0..k-1, parity row t is point k' + t
-            for (int t = 0; t < p.ds.n; t++) {
-                const int pt = t < p.ds.k ? t : p.ds.kp + (t - p.ds.k);
-                uint32_t *w = mk[t] ? er : rx;
-                w[pt >> 5] |= 1u << (pt & 31);
-            }
+            pack_points(mk, 0, p.ds.k, 0, rx, er);
+            pack_points(mk, p.ds.k, p.ds.n - p.ds.k, p.ds.kp, rx, er);
         }
     }
     return RS_OK;
@@ -1098,7 +1138,7 @@ int exec_codec(rs_ctx *ctx, const CodecPlan &cp, uint8_t *dev, hipStream_t strea
         wa.lo = wl.lo;
         wa.blk = wl.blk;
         wa.ts = sm ? sm->slots + sm->wide_off[i] : nullptr;
-        if (dev_err(ctx, wide_launch(wl.kind, wl.ld, wl.T, wa, kp, wl.ntiles, stream)))
+        if (dev_err(ctx, wide_launch(wl.kind, wl.ld, wl.T, wl.pk, wa, kp, wl.ntiles, stream)))
             return RS_EDEVICE;
     }
     if (sm && dev_err(ctx, stamp_reduce(ts, sm->slots, sm->seg_ptr, sm->segs, nstripes, stream)))
@@ -1111,31 +1151,27 @@ int run_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, in
 {
     if (!ctx)
         return RS_EINVAL;
-    CodecPlan cp;
-    size_t need = 0;
-    int rc = build_codec(ctx, descs, masks, count, decode, nullptr, &need, cp);
-    if (rc)
-        return rc;
-    if (cp.empty())
-        return RS_OK;
     DeviceGuard guard(ctx->device);
     if (!guard.ok)
         return RS_EDEVICE;
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (ctx->sticky)
         return ctx->sticky;
-    Scratch *sc = get_scratch(ctx, stream);
-    if (!sc)
+    Scratch *sc = nullptr;
+    // the stream's scratch, grown to what the pass pipelines need
+    auto get_sc = [&](size_t need, uint8_t **base) -> int {
+        if (!sc && !(sc = get_scratch(ctx, stream)))
+            return RS_ENOMEM;
+        return big_scratch(sc, need, base);
+    };
+    CodecPlan cp;
+    int rc = build_codec(ctx, descs, masks, count, decode, get_sc, cp);
+    if (rc)
+        return rc;
+    if (cp.empty())
+        return RS_OK;
+    if (!sc && !(sc = get_scratch(ctx, stream)))
         return RS_ENOMEM;
-    if (need) {
-        uint8_t *scr = nullptr;
-        rc = big_scratch(sc, need, &scr);
-        if (rc)
-            return rc;
-        rc = build_codec(ctx, descs, masks, count, decode, scr, nullptr, cp);
-        if (rc)
-            return rc;
-    }
     rc = ensure_dev(sc, &sc->dev, &sc->dev_cap, cp.dev_bytes);
     if (rc)
         return rc;
@@ -1704,13 +1740,12 @@ __attribute__((visibility("default"))) int rs_decode_static(rs_ctx *ctx, int n, 
     d.in = shards;
     d.out = out;
     CodecPlan cp;
-    size_t need = 0;
-    rc = build_codec(ctx, &d, erasure_mask, 1, true, nullptr, &need, cp);
+    rc = build_codec(ctx, &d, erasure_mask, 1, true, ScratchFn(), cp);   // no pass pipelines: no scratch
     if (rc)
         return rc;
     if (cp.empty())
         return RS_OK;
-    if (need || cp.dev_bytes > STATIC_SCRATCH_BYTES || cp.host.size() > sizeof(uint32_t) * STATIC_IMAGE_WORDS)
+    if (cp.dev_bytes > STATIC_SCRATCH_BYTES || cp.host.size() > sizeof(uint32_t) * STATIC_IMAGE_WORDS)
         return RS_ESHAPE;
     DeviceGuard guard(ctx->device);
     if (!guard.ok)
@@ -1944,19 +1979,17 @@ static int plan_batch(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *m
         return RS_ENOMEM;
     pl->ctx = ctx;
     pl->count = count;
-    size_t need = 0;
-    int rc = build_codec(ctx, descs, masks, count, decode, nullptr, &need, pl->cp);
     DeviceGuard guard(ctx->device);
-    if (!rc && !guard.ok)
-        rc = RS_EDEVICE;
-    if (!rc && need) {
-        if (hipMalloc((void **)&pl->scratch, need) != hipSuccess) {
-            pl->scratch = nullptr;
-            rc = RS_ENOMEM;
-        } else {
-            rc = build_codec(ctx, descs, masks, count, decode, pl->scratch, nullptr, pl->cp);
-        }
-    }
+    int rc = guard.ok ? RS_OK : RS_EDEVICE;
+    if (!rc)                                    // the plan's own scratch for its pass pipelines
+        rc = build_codec(ctx, descs, masks, count, decode, [&](size_t need, uint8_t **base) -> int {
+            if (hipMalloc((void **)&pl->scratch, need) != hipSuccess) {
+                pl->scratch = nullptr;
+                return RS_ENOMEM;
+            }
+            *base = pl->scratch;
+            return RS_OK;
+        }, pl->cp);
     if (!rc && pl->cp.dev_bytes) {
         if (hipMalloc((void **)&pl->arena, pl->cp.dev_bytes) != hipSuccess) {
             pl->arena = nullptr;

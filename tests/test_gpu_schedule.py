@@ -20,7 +20,9 @@ pytestmark = pytest.mark.gpu
 ENC_SHAPES = [(1024, 512), (2048, 1024), (4096, 2048), (8192, 4096), (16384, 8192)]   # N = lg k' = 9 .. 13
 DEC_SHAPES = [(512, 256), (300, 200), (1024, 512), (2048, 1024), (4096, 2048), (8192, 4096),
               (5000, 4000)]                                                            # lg n' = 9 .. 13
-NCOLS = (260, 37)     # a whole and a ragged tile with 8-byte-aligned rows; unaligned rows (74-byte rows)
+# a whole and a ragged tile with 8-byte-aligned rows; unaligned rows (74-byte rows); rows of 124 symbols
+# (248 bytes, aligned), which fill only half a wave and run the packed passes (as do the 74-byte rows)
+NCOLS = (260, 37, 124)
 
 
 def _cases(shapes, size_of):
@@ -68,7 +70,7 @@ def test_decode_every_split(cs, n, k, N, T1):
         cws, masks, ds = [], [], []
         for i, m in enumerate(_stripes(n, k, 100 + sum(v << (4 * q) for q, v in enumerate(T1)))):
             cw = np.concatenate([m, oracle.encode(16, n, k, m)])
-            mask = synth.erasure_mask(synth.key(61, n, k, len(T1), T1[0], i), n, [n - k, (n - k) // 2][i])
+            mask = synth.erasure_mask(synth.key(61, n, k, len(T1), T1[0], i), n, [n - k, (n - k) // 2, 1][i])
             rx = cw.copy()
             rx[mask == 1] = 0x5A
             cws.append(cw)
