@@ -126,10 +126,20 @@ template <> struct WTab<true> {
 
 // LDS of a pass: the group tile, then the staged words of the factor tables
 // (a second set for W_E2's forward part) and of the per-point tables.
+// Half-tile exchange: plain passes on groups of 32 to 128 rows hold a tile
+// of one word per row and lane and move the two words of each row in two
+// rounds, which halves the tile and lets more workgroups share a CU (the
+// partial-sum passes of longer pipelines keep the whole tile).
+__host__ __device__ constexpr bool half_tile(int T, int kind, bool pk)
+{
+    return !pk && T >= 5 && T <= 7 && kind != W_D2 && kind != W_D3 && kind != W_DPM;
+}
+
 template <int T, int KIND, bool PK = false>
 struct WideLds {
     static constexpr int R = 16, H = 1 << T, NV = WTab<PK>::WPE, NW = Traits<R>::NW;
-    static constexpr int TILE = T > WREG ? H * (PK ? 32 : 64) * NW : 0;
+    static constexpr bool HALF = half_tile(T, KIND, PK);
+    static constexpr int TILE = T > WREG ? H * (PK ? 32 : 64) * (HALF ? 1 : NW) : 0;
     static constexpr int EX = (KIND == W_D3 || KIND == W_DPM) ? 0 : H - 1;
     static constexpr int EX2 = KIND == W_E2 ? H - 1 : 0;
     static constexpr int EB = (KIND == W_D2 || KIND == W_D3) ? H : (KIND == W_DH || KIND == W_DL) ? 2 * H : 0;
@@ -147,7 +157,7 @@ struct WideLds {
 // the lane's views of the LDS tile.  The part's derivative factors are
 // B_(p << lo) and its inverse (staged at vb / vbi), local index p.  PK: a
 // packed pass (wave and g are then per-lane virtual wave indices).
-template <int T, int KIND, int LD, bool PK, class TW, class STAGE>
+template <int T, int KIND, int LD, bool PK, bool HALF, class TW, class STAGE>
 __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y)[T > WREG ? (1 << (T - 4)) : 1][2],
                                                   const WideStripe &ws, const DevStripe &st, const Lane &ln,
                                                   uint32_t gbase, uint32_t lo, int wave, int g, uint32_t *cb,
@@ -164,7 +174,9 @@ __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y
     constexpr bool TILED = T > WREG;
     static_assert(TILED || !PK, "packed passes are tiled");
     constexpr int L2 = TILED ? T - 4 : 0, NR2 = 1 << L2, GPW = TILED ? 16 >> L2 : 1;
-    constexpr int RS = (PK ? 32 : 64) * NW;
+    // tile row stride in words (HALF: one word per lane, cb / my then point
+    // at that layout)
+    constexpr int RS = HALF ? 64 : (PK ? 32 : 64) * NW;
     const uint64_t rb = st.row_bytes;
     auto grow = [&](int p) -> uint32_t { return gbase + ((uint32_t)p << lo); };
     auto lds_put = [&](uint32_t *base, int rows, const uint32_t *v) {
@@ -240,18 +252,35 @@ __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y
                 load_chunk<R, LD>(wrow(ws.src, grow(16 * g + j), rb), ln.off, ln.act, ln.nsym, x[j]);
             stage_tables();
             reg_levels<R, 4, true, SH_ZERO, false>(x, (uint32_t)(16 * g), 0, tw);
+            if constexpr (HALF) {
 #pragma unroll
-            for (int j = 0; j < 16; j++)
-                lds_put(cb, j, x[j]);
-            __syncthreads();
+                for (int w = 0; w < NW; w++) {
+                    if (w)
+                        __syncthreads();
 #pragma unroll
-            for (int u = 0; u < GPW; u++) {
-                const int r0 = wave * GPW + u;
+                    for (int j = 0; j < 16; j++)
+                        cb[RS * j] = x[j][w];
+                    __syncthreads();
 #pragma unroll
-                for (int j = 0; j < NR2; j++)
-                    lds_get(my + RS * r0, 16 * j, y[u][j]);
-                reg_levels<R, L2, true, SH_ZERO, false>(y[u], (uint32_t)r0, 4, tw);
+                    for (int u = 0; u < GPW; u++)
+#pragma unroll
+                        for (int j = 0; j < NR2; j++)
+                            y[u][j][w] = my[RS * (wave * GPW + u + 16 * j)];
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 16; j++)
+                    lds_put(cb, j, x[j]);
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < GPW; u++)
+#pragma unroll
+                    for (int j = 0; j < NR2; j++)
+                        lds_get(my + RS * (wave * GPW + u), 16 * j, y[u][j]);
             }
+#pragma unroll
+            for (int u = 0; u < GPW; u++)
+                reg_levels<R, L2, true, SH_ZERO, false>(y[u], (uint32_t)(wave * GPW + u), 4, tw);
         } else {
 #pragma unroll
             for (int u = 0; u < GPW; u++) {
@@ -273,32 +302,70 @@ __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y
                                 [&](int j, const Tab &t) {
                                     if (r0 + 16 * j)
                                         scale<R>(d[u][j], t);
-                                    lds_put(my + RS * r0, 16 * j, d[u][j]);
+                                    if constexpr (!HALF)
+                                        lds_put(my + RS * r0, 16 * j, d[u][j]);
                                 });
         }
-        __syncthreads();
+        // the sums over the rows p + 2^l with bit l of p clear: partners
+        // 16 * 2^l away in registers, 2^l away (l < 4) in other waves' tile
+        // rows; in place, j ascending: row j's sum reads only rows above it
+        if constexpr (HALF) {
+#pragma unroll
+            for (int w = 0; w < NW; w++) {
+                if (w)
+                    __syncthreads();
+#pragma unroll
+                for (int u = 0; u < GPW; u++)
+#pragma unroll
+                    for (int j = 0; j < NR2; j++)
+                        my[RS * (wave * GPW + u + 16 * j)] = d[u][j][w];
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < GPW; u++) {
+                    const int r0 = wave * GPW + u;
+#pragma unroll
+                    for (int j = 0; j < NR2; j++) {
+                        uint32_t z = 0u;
+#pragma unroll
+                        for (int l = 0; l < L2; l++)
+                            if (!((j >> l) & 1))
+                                z ^= d[u][j + (1 << l)][w];
+#pragma unroll
+                        for (int l = 0; l < 4; l++)
+                            if (!((r0 >> l) & 1))
+                                z ^= my[RS * (r0 + (1 << l) + 16 * j)];
+                        d[u][j][w] = z;
+                    }
+                }
+            }
+        } else {
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < GPW; u++) {
+                const int r0 = wave * GPW + u;
+#pragma unroll
+                for (int j = 0; j < NR2; j++) {
+                    uint32_t z[NW] = {0u, 0u};
+#pragma unroll
+                    for (int l = 0; l < L2; l++)
+                        if (!((j >> l) & 1))
+                            xorv(z, d[u][j + (1 << l)]);
+#pragma unroll
+                    for (int l = 0; l < 4; l++) {
+                        if (!((r0 >> l) & 1)) {
+                            uint32_t v[NW];
+                            lds_get(my + RS * r0, (1 << l) + 16 * j, v);
+                            xorv(z, v);
+                        }
+                    }
+                    d[u][j][0] = z[0];
+                    d[u][j][1] = z[1];
+                }
+            }
+        }
 #pragma unroll
         for (int u = 0; u < GPW; u++) {
             const int r0 = wave * GPW + u;
-            // in place, j ascending: row j's sum reads only rows above it
-#pragma unroll
-            for (int j = 0; j < NR2; j++) {
-                uint32_t z[NW] = {0u, 0u};
-#pragma unroll
-                for (int l = 0; l < L2; l++)
-                    if (!((j >> l) & 1))
-                        xorv(z, d[u][j + (1 << l)]);
-#pragma unroll
-                for (int l = 0; l < 4; l++) {
-                    if (!((r0 >> l) & 1)) {
-                        uint32_t v[NW];
-                        lds_get(my + RS * r0, (1 << l) + 16 * j, v);
-                        xorv(z, v);
-                    }
-                }
-                d[u][j][0] = z[0];
-                d[u][j][1] = z[1];
-            }
             pipelined<Tab, NR2>([&](int j) { return WT::row(p_Binv, vbi, r0 + 16 * j,
                                                                (uint32_t)(r0 + 16 * j) << lo); },
                                 [&](int j, const Tab &t) {
@@ -310,14 +377,29 @@ __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y
             reg_levels<R, L2, false, SH_ZERO, false>(y[u], (uint32_t)r0, 4, tw);
         }
         __syncthreads();                             // every partner read is done
+        if constexpr (HALF) {
 #pragma unroll
-        for (int u = 0; u < GPW; u++) {
-            const int r0 = wave * GPW + u;
+            for (int w = 0; w < NW; w++) {
+                if (w)
+                    __syncthreads();
 #pragma unroll
-            for (int j = 0; j < NR2; j++)
-                lds_put(my + RS * r0, 16 * j, y[u][j]);
+                for (int u = 0; u < GPW; u++)
+#pragma unroll
+                    for (int j = 0; j < NR2; j++)
+                        my[RS * (wave * GPW + u + 16 * j)] = y[u][j][w];
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < 16; j++)
+                    x[j][w] = cb[RS * j];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < GPW; u++)
+#pragma unroll
+                for (int j = 0; j < NR2; j++)
+                    lds_put(my + RS * (wave * GPW + u), 16 * j, y[u][j]);
+            __syncthreads();
         }
-        __syncthreads();
         if (KIND == W_DL) {
             // only the 16 consecutive rows that hold an erased stored point
             // need the last levels
@@ -327,9 +409,11 @@ __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y
             if (PK ? !__builtin_amdgcn_ballot_w64(need != 0u) : !fresh(need))
                 return;
         }
+        if constexpr (!HALF) {
 #pragma unroll
-        for (int j = 0; j < 16; j++)
-            lds_get(cb, j, x[j]);
+            for (int j = 0; j < 16; j++)
+                lds_get(cb, j, x[j]);
+        }
         reg_levels<R, 4, false, SH_ZERO, false>(x, (uint32_t)(16 * g), 0, tw);
         if (KIND == W_DH) {
 #pragma unroll
@@ -346,7 +430,7 @@ __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y
 }
 
 template <int T, int KIND, int LD, bool PK>
-__global__ __launch_bounds__(NB_WIDE_THREADS_PK(T, PK)) __attribute__((amdgpu_waves_per_eu(PK ? 2 : 4))) void k_wide(
+__global__ __launch_bounds__(NB_WIDE_THREADS_PK(T, PK)) __attribute__((amdgpu_waves_per_eu(PK ? 2 : (half_tile(T, KIND, PK) && KIND != W_E2 && KIND != W_DL) ? 5 : 4))) void k_wide(
     WideArgs a, const uint32_t *__restrict__ p_tw, const uint32_t *__restrict__ p_B,
     const uint32_t *__restrict__ p_Binv, const uint32_t *__restrict__ p_bits, const uint32_t *__restrict__ p_rowtabs)
 {
@@ -418,8 +502,9 @@ __global__ __launch_bounds__(NB_WIDE_THREADS_PK(T, PK)) __attribute__((amdgpu_wa
     const auto twI = WT::template tw<T>(p_tw, 0u, vX, lo, gbase);
     const auto twF = WT::template tw<T>(p_tw, lf, KIND == W_E2 ? vX2 : vX, lo, gbase);
 
-    constexpr int RS = (PK ? 32 : 64) * NW;
-    uint32_t *const my = lds + (PK ? (lane & 31) : lane) * NW;
+    constexpr bool HALF = LY::HALF;                // tile of one word per row and lane
+    constexpr int RS = HALF ? 64 : (PK ? 32 : 64) * NW;       // tile row stride in words
+    uint32_t *const my = lds + (PK ? (lane & 31) : lane) * (HALF ? 1 : NW);
     auto lds_put = [&](uint32_t *base, int rows, const uint32_t *v) {
         uint32_t *p = base + RS * rows;
         *reinterpret_cast<uint2 *>(p) = make_uint2(v[0], v[1]);
@@ -452,6 +537,65 @@ __global__ __launch_bounds__(NB_WIDE_THREADS_PK(T, PK)) __attribute__((amdgpu_wa
     uint32_t x[NX][NW];                             // consecutive-phase registers (local rows NX g + j)
     uint32_t y[GPW][NR2][NW];                       // stride-phase registers (local rows r0 + 16 j)
     auto xrow = [&](int j) { return NX * g + j; };
+    // The two register groupings through the LDS tile: consecutive rows x
+    // to stride groups y, and back (each wave first writes the tile rows it
+    // alone has read, so no barrier is needed before the first writes).
+    auto to_stride = [&]() {
+        if constexpr (HALF) {
+#pragma unroll
+            for (int w = 0; w < NW; w++) {
+                if (w)
+                    __syncthreads();
+#pragma unroll
+                for (int j = 0; j < 16; j++)
+                    cb[RS * j] = x[j][w];
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < GPW; u++)
+#pragma unroll
+                    for (int j = 0; j < NR2; j++)
+                        y[u][j][w] = my[RS * (vw * GPW + u + 16 * j)];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 16; j++)
+                lds_put(cb, j, x[j]);
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < GPW; u++)
+#pragma unroll
+                for (int j = 0; j < NR2; j++)
+                    lds_get(my + RS * (vw * GPW + u), 16 * j, y[u][j]);
+        }
+    };
+    auto to_consecutive = [&]() {
+        if constexpr (HALF) {
+#pragma unroll
+            for (int w = 0; w < NW; w++) {
+                if (w)
+                    __syncthreads();
+#pragma unroll
+                for (int u = 0; u < GPW; u++)
+#pragma unroll
+                    for (int j = 0; j < NR2; j++)
+                        my[RS * (vw * GPW + u + 16 * j)] = y[u][j][w];
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < 16; j++)
+                    x[j][w] = cb[RS * j];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < GPW; u++)
+#pragma unroll
+                for (int j = 0; j < NR2; j++)
+                    lds_put(my + RS * (vw * GPW + u), 16 * j, y[u][j]);
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < 16; j++)
+                lds_get(cb, j, x[j]);
+        }
+    };
 
     // Rows of the data once it sits in stride registers (TILED) or in x.
     auto store_data = [&](uint8_t *d) {
@@ -470,7 +614,7 @@ __global__ __launch_bounds__(NB_WIDE_THREADS_PK(T, PK)) __attribute__((amdgpu_wa
     };
 
     if constexpr (KIND == W_DH || KIND == W_DL) {
-        split_decode_pass<T, KIND, LD, PK>(x, y, ws, st, ln, gbase, lo, vw, g, cb, my, bits, rowtab, p_B, p_Binv,
+        split_decode_pass<T, KIND, LD, PK, HALF>(x, y, ws, st, ln, gbase, lo, vw, g, cb, my, bits, rowtab, p_B, p_Binv,
                                             vB, vB + NV * H, vRT, twI, stage_tables);
         return;
     }
@@ -591,18 +735,10 @@ __global__ __launch_bounds__(NB_WIDE_THREADS_PK(T, PK)) __attribute__((amdgpu_wa
                                [&](int j, const Tab &t) { dec_weigh<R>(x[j], rcv[j], t); });
         reg_levels<R, TA, true, SH_ZERO, false>(x, (uint32_t)(NX * g), 0, twI);
         if constexpr (TILED) {
+            to_stride();
 #pragma unroll
-            for (int j = 0; j < 16; j++)
-                lds_put(cb, j, x[j]);
-            __syncthreads();
-#pragma unroll
-            for (int u = 0; u < GPW; u++) {
-                const int r0 = vw * GPW + u;
-#pragma unroll
-                for (int j = 0; j < NR2; j++)
-                    lds_get(my + RS * r0, 16 * j, y[u][j]);
-                reg_levels<R, L2, true, SH_ZERO, false>(y[u], (uint32_t)r0, 4, twI);
-            }
+            for (int u = 0; u < GPW; u++)
+                reg_levels<R, L2, true, SH_ZERO, false>(y[u], (uint32_t)(vw * GPW + u), 4, twI);
         }
         if (KIND == W_E1 || KIND == W_D1) {
             store_data(ws.dst);
@@ -685,17 +821,9 @@ __global__ __launch_bounds__(NB_WIDE_THREADS_PK(T, PK)) __attribute__((amdgpu_wa
     if (FWD) {
         if constexpr (TILED) {
 #pragma unroll
-            for (int u = 0; u < GPW; u++) {
-                const int r0 = vw * GPW + u;
-                reg_levels<R, L2, false, SHF, false>(y[u], (uint32_t)r0, 4, twF);
-#pragma unroll
-                for (int j = 0; j < NR2; j++)
-                    lds_put(my + RS * r0, 16 * j, y[u][j]);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < 16; j++)
-                lds_get(cb, j, x[j]);
+            for (int u = 0; u < GPW; u++)
+                reg_levels<R, L2, false, SHF, false>(y[u], (uint32_t)(vw * GPW + u), 4, twF);
+            to_consecutive();
         }
         reg_levels<R, TA, false, SHF, false>(x, (uint32_t)(NX * g), 0, twF);
         if (KIND == W_D5) {
