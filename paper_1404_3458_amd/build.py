@@ -19,8 +19,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librs_nb.so")
-SOURCES = ["nb_fused16.hip", "nb_fused8.hip", "nb_init.hip", "nb_pass.hip", "nb_wide.hip", "nb_poly.hip", "rs_api.hip",
-           "rs_server.hip"]
+# longest first, for the parallel compile
+SOURCES = ["nb_wide.hip", "nb_fused16.hip", "nb_wide_plain.hip", "nb_fused8.hip", "nb_init.hip", "nb_pass.hip",
+           "nb_poly.hip", "rs_api.hip", "rs_server.hip"]
 ARCH = os.environ.get("RS_NB_ARCH", "gfx950")
 
 

@@ -118,6 +118,7 @@ struct WideArgs {
     int32_t nstripes;
     int32_t lo;               // groups are rows gbase + (j << lo)
     int32_t blk;              // encode: parity block, transformed at shift blk * k'
+    uint32_t l;               // plain transform passes: the shift
     uint64_t *ts;             // completion stamp slots of this launch (one per workgroup), or null
 };
 

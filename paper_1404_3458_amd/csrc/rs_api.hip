@@ -65,7 +65,7 @@ constexpr int PASS_MAX_T_FWD = 5, PASS_MAX_T_INV = 4;
 constexpr int LOC_ONE_WG_MAX = 4096; // larger mother codes use the multi-workgroup locator
 // pass kinds of nb_wide.hip
 enum { W_E1 = 0, W_E2 = 1, W_E2F = 2, W_E3 = 3, W_D1 = 4, W_D2 = 5, W_D3 = 6, W_D4 = 7, W_D5 = 8, W_DPM = 9,
-       W_DH = 10, W_DL = 11 };
+       W_DH = 10, W_DL = 11, W_PI = 12, W_PF = 13, W_PFM = 14 };
 // scratch of the 8-level pass pipelines: stripes are processed in chunks
 // whose scratch fits this budget (a stripe larger than it runs alone)
 constexpr size_t WIDE_SCRATCH_BUDGET = (size_t)2 << 30;
@@ -394,10 +394,19 @@ int validate_stripe(rs_ctx *ctx, const rs_stripe_desc &d, bool decode, const uin
 // passes of up to 4 levels.  The first pass reads `src` (src_rows rows, the
 // rest zero), every pass writes `work`, except that the last pass writes
 // rows [dst_lo, dst_hi) to `final_dst` when it is given.
-int run_passes(rs_ctx *ctx, hipStream_t s, bool inv, bool gen_l, int L, uint32_t l, const uint8_t *src,
+int run_plain_tiled(rs_ctx *ctx, Scratch *sc, hipStream_t s, bool inv, int L, uint32_t l, const uint8_t *src,
+                    int src_rows, uint8_t *work, uint8_t *final_dst, int dst_hi, uint64_t rb, int ncols, bool aligned,
+                    const uint8_t *mul_last);
+
+int run_passes(rs_ctx *ctx, Scratch *sc, hipStream_t s, bool inv, bool gen_l, int L, uint32_t l, const uint8_t *src,
                int src_rows, uint8_t *work, uint8_t *final_dst, int dst_lo, int dst_hi, uint64_t rb,
                int ncols, bool aligned, bool pre_B_first, bool post_B_last, const uint8_t *mul_last = nullptr)
 {
+    // GF(2^16) transforms at a shift with no bit below h: two passes of up to
+    // 8 levels on LDS tiles instead of register-only passes of 4 or 5
+    if (ctx->r == 16 && sc && L > FUSED_MAX_L && !gen_l && !pre_B_first && !post_B_last && dst_lo == 0)
+        return run_plain_tiled(ctx, sc, s, inv, L, l, src, src_rows, work, final_dst, dst_hi, rb, ncols, aligned,
+                               mul_last);
     // the L levels in as few passes as possible, as even as possible (e.g.
     // forward 13 = 5 + 4 + 4): every pass reads and writes all h rows, so the
     // pass count sets the traffic
@@ -454,6 +463,69 @@ int run_passes(rs_ctx *ctx, hipStream_t s, bool inv, bool gen_l, int L, uint32_t
             if (dev_err(ctx, pass_launch(ctx->r, cp.ld, T, inv, gen_l, a, ctx->kp, nblocks, s)))
                 return RS_EDEVICE;
         }
+    }
+    return RS_OK;
+}
+
+// A plain transform over h = 2^L rows (8 < L <= 16) at a shift l with no bit
+// below h, in two passes of the codec's pass kernels (Sec. 3.2 / 3.3): the
+// low T1 = ceil(L/2) levels on groups of 2^T1 consecutive rows and the high
+// ones on groups at stride 2^T1, the inverse low part first, the forward high
+// part first.  The first pass reads src (rows >= src_rows as zero), the
+// passes work in `work`, and the last one writes rows [0, dst_hi) of
+// final_dst when it is given, each multiplied symbol by symbol by the same
+// row of mul_last when that is given.
+int run_plain_tiled(rs_ctx *ctx, Scratch *sc, hipStream_t s, bool inv, int L, uint32_t l, const uint8_t *src,
+                    int src_rows, uint8_t *work, uint8_t *final_dst, int dst_hi, uint64_t rb, int ncols, bool aligned,
+                    const uint8_t *mul_last)
+{
+    const int h = 1 << L, T1 = (L + 1) / 2, T2 = L - T1;
+    const int lo_of[2] = {inv ? 0 : T1, inv ? T1 : 0}, T_of[2] = {inv ? T1 : T2, inv ? T2 : T1};
+    struct Launch {
+        int kind, ld, T, lo, ntiles;
+        size_t first;
+    };
+    WideStripe descs[4];
+    Launch launches[4];
+    int nl = 0;
+    const ColParts parts = col_parts(aligned, ncols);
+    for (int c = 0; c < 2; c++) {
+        const bool first = c == 0, last = c == 1;
+        for (const ColPart &cp : parts) {
+            WideStripe &w = descs[nl];
+            std::memset(&w, 0, sizeof(w));
+            w.st.row_bytes = rb;
+            w.st.ncols = ncols;
+            w.st.col0 = cp.col0;
+            w.st.n = w.st.kp = w.st.np = h;
+            w.src = first ? src : work;
+            w.src_rows = first ? src_rows : h;
+            w.dst = last && final_dst ? final_dst : work;
+            w.dst_rows = last && final_dst ? dst_hi : h;
+            w.src2 = last ? mul_last : nullptr;
+            w.tile0 = 0;
+            w.nct = cp.ntiles;
+            launches[nl] = {inv ? W_PI : (last && mul_last ? W_PFM : W_PF), cp.ld, T_of[c], lo_of[c],
+                            (h >> T_of[c]) * cp.ntiles, (size_t)nl};
+            nl++;
+        }
+    }
+    int rc = ensure_dev(sc, &sc->dev, &sc->dev_cap, sizeof(WideStripe) * nl);
+    if (!rc)
+        rc = stage_upload(sc, descs, sizeof(WideStripe) * nl, sc->dev);
+    if (rc)
+        return rc;
+    for (int i = 0; i < nl; i++) {
+        WideArgs wa;
+        wa.stripes = (const WideStripe *)sc->dev + launches[i].first;
+        wa.nstripes = 1;
+        wa.lo = launches[i].lo;
+        wa.blk = 0;
+        wa.l = l;
+        wa.ts = nullptr;
+        if (dev_err(ctx, wide_launch(launches[i].kind, launches[i].ld, launches[i].T, false, wa, ctx->kp,
+                                     launches[i].ntiles, s)))
+            return RS_EDEVICE;
     }
     return RS_OK;
 }
@@ -1137,6 +1209,7 @@ int exec_codec(rs_ctx *ctx, const CodecPlan &cp, uint8_t *dev, hipStream_t strea
         wa.nstripes = (int)wl.count;
         wa.lo = wl.lo;
         wa.blk = wl.blk;
+        wa.l = 0;
         wa.ts = sm ? sm->slots + sm->wide_off[i] : nullptr;
         if (dev_err(ctx, wide_launch(wl.kind, wl.ld, wl.T, wl.pk, wa, kp, wl.ntiles, stream)))
             return RS_EDEVICE;
@@ -1225,7 +1298,7 @@ int xform_locked(rs_ctx *ctx, Scratch *sc, int mode, int h, uint32_t l, uint8_t 
         return RS_OK;
     }
     if (mode == MODE_FFT || mode == MODE_IFFT)
-        return run_passes(ctx, stream, mode == MODE_IFFT, gen_l, L, l, d, h, d, nullptr, 0, 0, rb, ncols, aligned,
+        return run_passes(ctx, sc, stream, mode == MODE_IFFT, gen_l, L, l, d, h, d, nullptr, 0, 0, rb, ncols, aligned,
                           false, false);
     // derivative: y = B d in place, partial sums into scratch, result / B back in place
     uint8_t *Z;
@@ -1828,11 +1901,11 @@ __attribute__((visibility("default"))) int nb_polymul(rs_ctx *ctx, int h, uint32
         // pass pipelines: the first forward pass reads the h rows of the
         // operand and zeros above them, so no padding copy is needed
         const bool gen_l = (l & (uint32_t)(H - 1)) != 0;
-        if ((rc = run_passes(ctx, stream, false, gen_l, LH, l, (const uint8_t *)a, h, (uint8_t *)out, nullptr, 0, 0,
+        if ((rc = run_passes(ctx, sc, stream, false, gen_l, LH, l, (const uint8_t *)a, h, (uint8_t *)out, nullptr, 0, 0,
                              rb, ncols, vec_aligned(ctx, a, out, rb), false, false)))
             return rc;
         // B's last pass multiplies its values by A's, point by point, into out
-        if ((rc = run_passes(ctx, stream, false, gen_l, LH, l, (const uint8_t *)b, h, Z, (uint8_t *)out, 0, H, rb,
+        if ((rc = run_passes(ctx, sc, stream, false, gen_l, LH, l, (const uint8_t *)b, h, Z, (uint8_t *)out, 0, H, rb,
                              ncols, vec_aligned(ctx, b, Z, rb) && vec_aligned(ctx, out, out, rb), false, false,
                              (const uint8_t *)out)))
             return rc;

@@ -20,11 +20,12 @@ def _codec(request, r):
     return request.getfixturevalue("codec%d" % r)
 
 
-# products over 2h > 256 points run pass pipelines (2^9: 5 + 4 levels forward,
-# 2^10: 5 + 5, 2^11: 4 + 4 + 3, 2^12: 4 + 4 + 4) at aligned and general shifts
+# products over 2h > 256 points: at shifts with no bit below 2h, two passes of
+# up to 8 levels on LDS tiles (2^9: 5 + 4, 2^12: 6 + 6, 2^13: 7 + 6); at other
+# shifts register-only passes of 4 or 5 levels (2^10: 5 + 5, 2^11: 4 + 4 + 3)
 @pytest.mark.parametrize("r,h,l", [(16, 1, 0), (16, 2, 7), (16, 8, 16), (16, 64, 0), (16, 128, 300),
                                    (16, 256, 512), (16, 512, 1000), (16, 1024, 12345), (16, 2048, 0),
-                                   (8, 1, 0), (8, 4, 3), (8, 32, 64), (8, 128, 0)])
+                                   (16, 4096, 8192), (8, 1, 0), (8, 4, 3), (8, 32, 64), (8, 128, 0)])
 def test_polymul(request, r, h, l):
     c = _codec(request, r)
     sb = r // 8
