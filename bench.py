@@ -268,7 +268,8 @@ def schedule_for(args, codec, shapes, target_bytes=256 << 20):
         tab = tune.tune(codec, sorted({(n, k) for n, k, sb, e in shapes}), row_bytes=rbs, target_bytes=target_bytes)
         src = "autotuned"
     return {"source": src, "setup_s": round(time.perf_counter() - t0, 2), "T1": tune.summary(tab),
-            "candidate_ms": {"%s:%d" % (e["op"], e["N"]): e.get("ms") for e in tab["entries"]}}
+            "candidate_ms": {"%s:%d" % (e["op"], e["N"]): e.get("ms") for e in tab["entries"]},
+            "tile_ms": {"%s:%d" % (e["op"], e["N"]): e.get("tile_ms") for e in tab["entries"]}}
 
 
 def conv_mults_per_column(h):

@@ -268,8 +268,9 @@ void rs_server_free(rs_server *srv);
  * default); rs_schedule_set_parts takes the list (nparts = 0 restores the
  * default).  rs_init applies the environment variable RS_NB_SCHEDULE, a
  * comma-separated list of "enc:N:P" and "dec:N:P" entries where P is the low
- * part's count or the counts joined by '/', low part first, and returns
- * RS_EINVAL when it is malformed.
+ * part's count or the counts joined by '/', low part first, optionally
+ * followed by ":C" with C the column tile of rs_schedule_set_tile, and
+ * returns RS_EINVAL when it is malformed.
  * Errors: RS_ESHAPE for r = 8 or N outside 9..16; RS_EINVAL for a bad op or
  * split. */
 int rs_schedule_set(rs_ctx *ctx, int op, int N, int T1);
@@ -278,6 +279,17 @@ int rs_schedule_set_parts(rs_ctx *ctx, int op, int N, const int *parts, int npar
  * (parts: room for 4). */
 int rs_schedule_get(rs_ctx *ctx, int op, int N, int *T1);
 int rs_schedule_get_parts(rs_ctx *ctx, int op, int N, int *parts, int *nparts);
+/* Column tiles of the pass pipelines of (op, N): a workgroup covers 256
+ * columns (64 lanes of 4 columns each), or, in the "packed" form of the
+ * two-part pipelines' passes, 128 columns with each wave's two halves
+ * holding two sets of rows.  cols = 0 (the default): 256-column tiles, and
+ * packed ones for rows of at most 128 columns; 128: packed tiles for every
+ * row; 256: 256-column tiles for every row.  Like the level split this
+ * changes only the speed, never an output.
+ * Errors: RS_ESHAPE for r = 8 or N outside 9..16; RS_EINVAL for a bad op or
+ * cols. */
+int rs_schedule_set_tile(rs_ctx *ctx, int op, int N, int cols);
+int rs_schedule_get_tile(rs_ctx *ctx, int op, int N, int *cols);
 
 /* Wait for all work of this context on `stream`; reports deferred device
  * errors. */

@@ -132,6 +132,7 @@ struct rs_ctx {
     // schedules of the pass pipelines per (op, N): the level counts of the
     // parts, low part first, one per 4-bit field; 0 = two parts, ceil(N / 2) low
     std::atomic<int> sched[2][17] = {};
+    std::atomic<int> tile[2][17] = {};             // column tiles of the pass pipelines (rs_schedule_set_tile)
 };
 
 namespace {
@@ -680,7 +681,7 @@ void unpack_parts(int v, int N, int *parts, int *nparts);
 // list the launches: per chunk and transform size, every pass kind in order,
 // one launch per row-access variant.
 void plan_wide(const std::vector<Plan> &plans, const std::vector<int> &idx, bool decode, uint8_t *scratch_base,
-               const int *sched, WidePlan &wp)
+               const int *sched, const int *tile_cols, WidePlan &wp)
 {
     wp.descs.clear();
     wp.launches.clear();
@@ -840,12 +841,16 @@ void plan_wide(const std::vector<Plan> &plans, const std::vector<int> &idx, bool
                         case W_DL: w.src = Z; w.src2 = A; break;
                         }
                         for (const ColPart &cp : col_parts(p.aligned, d.ncols)) {
-                            const bool part_pk = cp.chunks <= 32 && wide_packable(stp.kind, stp.T);
+                            // packed 128-column tiles: by default for parts of at
+                            // most 32 chunks, else as the schedule's tile says
+                            const int tc = tile_cols[N];
+                            const bool part_pk = wide_packable(stp.kind, stp.T) &&
+                                                 (tc == 128 || (tc == 0 && cp.chunks <= 32));
                             if (cp.ld != ld || part_pk != pk)
                                 continue;
                             WideStripe e = w;
                             e.st.col0 = cp.col0;
-                            e.nct = part_pk ? 1 : cp.ntiles;
+                            e.nct = part_pk ? (int)((cp.chunks + 31) / 32) : cp.ntiles;
                             e.tile0 = tiles;
                             tiles += (1 << (N - stp.T)) * e.nct;
                             wp.descs.push_back(e);
@@ -1035,16 +1040,18 @@ int build_codec(rs_ctx *ctx, const rs_stripe_desc *descs, const uint8_t *masks, 
         if (runs_wide(plans[act[q]]))
             widx.push_back(act[q]);
     if (!widx.empty()) {
-        int sc[17];
-        for (int N = 0; N < 17; N++)
+        int sc[17], tl[17];
+        for (int N = 0; N < 17; N++) {
             sc[N] = ctx->sched[decode ? 1 : 0][N].load(std::memory_order_relaxed);
-        plan_wide(plans, widx, decode, nullptr, sc, cp.wp);        // sizes the scratch
+            tl[N] = ctx->tile[decode ? 1 : 0][N].load(std::memory_order_relaxed);
+        }
+        plan_wide(plans, widx, decode, nullptr, sc, tl, cp.wp);        // sizes the scratch
         if (cp.wp.scratch) {
             uint8_t *base = nullptr;
             const int rc = get_scratch ? get_scratch(cp.wp.scratch, &base) : RS_ESHAPE;
             if (rc)
                 return rc;
-            plan_wide(plans, widx, decode, base, sc, cp.wp);
+            plan_wide(plans, widx, decode, base, sc, tl, cp.wp);
         }
     }
 
@@ -1487,7 +1494,8 @@ void unpack_parts(int v, int N, int *parts, int *nparts)
 }
 
 // RS_NB_SCHEDULE: comma-separated "enc:N:P" / "dec:N:P" entries, P the low
-// part's level count or the parts' counts joined by '/', low part first.
+// part's level count or the parts' counts joined by '/', low part first,
+// optionally followed by ":C", the column tile (0, 128 or 256).
 bool apply_schedule_env(rs_ctx *ctx)
 {
     const char *env = std::getenv("RS_NB_SCHEDULE");
@@ -1519,6 +1527,14 @@ bool apply_schedule_env(rs_ctx *ctx)
                 break;
             p++;
         }
+        long cols = 0;                                  // optional ":C", the column tile
+        if (*p == ':') {
+            p++;
+            cols = std::strtol(p, &end, 10);
+            if (end == p || (cols != 0 && cols != 128 && cols != 256))
+                return false;
+            p = end;
+        }
         if (*p && *p != ',')
             return false;
         if (*p)
@@ -1530,6 +1546,7 @@ bool apply_schedule_env(rs_ctx *ctx)
         if (!schedule_ok(ctx->r, op, (int)N, parts, m))
             return false;
         ctx->sched[op][N].store(pack_parts(parts, m));
+        ctx->tile[op][N].store((int)cols);
     }
     return true;
 }
@@ -1731,6 +1748,28 @@ __attribute__((visibility("default"))) int rs_schedule_get_parts(rs_ctx *ctx, in
     if (ctx->r != 16 || N <= FUSED_MAX_L || N > 16)
         return RS_ESHAPE;
     unpack_parts(ctx->sched[op][N].load(), N, parts, nparts);
+    return RS_OK;
+}
+
+__attribute__((visibility("default"))) int rs_schedule_set_tile(rs_ctx *ctx, int op, int N, int cols)
+{
+    if (!ctx)
+        return RS_EINVAL;
+    if (ctx->r != 16 || N <= FUSED_MAX_L || N > 16)
+        return RS_ESHAPE;
+    if ((op != RS_OP_ENCODE && op != RS_OP_DECODE) || (cols != 0 && cols != 128 && cols != 256))
+        return RS_EINVAL;
+    ctx->tile[op][N].store(cols);
+    return RS_OK;
+}
+
+__attribute__((visibility("default"))) int rs_schedule_get_tile(rs_ctx *ctx, int op, int N, int *cols)
+{
+    if (!ctx || !cols || (op != RS_OP_ENCODE && op != RS_OP_DECODE))
+        return RS_EINVAL;
+    if (ctx->r != 16 || N <= FUSED_MAX_L || N > 16)
+        return RS_ESHAPE;
+    *cols = ctx->tile[op][N].load();
     return RS_OK;
 }
 

@@ -219,6 +219,8 @@ def load():
             "rs_schedule_get": (i32, [vp, i32, i32, ctypes.POINTER(i32)]),
             "rs_schedule_set_parts": (i32, [vp, i32, i32, vp, i32]),
             "rs_schedule_get_parts": (i32, [vp, i32, i32, vp, ctypes.POINTER(i32)]),
+            "rs_schedule_set_tile": (i32, [vp, i32, i32, i32]),
+            "rs_schedule_get_tile": (i32, [vp, i32, i32, ctypes.POINTER(i32)]),
             "rs_sync": (i32, [vp, vp]),
             "rs_get_table": (i32, [vp, i32, vp, sz]),
             "rs_strerror": (ctypes.c_char_p, [i32]),
@@ -459,6 +461,16 @@ class Codec:
         arr, m = (ctypes.c_int * 4)(), ctypes.c_int()
         _check(load().rs_schedule_get_parts(self._ctx, op, N, arr, ctypes.byref(m)), "rs_schedule_get_parts")
         return tuple(arr[:m.value])
+
+    def set_schedule_tile(self, op, N, cols):
+        """Column tiles of the pass pipelines over 2^N points: 0 (default),
+        128 (packed tiles for every row) or 256 (256-column tiles only)."""
+        return _check(load().rs_schedule_set_tile(self._ctx, op, N, cols), "rs_schedule_set_tile")
+
+    def get_schedule_tile(self, op, N):
+        t = ctypes.c_int()
+        _check(load().rs_schedule_get_tile(self._ctx, op, N, ctypes.byref(t)), "rs_schedule_get_tile")
+        return t.value
 
     # ------------------------------------------------------------ misc
     def sync(self, stream=None):

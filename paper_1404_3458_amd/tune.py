@@ -10,8 +10,11 @@ size, LDS per workgroup, resident workgroups per CU, arithmetic per byte
 moved), and more parts mean more passes over the rows.  For every
 (operation, N) class of a workload the tuner times each candidate split on
 a seeded synthetic batch of that class through a reusable plan and keeps
-the fastest.  The result is a versioned JSON table that apply() or load()
-puts into a context.
+the fastest, then times that split with the other column tiles
+(rs_schedule_set_tile: 256-column tiles, or packed 128-column tiles in
+which each wave's halves hold two sets of rows) and keeps the fastest
+tile.  The result is a versioned JSON table that apply() or load() puts
+into a context.
 """
 from __future__ import annotations
 
@@ -21,8 +24,9 @@ import time
 
 from . import rs, synth
 
-VERSION = 2
+VERSION = 3
 FUSED_MAX_L = 8
+TILES = (0, 128, 256)      # rs_schedule_set_tile: default, packed everywhere, 256-column only
 _OPS = {"enc": rs.RS_OP_ENCODE, "dec": rs.RS_OP_DECODE}
 
 
@@ -118,17 +122,29 @@ def tune(codec, shapes, row_bytes=(1024, 4096, 16384, 65536), target_bytes=256 <
         else:
             batch = enc
         torch.cuda.synchronize()
+        def timed():
+            plan = codec.plan_decode_batch(batch) if op == "dec" else codec.plan_encode_batch(batch)
+            t = _time_plan(plan, stream, warmup, reps)
+            plan.close()
+            return t
+
         ms = {}
+        codec.set_schedule_tile(_OPS[op], N, 0)
         for parts in candidates(N):
             codec.set_schedule(_OPS[op], N, parts)
-            plan = codec.plan_decode_batch(batch) if op == "dec" else codec.plan_encode_batch(batch)
-            ms[parts] = _time_plan(plan, stream, warmup, reps)
-            plan.close()
+            ms[parts] = timed()
         best = min(ms, key=lambda t: (ms[t], len(t), t))
         codec.set_schedule(_OPS[op], N, best)
-        entry = {"op": op, "N": N, "parts": list(best), "default": list(default_split(N)),
+        tms = {0: ms[best]}
+        for cols in TILES[1:]:
+            codec.set_schedule_tile(_OPS[op], N, cols)
+            tms[cols] = timed()
+        tile = min(tms, key=lambda c: (tms[c], c))
+        codec.set_schedule_tile(_OPS[op], N, tile)
+        entry = {"op": op, "N": N, "parts": list(best), "tile": tile, "default": list(default_split(N)),
                  "shapes": [list(x) for x in shp], "stripes": len(stripes), "codeword_bytes": total,
-                 "ms": {split_name(t): round(v, 4) for t, v in sorted(ms.items())}}
+                 "ms": {split_name(t): round(v, 4) for t, v in sorted(ms.items())},
+                 "tile_ms": {str(c): round(v, 4) for c, v in sorted(tms.items())}}
         table["entries"].append(entry)
         if log:
             log(entry)
@@ -137,11 +153,13 @@ def tune(codec, shapes, row_bytes=(1024, 4096, 16384, 65536), target_bytes=256 <
 
 
 def apply(codec, table):
-    """Set every entry of a table in `codec`."""
-    if table.get("version") != VERSION:
+    """Set every entry of a table in `codec` (tables of version 2 have no
+    column tiles: those stay at the default)."""
+    if table.get("version") not in (2, VERSION):
         raise ValueError("schedule table version %r, expected %d" % (table.get("version"), VERSION))
     for e in table["entries"]:
         codec.set_schedule(_OPS[e["op"]], int(e["N"]), tuple(int(p) for p in e["parts"]))
+        codec.set_schedule_tile(_OPS[e["op"]], int(e["N"]), int(e.get("tile", 0)))
 
 
 def save(table, path):
@@ -158,8 +176,10 @@ def load(path, codec=None):
 
 
 def summary(table):
-    """{"dec:12": "4/4/4", ...} of a table, for reports."""
-    return {"%s:%d" % (e["op"], e["N"]): split_name(e["parts"]) for e in table["entries"]}
+    """{"dec:12": "4/4/4", "enc:15": "7/8 t128", ...} of a table, for
+    reports (a non-default column tile after the split)."""
+    return {"%s:%d" % (e["op"], e["N"]): split_name(e["parts"]) + (" t%d" % e["tile"] if e.get("tile") else "")
+            for e in table["entries"]}
 
 
 if __name__ == "__main__":

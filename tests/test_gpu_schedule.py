@@ -1,9 +1,10 @@
 """GPU parity of every candidate schedule of the pass pipelines
-(rs_schedule_set_parts): each split of a transform over 2^N > 256 points
-into two, three or four parts of levels gives the oracle's parity and
-restores every erasure, for aligned and unaligned rows; plus the error paths
-of the schedule calls, the environment variable that sets schedules at
-rs_init, and the autotuner's table."""
+(rs_schedule_set_parts, rs_schedule_set_tile): each split of a transform
+over 2^N > 256 points into two, three or four parts of levels, and each
+column tile, gives the oracle's parity and restores every erasure, for
+aligned and unaligned rows; plus the error paths of the schedule calls, the
+environment variable that sets schedules at rs_init, and the autotuner's
+table."""
 import math
 import os
 
@@ -84,6 +85,34 @@ def test_decode_every_split(cs, n, k, N, T1):
         cs.set_schedule(rs.RS_OP_DECODE, N, 0)
 
 
+TILE_ENC = [(2048, 1024), (8192, 4096)]
+TILE_DEC = [(300, 200), (4096, 2048), (5000, 4000)]
+
+
+@pytest.mark.parametrize("cols", (128, 256))
+@pytest.mark.parametrize("n,k,N,T1", _cases(TILE_ENC, lambda np_, kp: kp))
+def test_encode_every_split_tile(cs, n, k, N, T1, cols):
+    # 128: packed tiles for every row (260 columns: three tiles, the last of
+    # one chunk); 256: 256-column tiles also for the narrow rows
+    cs.set_schedule_tile(rs.RS_OP_ENCODE, N, cols)
+    try:
+        assert cs.get_schedule_tile(rs.RS_OP_ENCODE, N) == cols
+        test_encode_every_split(cs, n, k, N, T1)
+    finally:
+        cs.set_schedule_tile(rs.RS_OP_ENCODE, N, 0)
+
+
+@pytest.mark.parametrize("cols", (128, 256))
+@pytest.mark.parametrize("n,k,N,T1", _cases(TILE_DEC, lambda np_, kp: np_))
+def test_decode_every_split_tile(cs, n, k, N, T1, cols):
+    cs.set_schedule_tile(rs.RS_OP_DECODE, N, cols)
+    try:
+        assert cs.get_schedule_tile(rs.RS_OP_DECODE, N) == cols
+        test_decode_every_split(cs, n, k, N, T1)
+    finally:
+        cs.set_schedule_tile(rs.RS_OP_DECODE, N, 0)
+
+
 def test_schedule_errors(cs, codec8):
     with pytest.raises(rs.RSError) as ei:
         cs.set_schedule(rs.RS_OP_DECODE, 12, 3)           # high part of 9 levels
@@ -111,19 +140,32 @@ def test_schedule_errors(cs, codec8):
     assert cs.get_schedule_parts(rs.RS_OP_DECODE, 12) == (4, 4, 4) and cs.get_schedule(rs.RS_OP_DECODE, 12) == 4
     cs.set_schedule(rs.RS_OP_DECODE, 12, ())
     assert cs.get_schedule_parts(rs.RS_OP_DECODE, 12) == (6, 6)
+    for N in range(9, 17):
+        assert cs.get_schedule_tile(rs.RS_OP_ENCODE, N) == 0
+    for args, code in (((rs.RS_OP_DECODE, 12, 64), rs.RS_EINVAL), ((2, 12, 128), rs.RS_EINVAL),
+                       ((rs.RS_OP_DECODE, 8, 128), rs.RS_ESHAPE)):
+        with pytest.raises(rs.RSError) as ei:
+            cs.set_schedule_tile(*args)
+        assert ei.value.code == code, args
+    with pytest.raises(rs.RSError) as ei:
+        codec8.set_schedule_tile(rs.RS_OP_DECODE, 9, 128)
+    assert ei.value.code == rs.RS_ESHAPE
 
 
 def test_schedule_environment():
     old = os.environ.get("RS_NB_SCHEDULE")
     try:
-        os.environ["RS_NB_SCHEDULE"] = "dec:12:8,enc:11:4,dec:16:4/4/4/4"
+        os.environ["RS_NB_SCHEDULE"] = "dec:12:8,enc:11:4:128,dec:16:4/4/4/4:256"
         c = rs.Codec(16)
         assert c.get_schedule(rs.RS_OP_DECODE, 12) == 8
         assert c.get_schedule(rs.RS_OP_ENCODE, 11) == 4
         assert c.get_schedule(rs.RS_OP_DECODE, 11) == 6
         assert c.get_schedule_parts(rs.RS_OP_DECODE, 16) == (4, 4, 4, 4)
+        assert (c.get_schedule_tile(rs.RS_OP_DECODE, 12), c.get_schedule_tile(rs.RS_OP_ENCODE, 11),
+                c.get_schedule_tile(rs.RS_OP_DECODE, 16)) == (0, 128, 256)
         c.close()
-        for bad in ("dec:12:3", "dec:12", "xyz:10:5", "enc:11:4;dec:12:6", "dec:12:4/4/3", "dec:12:4/"):
+        for bad in ("dec:12:3", "dec:12", "xyz:10:5", "enc:11:4;dec:12:6", "dec:12:4/4/3", "dec:12:4/",
+                    "dec:12:6:64", "dec:12:6:"):
             os.environ["RS_NB_SCHEDULE"] = bad
             with pytest.raises(rs.RSError) as ei:
                 rs.Codec(16)
@@ -145,12 +187,15 @@ def test_autotuner_table(tmp_path):
             assert tuple(e["parts"]) in tune.candidates(N)
             assert set(e["ms"]) == {tune.split_name(t) for t in tune.candidates(N)}
             assert c.get_schedule_parts(tune._OPS[op], N) == tuple(e["parts"])
+            assert e["tile"] in tune.TILES and set(e["tile_ms"]) == {str(t) for t in tune.TILES}
+            assert c.get_schedule_tile(tune._OPS[op], N) == e["tile"]
         path = str(tmp_path / "sched.json")
         tune.save(tab, path)
         c2 = rs.Codec(16)
         assert tune.load(path, c2) == tab
         for (op, N), e in got.items():
             assert c2.get_schedule_parts(tune._OPS[op], N) == tuple(e["parts"])
+            assert c2.get_schedule_tile(tune._OPS[op], N) == e["tile"]
         c2.close()
     finally:
         c.close()

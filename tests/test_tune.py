@@ -30,15 +30,23 @@ class FakeCodec:
     def set_schedule(self, op, N, T1):
         self.calls.append((op, N, T1))
 
+    def set_schedule_tile(self, op, N, cols):
+        self.calls.append(("tile", op, N, cols))
+
 
 def test_table_roundtrip(tmp_path):
-    tab = {"version": tune.VERSION, "entries": [{"op": "dec", "N": 12, "parts": [4, 4, 4]},
-                                                 {"op": "enc", "N": 11, "parts": [5, 6]}]}
+    tab = {"version": tune.VERSION, "entries": [{"op": "dec", "N": 12, "parts": [4, 4, 4], "tile": 0},
+                                                 {"op": "enc", "N": 11, "parts": [5, 6], "tile": 128}]}
     p = str(tmp_path / "t.json")
     tune.save(tab, p)
     c = FakeCodec()
     assert tune.load(p, c) == tab
-    assert c.calls == [(rs.RS_OP_DECODE, 12, (4, 4, 4)), (rs.RS_OP_ENCODE, 11, (5, 6))]
-    assert tune.summary(tab) == {"dec:12": "4/4/4", "enc:11": "5/6"}
+    assert c.calls == [(rs.RS_OP_DECODE, 12, (4, 4, 4)), ("tile", rs.RS_OP_DECODE, 12, 0),
+                       (rs.RS_OP_ENCODE, 11, (5, 6)), ("tile", rs.RS_OP_ENCODE, 11, 128)]
+    assert tune.summary(tab) == {"dec:12": "4/4/4", "enc:11": "5/6 t128"}
     with pytest.raises(ValueError):
         tune.apply(FakeCodec(), {"version": tune.VERSION + 1, "entries": []})
+    # a table of the previous version (no tiles) keeps the default tile
+    c = FakeCodec()
+    tune.apply(c, {"version": 2, "entries": [{"op": "dec", "N": 9, "parts": [5, 4]}]})
+    assert c.calls == [(rs.RS_OP_DECODE, 9, (5, 4)), ("tile", rs.RS_OP_DECODE, 9, 0)]
