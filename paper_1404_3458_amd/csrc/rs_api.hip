@@ -36,7 +36,8 @@ hipError_t perm_tables(int r, const uint32_t *vals, uint32_t count, uint32_t *ta
 hipError_t stamp_start(uint64_t *ts, uint64_t *slots, size_t nslots, hipStream_t s);
 hipError_t stamp_reduce(uint64_t *ts, const uint64_t *slots, const uint32_t *seg_ptr, const uint32_t *segs,
                         int nstripes, hipStream_t s);
-enum { PK_PAD = 0, PK_MUL = 1, PK_DEGREE = 2, PK_UP = 3, PK_DOWN = 4 };
+enum { PK_PAD = 0, PK_MUL = 1, PK_DEGREE = 2, PK_UP = 3, PK_DOWN = 4, PK_UP_TILE = 5, PK_DOWN_TILE = 6 };
+constexpr int CONV_TILE_L = 8;      // the block-tile conversion kernels cover the levels of 256-row blocks
 hipError_t fused_launch_16(int mode, int sh, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
                            bool pr, hipStream_t s);
 hipError_t fused_launch_8(int mode, int sh, int ld, int L, const FusedArgs &a, const KPtrs &k, int ntiles,
@@ -48,6 +49,7 @@ hipError_t dpart_launch(int r, int ld, int T, const DerivPassArgs &a, const KPtr
 hipError_t wide_launch(int kind, int ld, int T, bool pk, const WideArgs &a, const KPtrs &k, int ntiles, hipStream_t s);
 bool wide_packable(int kind, int T);
 hipError_t wide_prepare();
+hipError_t poly_prepare();
 }  // namespace nb
 
 using namespace nb;
@@ -1658,7 +1660,11 @@ __attribute__((visibility("default"))) int rs_init(int r, const uint32_t *basis,
         hipError_t e2 = fused_prepare_8();
         hipError_t e3 = init_prepare(16);
         hipError_t e4 = wide_prepare();
-        prep_err = e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : (e3 != hipSuccess ? e3 : e4));
+        hipError_t e5 = poly_prepare();
+        prep_err = e1 != hipSuccess ? e1
+                 : e2 != hipSuccess ? e2
+                 : e3 != hipSuccess ? e3
+                 : e4 != hipSuccess ? e4 : e5;
     });
     if (prep_err != hipSuccess) {
         delete ctx;
@@ -2020,8 +2026,16 @@ static int convert(rs_ctx *ctx, int h, void *data, size_t rb, hipStream_t stream
         uint8_t *Z;
         if ((rc = big_scratch(sc, (size_t)h * rb, &Z)))
             return rc;
+        // levels 1 .. min(L, 8) in one launch, in place (each workgroup holds
+        // its 256-row block in LDS); the higher ones level by level
+        const int LB = std::min(L, CONV_TILE_L);
+        PolyArgs pt = poly_args(d, nullptr, d, rb, ncols);
+        pt.rows = h;
+        pt.t = LB;
+        if ((rc = poly_run(ctx, stream, PK_UP_TILE, pt, aligned, (uint32_t)(h >> LB), ctx->d_wh_tab, nullptr)))
+            return rc;
         uint8_t *cur = d, *oth = Z;
-        for (int t = 1; t <= L; t++) {
+        for (int t = LB + 1; t <= L; t++) {
             PolyArgs pa = poly_args(cur, nullptr, oth, rb, ncols);
             pa.rows = h;
             pa.t = t;
@@ -2036,7 +2050,8 @@ static int convert(rs_ctx *ctx, int h, void *data, size_t rb, hipStream_t stream
         }
         return RS_OK;
     }
-    for (int t = L; t >= 1; t--) {
+    const int LB = std::min(L, CONV_TILE_L);
+    for (int t = L; t > LB; t--) {
         const int hh = 1 << (t - 1), nblk = h >> t;
         PolyArgs pa = poly_args(nullptr, nullptr, d, rb, ncols);
         pa.rows = h;
@@ -2054,7 +2069,11 @@ static int convert(rs_ctx *ctx, int h, void *data, size_t rb, hipStream_t stream
                 return rc;
         }
     }
-    return RS_OK;
+    // levels min(L, 8) .. 1 in one launch, each workgroup on its 256-row block
+    PolyArgs pt = poly_args(nullptr, nullptr, d, rb, ncols);
+    pt.rows = h;
+    pt.t = LB;
+    return poly_run(ctx, stream, PK_DOWN_TILE, pt, aligned, (uint32_t)(h >> LB), ctx->d_wh_tab, nullptr);
 }
 
 __attribute__((visibility("default"))) int nb_to_monomial(rs_ctx *ctx, int h, void *data, size_t row_bytes,

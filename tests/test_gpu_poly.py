@@ -89,7 +89,10 @@ def test_degree(request, r, h):
         assert (got == exp).all(), (r, h, nc, first_diff(got, exp))
 
 
-@pytest.mark.parametrize("r,h", [(16, 2), (16, 4), (16, 16), (16, 128), (16, 256), (8, 2), (8, 32), (8, 256)])
+# levels up to 8 run in one block-tile launch; 512 rows add a ninth level of
+# the one-level kernels in each direction
+@pytest.mark.parametrize("r,h", [(16, 2), (16, 4), (16, 16), (16, 128), (16, 256), (16, 512), (8, 2), (8, 32),
+                                 (8, 256)])
 def test_conversion_matches_oracle(request, r, h):
     c = _codec(request, r)
     sb = r // 8
