@@ -78,28 +78,36 @@ __host__ __device__ inline uint32_t gf_inv(uint32_t a, int r)
     return gf_pow(a, (1u << r) - 2u, r);
 }
 
-// Build the perm table of constant s (layout in the file comment).
-__device__ inline void build_perm_table(uint32_t s, int r, uint32_t *out)
+// Build the perm table of constant s (layout in the file comment); R fixed
+// at compile time, so that every loop unrolls and a local `out` stays in
+// registers.
+template <int R>
+__device__ __forceinline__ void build_perm_table_r(uint32_t s, uint32_t *out)
 {
-    uint32_t px[16];                 // s * x^t
+    uint32_t px[R];                  // s * x^t
     px[0] = s;
-    for (int t = 1; t < r; t++)
-        px[t] = gf_times_x(px[t - 1], r);
-    const int nbytes = r / 8;
+#pragma unroll
+    for (int t = 1; t < R; t++)
+        px[t] = gf_times_x(px[t - 1], R);
+    constexpr int nbytes = R / 8;
+#pragma unroll
     for (int b = 0; b < nbytes; b++) {
+#pragma unroll
         for (int g = 0; g < 3; g++) {
             const int nbits = g == 2 ? 2 : 3;
             const int shift = 8 * b + 3 * g;
             uint32_t lo_out[2] = {0, 0}, hi_out[2] = {0, 0};
+#pragma unroll
             for (int e = 0; e < (1 << nbits); e++) {
                 uint32_t prod = 0;
+#pragma unroll
                 for (int u = 0; u < nbits; u++)
                     if ((e >> u) & 1)
                         prod ^= px[shift + u];
                 lo_out[e >> 2] |= (prod & 0xFFu) << (8 * (e & 3));
                 hi_out[e >> 2] |= ((prod >> 8) & 0xFFu) << (8 * (e & 3));
             }
-            if (r == 16) {
+            if (R == 16) {
                 if (g < 2) {
                     const int v = 4 * b + 2 * g;          // table index among the eight
                     out[v] = lo_out[0];
@@ -120,9 +128,30 @@ __device__ inline void build_perm_table(uint32_t s, int r, uint32_t *out)
             }
         }
     }
-    if (r == 8) {
+    if (R == 8) {
         out[5] = out[6] = out[7] = 0;
     }
+}
+
+__device__ inline void build_perm_table(uint32_t s, int r, uint32_t *out)
+{
+    if (r == 16)
+        build_perm_table_r<16>(s, out);
+    else
+        build_perm_table_r<8>(s, out);
+}
+
+// The perm table of s built in registers and stored at out (16-byte aligned)
+// as 16-byte pieces.
+template <int R>
+__device__ __forceinline__ void store_perm_table(uint32_t s, uint32_t *out)
+{
+    constexpr int TS = R == 16 ? 20 : 8;
+    uint32_t t[TS];
+    build_perm_table_r<R>(s, t);
+#pragma unroll
+    for (int i = 0; i < TS / 4; i++)
+        reinterpret_cast<uint4 *>(out)[i] = make_uint4(t[4 * i], t[4 * i + 1], t[4 * i + 2], t[4 * i + 3]);
 }
 
 // ---------------------------------------------------------------- hot ops

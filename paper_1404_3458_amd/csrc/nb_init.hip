@@ -200,10 +200,10 @@ __global__ void k_locator(LocatorArgs a, const uint32_t *__restrict__ p_bits, ui
             lg = ((lg << sh) | (lg >> (r - sh))) & M;
         const bool er = !((rxb[p >> 5] >> (p & 31)) & 1u) && !(p >= st.k && p < st.kp);
         const uint32_t e = er ? (M - lg) % M : lg;
-        uint32_t tab[TAB16];
-        build_perm_table(expt[e], r, tab);
-        for (int u = 0; u < ts; u++)
-            out[(size_t)ts * p + u] = tab[u];
+        if (r == 16)
+            store_perm_table<16>(expt[e], out + (size_t)ts * p);
+        else
+            store_perm_table<8>(expt[e], out + (size_t)ts * p);
     }
 }
 
@@ -272,10 +272,10 @@ __global__ __launch_bounds__(256) void k_loc_pass(LocPassArgs a, const uint32_t 
         if (sh)
             x = ((x << sh) | (x >> (r - sh))) & M;
         const uint32_t e = erased(p) ? (M - x) % M : x % M;
-        uint32_t tab[TAB16];
-        build_perm_table(expt[e], r, tab);
-        for (int u = 0; u < ts; u++)
-            out[(size_t)ts * p + u] = tab[u];
+        if (r == 16)
+            store_perm_table<16>(expt[e], out + (size_t)ts * p);
+        else
+            store_perm_table<8>(expt[e], out + (size_t)ts * p);
     }
 }
 
