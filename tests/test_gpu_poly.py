@@ -109,6 +109,22 @@ def test_conversion_matches_oracle(request, r, h):
         assert (got == exp).all(), ("from", r, h, nc, first_diff(got, exp))
 
 
+def test_conversion_matches_oracle_4096(codec16):
+    # the measured size: levels 1-8 in the block-tile kernels, 9-12 level by
+    # level, on 4 columns (8-byte rows: vector accesses) against the oracle
+    h, nc = 4096, 4
+    d = rand_rows(h, 2 * nc, 80, h)
+    t = to_dev(d)
+    codec16.to_monomial(h, t)
+    got, exp = to_host(t), oracle.convert_rows(16, d.copy(), True)
+    assert (got == exp).all(), ("to", first_diff(got, exp))
+    m = rand_rows(h, 2 * nc, 81, h)
+    t = to_dev(m)
+    codec16.from_monomial(h, t)
+    got, exp = to_host(t), oracle.convert_rows(16, m.copy(), False)
+    assert (got == exp).all(), ("from", first_diff(got, exp))
+
+
 @pytest.mark.parametrize("h", [1024, 8192])
 def test_conversion_round_trip_large(codec16, h):
     # sizes past the oracle's O(h^2) tables: the two conversions invert each
