@@ -58,7 +58,8 @@ CONFIGS = {
     "c4": dict(r=16, stripes=8192, mixed=True,
                workload="GF(2^16) mod 0x1100B, 8192 stripes, (n,k) uniform over (16,8) (64,48) (256,224) "
                         "(1024,512) (4096,2048), shards log-uniform 1-64 KiB, erasures uniform in [0,n-k]; "
-                        "encode + decode, batched plans replayed as a HIP graph vs per-stripe calls"),
+                        "encode + decode, per-class batched plans replayed as one HIP graph (smallest class first) "
+                        "vs per-stripe calls"),
 }
 
 
@@ -406,9 +407,11 @@ def run_poly(args, cfg):
 
 def run_mixed(args, cfg):
     """The mixed-stripe workload: every stripe encoded and then decoded in
-    place per step, as one encode plan and one decode plan replayed in a HIP
-    graph; also timed as batched calls and as per-stripe calls, overall and
-    per (n, k) class."""
+    place per step, as one encode plan and one decode plan per (n, k) class
+    replayed in one HIP graph, the classes in order of size (each class's
+    encode, then its decode, so that a stripe of a small class completes
+    early); also timed as one encode and one decode plan over all stripes, as
+    batched calls and as per-stripe calls, overall and per class."""
     import numpy as np
     import torch
 
@@ -482,30 +485,48 @@ def run_mixed(args, cfg):
                 p_.launch()
         return g
 
-    # batched plans in a graph (the measured configuration)
-    pe, pd = codec.plan_encode_batch(enc_b), codec.plan_decode_batch(dec_b)
-    g = graph_of([pe, pd])
+    classes = [c for c in synth.MIXED_CLASSES if any(sh[:2] == c for sh in shapes)]
+    cidx = {c: [s for s, sh in enumerate(shapes) if sh[:2] == c] for c in classes}
+    cplans = {c: (codec.plan_encode_batch([enc_list[s] for s in cidx[c]]),
+                  codec.plan_decode_batch([dec_list[s] for s in cidx[c]])) for c in classes}
+    # the measured configuration: per-class plans, smallest class first
+    g = graph_of([p_ for c in classes for p_ in cplans[c]])
     for _ in range(args.warmup):
         g.replay()
     wall_g, ev_g = timed(g.replay, args.steps)
+    # the same work as one encode and one decode plan over all stripes
+    pe, pd = codec.plan_encode_batch(enc_b), codec.plan_decode_batch(dec_b)
+    g1 = graph_of([pe, pd])
+    g1.replay()
+    wall_g1, ev_g1 = timed(g1.replay, max(2, args.steps // 2))
+    del g1
     # per-stripe completion within a step, from device stamps written as the
-    # last workgroup on each stripe finishes (eager launches of the same plans;
-    # the graph above was captured without stamps): a stripe is done when its
-    # decode is, or its encode when its decode has no work (no erasures)
-    ts_e = torch.zeros(ns + 1, dtype=torch.int64, device=dev)
-    ts_d = torch.zeros_like(ts_e)
-    khz = pe.set_timestamps(ts_e)
-    pd.set_timestamps(ts_d)
+    # last workgroup on each stripe finishes (eager launches of the same
+    # per-class plans in the same order; the graph was captured without
+    # stamps), relative to the start of the first launch: a stripe is done
+    # when its decode is, or its encode when its decode has no work (no
+    # erasures)
+    stamps = {c: (torch.zeros(len(cidx[c]) + 1, dtype=torch.int64, device=dev),
+                  torch.zeros(len(cidx[c]) + 1, dtype=torch.int64, device=dev)) for c in classes}
+    khz = None
+    for c in classes:
+        khz = cplans[c][0].set_timestamps(stamps[c][0])
+        cplans[c][1].set_timestamps(stamps[c][1])
     done = []
     for _ in range(3):
-        pe.launch()
-        pd.launch()
+        for c in classes:
+            cplans[c][0].launch()
+            cplans[c][1].launch()
         torch.cuda.synchronize()
-        te, td = ts_e.cpu().numpy(), ts_d.cpu().numpy()
-        fin = np.where(td[1:] > 0, td[1:], te[1:])
-        done.append((fin - te[0]) / khz)
-    pe.set_timestamps(None)
-    pd.set_timestamps(None)
+        t0 = int(stamps[classes[0]][0][0].item())
+        fin = np.zeros(ns)
+        for c in classes:
+            te, td = stamps[c][0].cpu().numpy(), stamps[c][1].cpu().numpy()
+            fin[cidx[c]] = np.where(td[1:] > 0, td[1:], te[1:])
+        done.append((fin - t0) / khz)
+    for c in classes:
+        cplans[c][0].set_timestamps(None)
+        cplans[c][1].set_timestamps(None)
     done = np.stack(done)
     # batched calls (planned on every call)
     for _ in range(max(1, args.warmup // 2)):
@@ -523,14 +544,10 @@ def run_mixed(args, cfg):
 
     per_class = {}
     wall_ps_total = 0.0
-    for c in synth.MIXED_CLASSES:
-        idx = [s for s, sh in enumerate(shapes) if sh[:2] == c]
-        if not idx:
-            continue
+    for c in classes:
+        idx = cidx[c]
         cb = sum(shapes[s][1] * shapes[s][2] for s in idx)
-        pce = codec.plan_encode_batch([enc_list[s] for s in idx])
-        pcd = codec.plan_decode_batch([dec_list[s] for s in idx])
-        gc = graph_of([pce, pcd])
+        gc = graph_of(list(cplans[c]))
         gc.replay()
         wall_c, _ = timed(gc.replay, 3)
         per_stripe(idx)
@@ -543,8 +560,6 @@ def run_mixed(args, cfg):
                                   "graph_msg_GBps": round(cb / wall_c / 1e6, 1),
                                   "per_stripe_msg_GBps": round(cb / wall_p / 1e6, 1),
                                   "factor": round(wall_p / wall_c, 2)}
-        pce.close()
-        pcd.close()
         del gc
     value = msg_bytes / (wall_g * 1e-3) / 1e9
     hbm = 2 * cw_bytes / (wall_g * 1e-3) / 1e9        # encode n*S + decode n*S per stripe
@@ -566,7 +581,7 @@ def run_mixed(args, cfg):
         "config": {"workload": cfg["workload"], "field_bits": 16, "stripes": ns,
                    "message_GB": round(msg_bytes / 1e9, 2), "codeword_GB": round(cw_bytes / 1e9, 2),
                    "parallelism": "single GPU"},
-        "roofline": hbm_roofline("whole step (encode and decode plans of every class)", 2 * cw_bytes,
+        "roofline": hbm_roofline("whole step (encode and decode plans of every class, in order)", 2 * cw_bytes,
                                  wall_g * 1e-3, None, None, alu_figures(mults, wall_g * 1e-3, 16)),
         "cpu_baseline": None,
         "detail": {
@@ -575,6 +590,8 @@ def run_mixed(args, cfg):
             "stripe_done_ms_p50": round(float(np.percentile(done, 50)), 3),
             "stripe_done_ms_p99": round(float(np.percentile(done, 99)), 3),
             "stripe_done_ms_max": round(float(done.max()), 3),
+            "one_plan_graph_step_ms": round(wall_g1, 3),
+            "one_plan_graph_step_ms_p99": round(float(np.percentile(ev_g1, 99)), 3),
             "batched_call_step_ms": round(wall_b, 3),
             "batched_call_step_ms_p99": round(float(np.percentile(ev_b, 99)), 3),
             "per_stripe_step_ms": round(wall_ps_total, 3),
@@ -586,6 +603,9 @@ def run_mixed(args, cfg):
     }
     pe.close()
     pd.close()
+    for c in classes:
+        cplans[c][0].close()
+        cplans[c][1].close()
     codec.close()
     return out
 
@@ -595,6 +615,7 @@ def mixed_summary(out):
     d = out["detail"]
     return {"workload": out["config"]["workload"], "steps": out["steps"], "msg_GBps": out["value"],
             "ms_per_step": out["ms_per_step"], "hbm_frac": out["roofline"]["frac"],
+            "one_plan_graph_step_ms": d["one_plan_graph_step_ms"],
             "batched_graph_over_per_stripe": d["graph_over_per_stripe"],
             "batched_calls_over_per_stripe": d["batched_calls_over_per_stripe"],
             "per_stripe_step_ms": d["per_stripe_step_ms"],
