@@ -888,8 +888,11 @@ def main():
     mults = ns * cols * paper_mults_per_column(n, k, dom == "decode")
     lg = int(np.log2(pow2ceil(k) if dom == "encode" else pow2ceil(pow2ceil(k) + n - k)))
     copy_rate = copy_gbps()
-    roof = hbm_roofline("%s launch (%s, L=%d)" % (dom, "k_tiled" if 4 < lg <= 8 else
-                                                  ("k_small" if lg <= 4 else "multi-pass"), lg),
+    # GF(2^16) decodes of 128 or 256 points over 8-byte-aligned rows run the
+    # persistent decode kernel when there are more tiles than workgroup slots
+    persist = dom == "decode" and r == 16 and lg in (7, 8) and S % 8 == 0 and ns * -(-cols // 256) > 512
+    kname = "k_dec_persist" if persist else ("k_tiled" if 4 < lg <= 8 else ("k_small" if lg <= 4 else "multi-pass"))
+    roof = hbm_roofline("%s launch (%s, L=%d)" % (dom, kname, lg),
                         algo_bytes, dom_ms * 1e-3, traffic_from_profiles(args.config), copy_rate,
                         alu_figures(mults, dom_ms * 1e-3, r))
 

@@ -203,6 +203,17 @@ struct DecTile {
                                         const Lane &ln, const uint32_t *__restrict__ bits,
                                         const uint32_t *__restrict__ rowtab) const
     {
+        run<LD, PR>(x, rcv, st, ln, bits, rowtab, [] {});
+    }
+
+    // after_read: called once this wave has read its consecutive rows for the
+    // last phase, from which point no other wave reads its tile rows (rows
+    // 16 g .. 16 g + 15) of this tile again.
+    template <int LD, bool PR, class AFTER>
+    __device__ __forceinline__ void run(uint32_t (*x)[Traits<R>::NW], const bool *rcv, const DevStripe &st,
+                                        const Lane &ln, const uint32_t *__restrict__ bits,
+                                        const uint32_t *__restrict__ rowtab, const AFTER &after_read) const
+    {
         const int g = wave;
         const TwLds<R, L> twX = {p_tw, 0u, vX()};
         uint32_t *const vb = vB(), *const vbi = vBi(), *const vrt = vRT();
@@ -295,6 +306,7 @@ struct DecTile {
 #pragma unroll
         for (int j = 0; j < 16; j++)
             get(16 * g + j, x[j]);
+        after_read();
         // levels 3..0 and step 6
         reg_levels<R, 4, false, SH_ZERO, false>(x, (uint32_t)(16 * g), 0, twX);
         pipelined<Tab, 16>([&](int j) { return row_tab<R>(rowtab, vrt, 16 * g + j); },
@@ -640,6 +652,140 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(
 
 }
 
+// Decode (Algorithm 2 steps 2-6) of 2^L-point stripes with vector-aligned
+// rows, persistent: one workgroup per LDS slot of the device walks a
+// contiguous range of tiles.  The transform and derivative tables are staged
+// once, the per-point locator tables when the stripe changes, and while a
+// wave computes the last phase of one tile the received rows of its part of
+// the next tile travel from global memory straight into its (then unused)
+// tile rows (global_load_lds, no registers), so that the next tile starts
+// from LDS instead of waiting for HBM.  A copied tile row holds the row's
+// 512 bytes in memory order (lane l's chunk at dwords 2l, 2l + 1).  Only
+// launches without
+// completion stamps (one stamp slot per workgroup would span several
+// stripes) and without pruning.
+template <int R, int L>
+__global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4))) void k_dec_persist(
+    NB_FUSED_PARAMS, int ntiles)
+{
+    static_assert(R == 16, "GF(2^16) rows of 4-byte dwords");
+    typedef TiledLds<R, L, M_DEC> LY;
+    constexpr int NW = Traits<R>::NW, NV = Ops<R>::NV, H = 1 << L, NT = 64 << (L - 4), RS = 64 * NW;
+    extern __shared__ uint32_t lds[];
+    uint32_t *const vX = lds + LY::TILE;
+    uint32_t *const vB = vX + NV * LY::EX;
+    uint32_t *const vBi = vB + NV * LY::EB;
+    uint32_t *const vRT = vBi + NV * LY::EB;
+    const int tid = (int)threadIdx.x;
+    // workgroup b takes tiles [t0, t1): ntiles / G each, one more for the
+    // first ntiles % G
+    const int G = (int)gridDim.x, b = (int)blockIdx.x, q = ntiles / G, rm = ntiles % G;
+    const int t0 = b * q + (b < rm ? b : rm);
+    const int t1 = t0 + q + (b < rm ? 1 : 0);
+
+    // Copies the received rows of tile t's consecutive group of this wave
+    // into the wave's tile rows, in two 256-byte halves: in the first, lane l
+    // copies dword l of the row (half of chunk l / 2), in the second dword
+    // 64 + l (half of chunk 32 + l / 2); a chunk past the stripe's columns is
+    // not copied.
+    ConstStripe *const cst = const_stripes(a.stripes);
+    auto issue = [&](int t, int g, int lane) {
+        const DevStripe st = cst[find_stripe(cst, a.nstripes, t)];
+        const Lane la = lane_of<R, LD_VEC>(t - st.tile0, lane >> 1, st.col0, st.ncols);
+        const Lane lb = lane_of<R, LD_VEC>(t - st.tile0, 32 + (lane >> 1), st.col0, st.ncols);
+        const uint32_t half = 4u * (uint32_t)(lane & 1);
+        const uint32_t *__restrict__ bits = p_bits + st.bits_off;
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            const int p = 16 * g + j;
+            if (point_bit(bits, p)) {
+                const uint8_t *row = row_ptr(st.in, (uint32_t)point_row(p, st), st.row_bytes) + half;
+                uint32_t *dst = lds + (size_t)p * RS;
+                if (la.act)
+                    __builtin_amdgcn_global_load_lds((const void *)(row + la.off),
+                                                     (__attribute__((address_space(3))) void *)dst, 4, 0, 0);
+                if (lb.act)
+                    __builtin_amdgcn_global_load_lds((const void *)(row + lb.off),
+                                                     (__attribute__((address_space(3))) void *)(dst + 64), 4, 0,
+                                                     0);
+            }
+        }
+    };
+    if (t0 < t1)
+        issue(t0, __builtin_amdgcn_readfirstlane(tid >> 6), tid & 63);
+    stage_levels<R, L>(vX, p_tw, 0u, tid, NT);
+    stage_rows<R>(vB, p_B, H, tid, NT);
+    stage_rows<R>(vBi, p_Binv, H, tid, NT);
+    int cur = -1;                                // stripe whose locator tables are staged
+    for (int tile = t0; tile < t1; tile++) {
+        // the table pointers pass through an empty asm per tile, so the
+        // compiler reloads the tables' scalar words inside the loop instead
+        // of keeping a hundred of them live across it
+        // wave and lane pass through an empty asm per tile, so that the
+        // compiler recomputes the hundred addresses and table indices derived
+        // from them inside the loop instead of keeping them live across it
+        int g = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+        asm volatile("" : "+s"(g), "+v"(lane));
+        const DecTile<R, L> dt = {lds, p_tw, p_B, p_Binv, g, lane};
+        const int s = find_stripe(cst, a.nstripes, tile);
+        const DevStripe st = cst[s];
+        const Lane ln = lane_of<R, LD_VEC>(tile - st.tile0, lane, st.col0, st.ncols);
+        const uint32_t *__restrict__ bits = p_bits + st.bits_off;
+        const uint32_t *__restrict__ rowtab = p_rowtabs + st.rowtab_off;
+        if (s != cur) {
+            __syncthreads();                     // every wave is done with the previous tables
+            stage_rows<R>(vRT, rowtab, H, tid, NT);
+            __syncthreads();
+            cur = s;
+        }
+        uint32_t x[16][NW];
+        bool rcv[16];
+        __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0): this wave's row copies have landed
+        asm volatile("" ::: "memory");
+        // one per-lane base; the rows sit at constant offsets from it
+        const uint2 *const mine = reinterpret_cast<const uint2 *>(lds + (size_t)(16 * g) * RS) + lane;
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            const int p = 16 * g + j;
+            rcv[j] = point_bit(bits, p);
+            if (rcv[j]) {
+                // chunks past the stripe's columns were not copied: zero
+                const uint2 w = mine[j * (RS / 2)];
+                Ops<R>::unpack(ln.act ? w.x : 0u, ln.act ? w.y : 0u, x[j]);
+            } else {
+                zero_vec<R>(x[j]);
+            }
+        }
+        if (st.copy_survivors) {
+#pragma unroll
+            for (int j = 0; j < 16; j++) {
+                const int p = 16 * g + j;
+                if (rcv[j])
+                    store_chunk<R, LD_VEC>(row_ptr(st.out, (uint32_t)point_row(p, st), st.row_bytes), ln.off, ln.act,
+                                           ln.nsym, x[j]);
+            }
+        }
+        const int nx = tile + 1;
+        dt.template run<LD_VEC, false>(x, rcv, st, ln, bits, rowtab, [&] {
+            if (nx < t1) {
+                // this wave's reads of its tile rows have returned before the
+                // copies into them start
+                __builtin_amdgcn_s_waitcnt(0xC07F); // lgkmcnt(0)
+                asm volatile("" ::: "memory");
+                issue(nx, g, lane);
+                asm volatile("" ::: "memory");
+            }
+        });
+    }
+}
+
+// Workgroups of k_dec_persist that fit one CU at once.
+template <int L>
+constexpr int dec_persist_per_cu()
+{
+    return (int)((160 * 1024) / TiledLds<16, L, M_DEC>::BYTES);
+}
+
 // ------------------------------------------------------------------ launchers
 
 // Modes with a pruned variant.
@@ -650,12 +796,39 @@ constexpr bool can_prune(int mode) { return mode == M_ENC || mode == M_ENC2 || m
 template <int R, int L, int MODE>
 constexpr bool fused_built() { return !(MODE == M_ENC && L >= 8); }
 
+// Compute units of the current device (cached per device).
+static int device_cus()
+{
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 0;
+    if (!cus[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+            cus[dev] = v;
+    }
+    return cus[dev];
+}
+
 template <int R, int L, int MODE, int SH, int LD, bool PR>
 static hipError_t launch_pr(const FusedArgs &a, const KPtrs &k, int ntiles, hipStream_t stream)
 {
     if constexpr (!fused_built<R, L, MODE>())
         return hipErrorInvalidValue;
-    else if (L <= 4) {
+    else if constexpr (R == 16 && MODE == M_DEC && LD == LD_VEC && !PR && L >= 7) {
+        // persistent when there is more than one round of workgroups and no
+        // completion stamps are asked for
+        const int slots = device_cus() * dec_persist_per_cu<L>();
+        const size_t lds = TiledLds<R, L, MODE>::BYTES;
+        if (!a.ts && slots > 0 && ntiles > slots) {
+            hipLaunchKernelGGL((k_dec_persist<R, L>), dim3(slots), dim3(64 << (L - 4)), lds, stream, a, k.tw, k.B,
+                               k.Binv, k.bits, k.rowtabs, ntiles);
+        } else {
+            hipLaunchKernelGGL((k_tiled<R, L, MODE, SH, LD, PR>), dim3(ntiles), dim3(64 << (L - 4)), lds, stream, a,
+                               k.tw, k.B, k.Binv, k.bits, k.rowtabs);
+        }
+    } else if (L <= 4) {
         hipLaunchKernelGGL((k_small<R, (L <= 4 ? L : 4), MODE, SH, LD, PR>), dim3(ntiles), dim3(64), 0, stream, a,
                            k.tw, k.B, k.Binv, k.bits, k.rowtabs);
     } else {
@@ -690,6 +863,13 @@ static hipError_t prep_one()
                                            (int)TiledLds<R, LL, MODE>::BYTES);
         if constexpr (can_prune(MODE)) {
             const hipError_t f = hipFuncSetAttribute((const void *)k_tiled<R, LL, MODE, SH, LD, true>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     (int)TiledLds<R, LL, MODE>::BYTES);
+            if (e == hipSuccess)
+                e = f;
+        }
+        if constexpr (R == 16 && MODE == M_DEC && LD == LD_VEC && LL >= 7) {
+            const hipError_t f = hipFuncSetAttribute((const void *)k_dec_persist<R, LL>,
                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                                      (int)TiledLds<R, LL, MODE>::BYTES);
             if (e == hipSuccess)

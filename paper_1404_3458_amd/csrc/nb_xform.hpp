@@ -13,7 +13,23 @@
 
 namespace nb {
 
-__device__ __forceinline__ int find_stripe(const DevStripe *__restrict__ st, int n, int tile)
+// Stripe descriptors are written by the host only; a kernel that stores to
+// global memory before reading one reads it through the constant address
+// space, so that the reads stay scalar loads.  (The host pass of a kernel
+// body sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const __attribute__((address_space(4))) DevStripe ConstStripe;
+#else
+typedef const DevStripe ConstStripe;
+#endif
+
+__device__ __forceinline__ ConstStripe *const_stripes(const DevStripe *p)
+{
+    return (ConstStripe *)p;
+}
+
+template <class P>
+__device__ __forceinline__ int find_stripe(P st, int n, int tile)
 {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
