@@ -552,7 +552,10 @@ __device__ __forceinline__ void load_chunk(const uint8_t *row_, uint32_t off, bo
         v[0] = w;
     }
 }
-template <int R, int LD>
+// NT: a streamed output that nothing in the launch reads again; with 8-byte
+// alignment it is stored non-temporally, so that it does not push the
+// tables the launch keeps re-reading out of L2.
+template <int R, int LD, bool NT = false>
 __device__ __forceinline__ void store_chunk(uint8_t *row_, uint32_t off, bool act, int nsym, const uint32_t *v)
 {
     if (!act)
@@ -562,7 +565,11 @@ __device__ __forceinline__ void store_chunk(uint8_t *row_, uint32_t off, bool ac
         uint32_t w0, w1;
         Ops<16>::pack(v, w0, w1);
         if (LD == LD_VEC) {
-            *(gu64 *)row = (uint64_t)w0 | ((uint64_t)w1 << 32);
+            const uint64_t t = (uint64_t)w0 | ((uint64_t)w1 << 32);
+            if (NT)
+                __builtin_nontemporal_store(t, (gu64 *)row);
+            else
+                *(gu64 *)row = t;
         } else if (nsym == 4) {
             *(gu64_a2 *)row = (uint64_t)w0 | ((uint64_t)w1 << 32);
         } else {

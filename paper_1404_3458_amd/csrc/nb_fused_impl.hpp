@@ -203,13 +203,14 @@ struct DecTile {
                                         const Lane &ln, const uint32_t *__restrict__ bits,
                                         const uint32_t *__restrict__ rowtab) const
     {
-        run<LD, PR>(x, rcv, st, ln, bits, rowtab, [] {});
+        run<LD, PR, false>(x, rcv, st, ln, bits, rowtab, [] {});
     }
 
     // after_read: called once this wave has read its consecutive rows for the
     // last phase, from which point no other wave reads its tile rows (rows
-    // 16 g .. 16 g + 15) of this tile again.
-    template <int LD, bool PR, class AFTER>
+    // 16 g .. 16 g + 15) of this tile again.  NT: the decoded rows are
+    // stored non-temporally.
+    template <int LD, bool PR, bool NT, class AFTER>
     __device__ __forceinline__ void run(uint32_t (*x)[Traits<R>::NW], const bool *rcv, const DevStripe &st,
                                         const Lane &ln, const uint32_t *__restrict__ bits,
                                         const uint32_t *__restrict__ rowtab, const AFTER &after_read) const
@@ -311,7 +312,8 @@ struct DecTile {
         reg_levels<R, 4, false, SH_ZERO, false>(x, (uint32_t)(16 * g), 0, twX);
         pipelined<Tab, 16>([&](int j) { return row_tab<R>(rowtab, vrt, 16 * g + j); },
                            [&](int j, const Tab &t) {
-                               dec_store<R, LD>(x[j], 16 * g + j, st, ln, bits, [&](int) { return t; });
+                               dec_store<R, LD, true, NT>(x[j], 16 * g + j, st, ln, bits,
+                                                          [&](int) { return t; });
                            });
     }
 };
@@ -660,8 +662,11 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(
 // the next tile travel from global memory straight into its (then unused)
 // tile rows (global_load_lds, no registers), so that the next tile starts
 // from LDS instead of waiting for HBM.  A copied tile row holds the row's
-// 512 bytes in memory order (lane l's chunk at dwords 2l, 2l + 1).  Only
-// launches without
+// 512 bytes in memory order (lane l's chunk at dwords 2l, 2l + 1).  Rows
+// are read and written non-temporally: each XCD streams about as many row
+// bytes per tile as its L2 holds, which otherwise evicts the table words
+// every tile re-reads (they came back as extra 64-byte HBM reads, about a
+// sixth of the row bytes, and slower scalar loads).  Only launches without
 // completion stamps (one stamp slot per workgroup would span several
 // stripes) and without pruning.
 template <int R, int L>
@@ -701,13 +706,14 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
             if (point_bit(bits, p)) {
                 const uint8_t *row = row_ptr(st.in, (uint32_t)point_row(p, st), st.row_bytes) + half;
                 uint32_t *dst = lds + (size_t)p * RS;
+                // cache policy 2: non-temporal
                 if (la.act)
                     __builtin_amdgcn_global_load_lds((const void *)(row + la.off),
-                                                     (__attribute__((address_space(3))) void *)dst, 4, 0, 0);
+                                                     (__attribute__((address_space(3))) void *)dst, 4, 0, 2);
                 if (lb.act)
                     __builtin_amdgcn_global_load_lds((const void *)(row + lb.off),
                                                      (__attribute__((address_space(3))) void *)(dst + 64), 4, 0,
-                                                     0);
+                                                     2);
             }
         }
     };
@@ -761,12 +767,12 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
             for (int j = 0; j < 16; j++) {
                 const int p = 16 * g + j;
                 if (rcv[j])
-                    store_chunk<R, LD_VEC>(row_ptr(st.out, (uint32_t)point_row(p, st), st.row_bytes), ln.off, ln.act,
-                                           ln.nsym, x[j]);
+                    store_chunk<R, LD_VEC, true>(row_ptr(st.out, (uint32_t)point_row(p, st), st.row_bytes), ln.off,
+                                                 ln.act, ln.nsym, x[j]);
             }
         }
         const int nx = tile + 1;
-        dt.template run<LD_VEC, false>(x, rcv, st, ln, bits, rowtab, [&] {
+        dt.template run<LD_VEC, false, true>(x, rcv, st, ln, bits, rowtab, [&] {
             if (nx < t1) {
                 // this wave's reads of its tile rows have returned before the
                 // copies into them start

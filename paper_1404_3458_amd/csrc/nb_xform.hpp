@@ -359,8 +359,9 @@ __device__ __forceinline__ void dec_weigh(uint32_t *x, bool rcv, const typename 
 
 // Decode step 6 (eq. F(j)) for one point: erased stored rows get
 // Phi^d[p] / Pi'(omega_p); tabf(p) yields the point's perm table.  UNI:
-// the point is the same for the whole wave (else per lane).
-template <int R, int LD, bool UNI = true, class TABF>
+// the point is the same for the whole wave (else per lane).  NT: stored
+// non-temporally (see store_chunk).
+template <int R, int LD, bool UNI = true, bool NT = false, class TABF>
 __device__ __forceinline__ void dec_store(const uint32_t *v, int p_, const DevStripe &st, const Lane &ln,
                                           const uint32_t *__restrict__ bits, const TABF &tabf)
 {
@@ -370,7 +371,7 @@ __device__ __forceinline__ void dec_store(const uint32_t *v, int p_, const DevSt
         uint32_t o[Traits<R>::NW];
         zero_vec<R>(o);
         Ops<R>::mac(o, v, tabf(p));
-        store_chunk<R, LD>(row_ptr(st.out, (uint32_t)t, st.row_bytes), ln.off, ln.act, ln.nsym, o);
+        store_chunk<R, LD, NT>(row_ptr(st.out, (uint32_t)t, st.row_bytes), ln.off, ln.act, ln.nsym, o);
     }
 }
 
