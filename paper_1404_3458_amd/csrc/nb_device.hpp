@@ -508,8 +508,11 @@ __device__ __forceinline__ void pipelined(const F &fetch, const W &work)
 }
 
 // Load this lane's chunk (byte offset `off` in the row) into byte-sliced
-// registers; inactive lanes and symbols >= nsym read zero.
-template <int R, int LD>
+// registers; inactive lanes and symbols >= nsym read zero.  NT: a streamed
+// input the launch reads once; a full GF(2^16) chunk is then read
+// non-temporally, so that it does not push the tables the launch keeps
+// re-reading out of L2.
+template <int R, int LD, bool NT = false>
 __device__ __forceinline__ void load_chunk(const uint8_t *row_, uint32_t off, bool act, int nsym, uint32_t *v)
 {
     const gu8 *row = (const gu8 *)row_ + off;
@@ -519,11 +522,11 @@ __device__ __forceinline__ void load_chunk(const uint8_t *row_, uint32_t off, bo
         uint32_t w0 = 0, w1 = 0;
         if (act) {
             if (LD == LD_VEC) {
-                const uint64_t t = *(const gu64 *)row;
+                const uint64_t t = NT ? __builtin_nontemporal_load((const gu64 *)row) : *(const gu64 *)row;
                 w0 = (uint32_t)t;
                 w1 = (uint32_t)(t >> 32);
             } else if (nsym == 4) {
-                const uint64_t t = *(const gu64_a2 *)row;
+                const uint64_t t = NT ? __builtin_nontemporal_load((const gu64_a2 *)row) : *(const gu64_a2 *)row;
                 w0 = (uint32_t)t;
                 w1 = (uint32_t)(t >> 32);
             } else {
@@ -552,9 +555,9 @@ __device__ __forceinline__ void load_chunk(const uint8_t *row_, uint32_t off, bo
         v[0] = w;
     }
 }
-// NT: a streamed output that nothing in the launch reads again; with 8-byte
-// alignment it is stored non-temporally, so that it does not push the
-// tables the launch keeps re-reading out of L2.
+// NT: a streamed output that nothing in the launch reads again; a full
+// GF(2^16) chunk is then stored non-temporally, so that it does not push
+// the tables the launch keeps re-reading out of L2.
 template <int R, int LD, bool NT = false>
 __device__ __forceinline__ void store_chunk(uint8_t *row_, uint32_t off, bool act, int nsym, const uint32_t *v)
 {
@@ -571,7 +574,11 @@ __device__ __forceinline__ void store_chunk(uint8_t *row_, uint32_t off, bool ac
             else
                 *(gu64 *)row = t;
         } else if (nsym == 4) {
-            *(gu64_a2 *)row = (uint64_t)w0 | ((uint64_t)w1 << 32);
+            const uint64_t t = (uint64_t)w0 | ((uint64_t)w1 << 32);
+            if (NT)
+                __builtin_nontemporal_store(t, (gu64_a2 *)row);
+            else
+                *(gu64_a2 *)row = t;
         } else {
             gu16 *r16 = (gu16 *)row;
             r16[0] = (uint16_t)w0;

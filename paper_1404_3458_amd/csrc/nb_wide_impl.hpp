@@ -52,6 +52,9 @@
 //            are not written
 //     W_PFM  the same, each output row first multiplied symbol by symbol by
 //            the same row of src2 (the product of Sec. 6.1)
+// Every pass reads and writes its rows once, non-temporally: the rows
+// streaming through an XCD's L2 would otherwise evict the factor and
+// locator tables each workgroup re-reads.
 #pragma once
 #include "nb_xform.hpp"
 
@@ -205,9 +208,9 @@ __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y
         uint32_t a[H][NW];
 #pragma unroll
         for (int j = 0; j < H; j++) {
-            load_chunk<R, LD>(wrow(ws.src, grow(j), rb), ln.off, ln.act, ln.nsym, x[j]);
+            load_chunk<R, LD, true>(wrow(ws.src, grow(j), rb), ln.off, ln.act, ln.nsym, x[j]);
             if (KIND == W_DL)
-                load_chunk<R, LD>(wrow(ws.src2, grow(j), rb), ln.off, ln.act, ln.nsym, a[j]);
+                load_chunk<R, LD, true>(wrow(ws.src2, grow(j), rb), ln.off, ln.act, ln.nsym, a[j]);
         }
         stage_tables();
         uint32_t (*d)[NW] = KIND == W_DH ? x : a;
@@ -241,7 +244,7 @@ __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y
         if (KIND == W_DH) {
 #pragma unroll
             for (int j = 0; j < H; j++)
-                store_chunk<R, LD>(wrow(ws.dst, WT::uni(grow(j)), rb), ln.off, ln.act, ln.nsym, x[j]);
+                store_chunk<R, LD, true>(wrow(ws.dst, WT::uni(grow(j)), rb), ln.off, ln.act, ln.nsym, x[j]);
         } else {
             pipelined<Tab, H>([&](int j) { return WT::row(rowtab, vrt, j, grow(j)); },
                               [&](int j, const Tab &t) {
@@ -257,7 +260,7 @@ __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y
         if (KIND == W_DH) {
 #pragma unroll
             for (int j = 0; j < 16; j++)
-                load_chunk<R, LD>(wrow(ws.src, grow(16 * g + j), rb), ln.off, ln.act, ln.nsym, x[j]);
+                load_chunk<R, LD, true>(wrow(ws.src, grow(16 * g + j), rb), ln.off, ln.act, ln.nsym, x[j]);
             stage_tables();
             reg_levels<R, 4, true, SH_ZERO, false>(x, (uint32_t)(16 * g), 0, tw);
             if constexpr (HALF) {
@@ -295,8 +298,8 @@ __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y
                 const int r0 = wave * GPW + u;
 #pragma unroll
                 for (int j = 0; j < NR2; j++) {
-                    load_chunk<R, LD>(wrow(ws.src, grow(r0 + 16 * j), rb), ln.off, ln.act, ln.nsym, y[u][j]);
-                    load_chunk<R, LD>(wrow(ws.src2, grow(r0 + 16 * j), rb), ln.off, ln.act, ln.nsym, a[u][j]);
+                    load_chunk<R, LD, true>(wrow(ws.src, grow(r0 + 16 * j), rb), ln.off, ln.act, ln.nsym, y[u][j]);
+                    load_chunk<R, LD, true>(wrow(ws.src2, grow(r0 + 16 * j), rb), ln.off, ln.act, ln.nsym, a[u][j]);
                 }
             }
             stage_tables();
@@ -426,7 +429,7 @@ __device__ __forceinline__ void split_decode_pass(uint32_t (*x)[2], uint32_t (*y
         if (KIND == W_DH) {
 #pragma unroll
             for (int j = 0; j < 16; j++)
-                store_chunk<R, LD>(wrow(ws.dst, WT::uni(grow(16 * g + j)), rb), ln.off, ln.act, ln.nsym, x[j]);
+                store_chunk<R, LD, true>(wrow(ws.dst, WT::uni(grow(16 * g + j)), rb), ln.off, ln.act, ln.nsym, x[j]);
         } else {
             pipelined<Tab, 16>([&](int j) { return WT::row(rowtab, vrt, 16 * g + j, grow(16 * g + j)); },
                                [&](int j, const Tab &t) {
@@ -624,12 +627,12 @@ void k_wide(
             for (int u = 0; u < GPW; u++)
 #pragma unroll
                 for (int j = 0; j < NR2; j++)
-                    store_chunk<R, LD>(wrow(d, WT::uni(grow(vw * GPW + u + 16 * j)), rb), ln.off, ln.act, ln.nsym,
+                    store_chunk<R, LD, true>(wrow(d, WT::uni(grow(vw * GPW + u + 16 * j)), rb), ln.off, ln.act, ln.nsym,
                                        y[u][j]);
         } else {
 #pragma unroll
             for (int j = 0; j < NX; j++)
-                store_chunk<R, LD>(wrow(d, WT::uni(grow(j)), rb), ln.off, ln.act, ln.nsym, x[j]);
+                store_chunk<R, LD, true>(wrow(d, WT::uni(grow(j)), rb), ln.off, ln.act, ln.nsym, x[j]);
         }
     };
 
@@ -648,7 +651,7 @@ void k_wide(
             if (KIND == W_D1)
                 rcv[j] = dec_fetch<R, LD>(x[j], (int)p, st, ln, bits);
             else
-                load_chunk<R, LD>(wrow(ws.src, p, rb), ln.off, ln.act && (int)p < ws.src_rows, ln.nsym, x[j]);
+                load_chunk<R, LD, true>(wrow(ws.src, p, rb), ln.off, ln.act && (int)p < ws.src_rows, ln.nsym, x[j]);
         }
     } else {
         if constexpr (TILED) {
@@ -657,7 +660,7 @@ void k_wide(
 #pragma unroll
                 for (int j = 0; j < NR2; j++) {
                     const uint32_t p = grow(vw * GPW + u + 16 * j);
-                    load_chunk<R, LD>(wrow(ws.src, p, rb), ln.off, ln.act && (int)p < ws.src_rows, ln.nsym, y[u][j]);
+                    load_chunk<R, LD, true>(wrow(ws.src, p, rb), ln.off, ln.act && (int)p < ws.src_rows, ln.nsym, y[u][j]);
                 }
         }
     }
@@ -674,7 +677,7 @@ void k_wide(
             uint32_t z[NC][NW];
 #pragma unroll
             for (int j = 0; j < NC; j++)
-                load_chunk<R, LD>(wrow(ws.src2, grow(c + j), rb), ln.off, ln.act, ln.nsym, z[j]);
+                load_chunk<R, LD, true>(wrow(ws.src2, grow(c + j), rb), ln.off, ln.act, ln.nsym, z[j]);
 #pragma unroll
             for (int j = 0; j < NC; j++)
 #pragma unroll
@@ -686,14 +689,14 @@ void k_wide(
             if (KIND == W_DPM) {
 #pragma unroll
                 for (int j = 0; j < NC; j++)
-                    store_chunk<R, LD>(wrow(ws.dst, WT::uni(grow(c + j)), rb), ln.off, ln.act, ln.nsym, z[j]);
+                    store_chunk<R, LD, true>(wrow(ws.dst, WT::uni(grow(c + j)), rb), ln.off, ln.act, ln.nsym, z[j]);
             } else {
                 pipelined<Tab, NC>([&](int j) { return WT::row(p_Binv, vB, c + j, grow(c + j)); },
                                    [&](int j, const Tab &t) {
                                        const uint32_t p = grow(c + j);
                                        if (p)
                                            scale<R>(z[j], t);
-                                       store_chunk<R, LD>(wrow(ws.dst, WT::uni(p), rb), ln.off, ln.act, ln.nsym, z[j]);
+                                       store_chunk<R, LD, true>(wrow(ws.dst, WT::uni(p), rb), ln.off, ln.act, ln.nsym, z[j]);
                                    });
             }
         }
@@ -705,7 +708,7 @@ void k_wide(
         uint32_t z[NX][NW];
 #pragma unroll
         for (int j = 0; j < NX; j++)
-            load_chunk<R, LD>(wrow(ws.src2, grow(xrow(j)), rb), ln.off, ln.act, ln.nsym, z[j]);
+            load_chunk<R, LD, true>(wrow(ws.src2, grow(xrow(j)), rb), ln.off, ln.act, ln.nsym, z[j]);
 #pragma unroll
         for (int j = 0; j < NX; j++)
 #pragma unroll
@@ -736,14 +739,14 @@ void k_wide(
         if (KIND == W_DPM) {
 #pragma unroll
             for (int j = 0; j < NX; j++)
-                store_chunk<R, LD>(wrow(ws.dst, WT::uni(grow(xrow(j))), rb), ln.off, ln.act, ln.nsym, z[j]);
+                store_chunk<R, LD, true>(wrow(ws.dst, WT::uni(grow(xrow(j))), rb), ln.off, ln.act, ln.nsym, z[j]);
         } else {
             pipelined<Tab, NX>([&](int j) { return WT::row(p_Binv, vB, xrow(j), grow(xrow(j))); },
                                [&](int j, const Tab &t) {
                                    const uint32_t p = grow(xrow(j));
                                    if (p)
                                        scale<R>(z[j], t);
-                                   store_chunk<R, LD>(wrow(ws.dst, WT::uni(p), rb), ln.off, ln.act, ln.nsym, z[j]);
+                                   store_chunk<R, LD, true>(wrow(ws.dst, WT::uni(p), rb), ln.off, ln.act, ln.nsym, z[j]);
                                });
         }
         return;
@@ -807,7 +810,7 @@ void k_wide(
                                     z[w] ^= v[w];
                             }
                         }
-                        store_chunk<R, LD>(wrow(ws.dst2, WT::uni(grow(r0 + 16 * j)), rb), ln.off, ln.act, ln.nsym,
+                        store_chunk<R, LD, true>(wrow(ws.dst2, WT::uni(grow(r0 + 16 * j)), rb), ln.off, ln.act, ln.nsym,
                                            z);
                     }
                 }
@@ -828,7 +831,7 @@ void k_wide(
 #pragma unroll
                             for (int w = 0; w < NW; w++)
                                 z[w] ^= x[j + (1 << lv)][w];
-                    store_chunk<R, LD>(wrow(ws.dst2, WT::uni(grow(j)), rb), ln.off, ln.act, ln.nsym, z);
+                    store_chunk<R, LD, true>(wrow(ws.dst2, WT::uni(grow(j)), rb), ln.off, ln.act, ln.nsym, z);
                 }
             }
             return;
@@ -859,10 +862,10 @@ void k_wide(
             if ((int)p < ws.dst_rows) {
                 if (KIND == W_PFM) {                 // times row p of src2, symbol by symbol
                     uint32_t m[NW];
-                    load_chunk<R, LD>(wrow(ws.src2, WT::uni(p), rb), ln.off, ln.act, ln.nsym, m);
+                    load_chunk<R, LD, true>(wrow(ws.src2, WT::uni(p), rb), ln.off, ln.act, ln.nsym, m);
                     mul_symbols16<4>(x[j], m);
                 }
-                store_chunk<R, LD>(wrow(ws.dst, WT::uni(p), rb), ln.off, ln.act, ln.nsym, x[j]);
+                store_chunk<R, LD, true>(wrow(ws.dst, WT::uni(p), rb), ln.off, ln.act, ln.nsym, x[j]);
             }
         }
     }
