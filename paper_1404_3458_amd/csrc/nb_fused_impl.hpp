@@ -694,8 +694,8 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
     // 64 + l (half of chunk 32 + l / 2); a chunk past the stripe's columns is
     // not copied.
     ConstStripe *const cst = const_stripes(a.stripes);
-    auto issue = [&](int t, int g, int lane) {
-        const DevStripe st = cst[find_stripe(cst, a.nstripes, t)];
+    auto issue = [&](int t, int si, int g, int lane) {
+        const DevStripe st = cst[si];
         const Lane la = lane_of<R, LD_VEC>(t - st.tile0, lane >> 1, st.col0, st.ncols);
         const Lane lb = lane_of<R, LD_VEC>(t - st.tile0, 32 + (lane >> 1), st.col0, st.ncols);
         const uint32_t half = 4u * (uint32_t)(lane & 1);
@@ -717,23 +717,22 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
             }
         }
     };
+    // stripes are in tile order: the stripe of the next tile is this one or
+    // a later one (past any without tiles), so one search at the start
+    int s = t0 < t1 ? find_stripe(cst, a.nstripes, t0) : 0;
     if (t0 < t1)
-        issue(t0, __builtin_amdgcn_readfirstlane(tid >> 6), tid & 63);
+        issue(t0, s, __builtin_amdgcn_readfirstlane(tid >> 6), tid & 63);
     stage_levels<R, L>(vX, p_tw, 0u, tid, NT);
     stage_rows<R>(vB, p_B, H, tid, NT);
     stage_rows<R>(vBi, p_Binv, H, tid, NT);
     int cur = -1;                                // stripe whose locator tables are staged
     for (int tile = t0; tile < t1; tile++) {
-        // the table pointers pass through an empty asm per tile, so the
-        // compiler reloads the tables' scalar words inside the loop instead
-        // of keeping a hundred of them live across it
         // wave and lane pass through an empty asm per tile, so that the
         // compiler recomputes the hundred addresses and table indices derived
         // from them inside the loop instead of keeping them live across it
         int g = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
         asm volatile("" : "+s"(g), "+v"(lane));
         const DecTile<R, L> dt = {lds, p_tw, p_B, p_Binv, g, lane};
-        const int s = find_stripe(cst, a.nstripes, tile);
         const DevStripe st = cst[s];
         const Lane ln = lane_of<R, LD_VEC>(tile - st.tile0, lane, st.col0, st.ncols);
         const uint32_t *__restrict__ bits = p_bits + st.bits_off;
@@ -772,16 +771,20 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(4
             }
         }
         const int nx = tile + 1;
+        int s2 = s;
+        while (s2 + 1 < a.nstripes && cst[s2 + 1].tile0 <= nx)
+            s2++;
         dt.template run<LD_VEC, false, true>(x, rcv, st, ln, bits, rowtab, [&] {
             if (nx < t1) {
                 // this wave's reads of its tile rows have returned before the
                 // copies into them start
                 __builtin_amdgcn_s_waitcnt(0xC07F); // lgkmcnt(0)
                 asm volatile("" ::: "memory");
-                issue(nx, g, lane);
+                issue(nx, s2, g, lane);
                 asm volatile("" ::: "memory");
             }
         });
+        s = s2;
     }
 }
 
