@@ -67,7 +67,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == M_EN
 {
     constexpr int NW = Traits<R>::NW, NR = 1 << L;
     const int tile = blockIdx.x;
-    const int s = find_stripe(a.stripes, a.nstripes, tile);
+    const int s = find_stripe_guess(a.stripes, a.nstripes, tile, (int)gridDim.x);
     const DevStripe st = a.stripes[s];
     const Lane ln = lane_of<R, LD>(tile - st.tile0, (int)threadIdx.x, st.col0, st.ncols);
     const DoneStamp done = {a.ts};
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(64 << (L - 4)) __attribute__((amdgpu_waves_per_eu(
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int tile = blockIdx.x;
-    const int s = find_stripe(a.stripes, a.nstripes, tile);
+    const int s = find_stripe_guess(a.stripes, a.nstripes, tile, (int)gridDim.x);
     const DevStripe st = a.stripes[s];
     const Lane ln = lane_of<R, LD>(tile - st.tile0, lane, st.col0, st.ncols);
     const DoneStamp done = {a.ts};

@@ -42,6 +42,20 @@ __device__ __forceinline__ int find_stripe(P st, int n, int tile)
     return lo;
 }
 
+// The same for a launch of one workgroup per tile over ntiles tiles: the
+// stripe at the tile's share of the stripe count is tried first (it is
+// the right one when the stripes have equal tile counts, with both loads
+// in flight at once), the search only when it is not.
+template <class P>
+__device__ __forceinline__ int find_stripe_guess(P st, int n, int tile, int ntiles)
+{
+    const int g = (int)((int64_t)tile * n / ntiles);
+    const int lo = st[g].tile0, hi = g + 1 < n ? st[g + 1].tile0 : ntiles;
+    if (lo <= tile && tile < hi)
+        return g;
+    return find_stripe(st, n, tile);
+}
+
 // How the shift l of a transform is known to the kernel:
 //   SH_ZERO     l = 0: the factor of block c = 0 is zero at every level;
 //   SH_ALIGNED  h divides l and l != 0: no factor is zero, and bit i of l is
