@@ -890,7 +890,9 @@ def main():
     copy_rate = copy_gbps()
     # GF(2^16) decodes of 128 or 256 points over 8-byte-aligned rows run the
     # persistent decode kernel when there are more tiles than workgroup slots
-    persist = dom == "decode" and r == 16 and lg in (7, 8) and S % 8 == 0 and ns * -(-cols // 256) > 512
+    # (one per CU for 256 points, two for 128, on 256 CUs)
+    slots = 256 if lg == 8 else 512
+    persist = dom == "decode" and r == 16 and lg in (7, 8) and S % 8 == 0 and ns * -(-cols // 256) > slots
     kname = "k_dec_persist" if persist else ("k_tiled" if 4 < lg <= 8 else ("k_small" if lg <= 4 else "multi-pass"))
     roof = hbm_roofline("%s launch (%s, L=%d)" % (dom, kname, lg),
                         algo_bytes, dom_ms * 1e-3, traffic_from_profiles(args.config), copy_rate,
