@@ -314,29 +314,34 @@ def test_decode_many_tiles(request, r, n, k, ns, ncols, inplace):
             assert torch.equal(cw[s], rx[s]), s          # input untouched
 
 
-def test_decode_persistent_mixed_stripes(codec16):
-    # one 256-point decode launch with more tiles than workgroup slots over
-    # stripes of different shapes, widths (whole and ragged last tiles) and
-    # erasure counts, in place and out of place in the same batch: the
-    # workgroups' tile ranges cross stripes of every kind
-    shapes = [(256, 128), (240, 120), (192, 96), (200, 128), (160, 64)]
-    widths = [8192, 4100, 6000, 260]
+@pytest.mark.parametrize("points", [256, 128])
+def test_decode_persistent_mixed_stripes(codec16, points):
+    # one decode launch of 2^8 or 2^7 points with more tiles than workgroup
+    # slots over stripes of different shapes, widths (whole and ragged last
+    # tiles) and erasure counts, in place and out of place in the same
+    # batch: the workgroups' tile ranges cross stripes of every kind
+    if points == 256:
+        shapes = [(256, 128), (240, 120), (192, 96), (200, 128), (160, 64)]
+        widths = [8192, 4100, 6000, 260]
+    else:
+        shapes = [(128, 64), (96, 48), (80, 40), (120, 64), (72, 16)]
+        widths = [16384, 8196, 12000, 516]
     specs = [(shapes[i % 5], widths[i % 4]) for i in range(30)]
     cws, masks, refs, outs = [], [], [], []
     for i, ((n, k), ncols) in enumerate(specs):
         cw = torch.empty((n, 2 * ncols), dtype=torch.uint8, device="cuda")
-        synth.fill_random_torch(synth.key(90, i), cw[:k])
+        synth.fill_random_torch(synth.key(90, points, i), cw[:k])
         cws.append(cw)
     codec16.encode_batch([(n, k, cws[i][:k], cws[i][k:]) for i, ((n, k), _) in enumerate(specs)])
     torch.cuda.synchronize()
     for i in (0, 1, 7, 29):
         (n, k), ncols = specs[i]
-        cols = sorted({0, ncols - 1} | set(int(c) for c in synth.uniform_int(synth.key(91, i), 6, 0, ncols - 1)))
+        cols = sorted({0, ncols - 1} | set(int(c) for c in synth.uniform_int(synth.key(91, points, i), 6, 0, ncols - 1)))
         host = to_host(cws[i]).reshape(n, ncols, 2)[:, cols, :].reshape(n, 2 * len(cols))
         assert (oracle.encode(16, n, k, np.ascontiguousarray(host[:k])) == host[k:]).all(), specs[i]
     for i, ((n, k), ncols) in enumerate(specs):
         e = [n - k, (3 * (n - k)) // 4, n - k - 3][i % 3]
-        m = synth.erasure_mask(synth.key(92, i), n, e)
+        m = synth.erasure_mask(synth.key(92, points, i), n, e)
         refs.append(cws[i].clone())
         cws[i][torch.from_numpy(m).bool().cuda()] = 0
         masks.append(m)
